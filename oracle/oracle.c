@@ -1,0 +1,533 @@
+/*
+ * Picasso palette colouring -- plain CPU oracle.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct
+ * single-threaded reference that the HIP path is checked against.  It shares
+ * no code, header, table or constant with the GPU library; only the tests,
+ * the smoke check and the benchmark's CPU-baseline leg may load it.
+ *
+ * Every function follows a passage of the paper (Picasso: memory-efficient
+ * graph coloring using palettes, arXiv 2401.06713) and cites it by section,
+ * equation or algorithm.  Where the paper is silent the reading used here is
+ * stated beside the code; the same readings are listed in the design notes.
+ *
+ * Pinning status (what fixes each function other than this file):
+ *   relation        -- Kronecker products of the Pauli matrices, per-qubit
+ *                      matrix commutators, the paper's 3-bit code, and the
+ *                      Jordan-Wigner / {I,Z} special cases (tests).
+ *   params          -- the list/palette sizes printed for the paper-scale
+ *                      configurations (2 ln 2000 -> 16, 0.125*2000 -> 250).
+ *   philox, sampler -- Philox4x32-10 values are parity unpinned (no published
+ *                      known-answer vectors are available here); the sampler
+ *                      is pinned by structure (T distinct sorted values in
+ *                      range, T = P gives the whole palette) and by statistics
+ *                      (marginals T/P, pair-share probability, bucket pairs).
+ *   conflict edges  -- brute force on tiny inputs, T = P special case, the
+ *                      closed-form expectation of |E_c|.
+ *   greedy colouring-- validity, list respect, progress, textbook greedy when
+ *                      T = P, complete and empty relation graphs, chromatic
+ *                      lower bound by subset DP for n <= 12.  Exact colour
+ *                      values beyond these are parity unpinned by the paper.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_REL_ANTICOMMUTE 0
+#define ORC_REL_QWC 1
+
+/* ------------------------------------------------------------------------ */
+/* Pauli strings and the pairwise relation (Sec. IV-A, Eq. 4-5; Sec. III)     */
+/* ------------------------------------------------------------------------ */
+
+/* Qubit k of a string held as two bit-planes: (x,z) = (0,0) I, (1,0) X,
+ * (1,1) Y, (0,1) Z.  Qubit k is bit k%64 of word k/64. */
+static char pauli_char(const uint64_t *x, const uint64_t *z, int k)
+{
+    int xb = (int)((x[k / 64] >> (k % 64)) & 1u);
+    int zb = (int)((z[k / 64] >> (k % 64)) & 1u);
+    if (xb && zb) return 'Y';
+    if (xb) return 'X';
+    if (zb) return 'Z';
+    return 'I';
+}
+
+/* Decode n strings of q qubits into characters, n*q bytes, row-major. */
+void orc_decode(int64_t n, int32_t q, const uint64_t *x, const uint64_t *z, char *out)
+{
+    int W = (q + 63) / 64;
+    for (int64_t i = 0; i < n; i++)
+        for (int k = 0; k < q; k++)
+            out[i * q + k] = pauli_char(x + i * W, z + i * W, k);
+}
+
+/* Two single-qubit Pauli matrices anticommute exactly when both are
+ * non-identity and they differ (Eq. 5); every other pair commutes. */
+int orc_qubit_anticommutes(char a, char b)
+{
+    return a != 'I' && b != 'I' && a != b;
+}
+
+/* Relation on two decoded strings.
+ * ANTICOMMUTE: the strings anticommute iff the number of anticommuting
+ *              positions is odd (Sec. IV-A, the parity rule after Eq. 5).
+ * QWC:         "not qubit-wise commuting": some position anticommutes
+ *              (qubit-wise commutativity, Sec. III).
+ * Returns 1 when the pair fails the grouping relation (a graph edge). */
+int orc_relation_chars(int32_t q, const char *a, const char *b, int32_t rel)
+{
+    int count = 0;
+    for (int k = 0; k < q; k++)
+        if (orc_qubit_anticommutes(a[k], b[k])) count++;
+    if (rel == ORC_REL_ANTICOMMUTE) return count % 2 == 1;
+    return count > 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Counter-based random numbers                                              */
+/* ------------------------------------------------------------------------ */
+
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the
+ * two-multiplier Feistel-like bijection on a 4x32-bit counter, the 2x32-bit
+ * key bumped by the Weyl constants between rounds. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; round++) {
+        if (round > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        uint64_t p0 = (uint64_t)M0 * c0;
+        uint64_t p1 = (uint64_t)M1 * c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+#define ORC_TAG_LIST 0x4C495354u /* colour-list draws */
+#define ORC_TAG_PRIO 0x5052494Fu /* vertex priorities */
+
+/* 64-bit draw keyed by (seed; vertex, slot, iteration, tag): counter
+ * (v, s, ell, tag), key (seed low, seed high); the value is word1:word0. */
+uint64_t orc_hash64(uint64_t seed, uint32_t v, uint32_t s, uint32_t ell, uint32_t tag)
+{
+    uint32_t ctr[4] = {v, s, ell, tag};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    orc_philox4x32_10(ctr, key, out);
+    return ((uint64_t)out[1] << 32) | out[0];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Per-iteration palette and list size (Alg. 1 "estimate" step; Table I;      */
+/* Sec. VII: P is a percentage of |V|, L = alpha log|V|, same every iteration)*/
+/* Readings: natural log, ceiling, P >= 1, 1 <= T <= P.                       */
+/* ------------------------------------------------------------------------ */
+void orc_params(int64_t m, double frac, double alpha, int32_t fixed_T, int64_t *P_out, int32_t *T_out)
+{
+    double pd = ceil(frac * (double)m);
+    int64_t P = (int64_t)pd;
+    if (P < 1) P = 1;
+    int64_t T;
+    if (fixed_T > 0) {
+        T = fixed_T;
+    } else {
+        double td = ceil(alpha * log((double)m));
+        T = (int64_t)td;
+    }
+    if (T < 1) T = 1;
+    if (T > P) T = P;
+    *P_out = P;
+    *T_out = (int32_t)T;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Random colour lists (Alg. 1 assign_rand_list_colors; Sec. IV: each vertex  */
+/* gets T colours chosen uniformly at random from the palette).               */
+/* Reading: a uniform T-subset drawn with Floyd's algorithm (Bentley & Floyd, */
+/* CACM 1987), one keyed draw per step, then sorted ascending.                */
+/* ------------------------------------------------------------------------ */
+static uint64_t mul_high64(uint64_t a, uint64_t b)
+{
+    unsigned __int128 p = (unsigned __int128)a * b;
+    return (uint64_t)(p >> 64);
+}
+
+void orc_sample_list(uint64_t seed, uint32_t ell, uint32_t v, int64_t P, int32_t T, uint32_t *out)
+{
+    int cnt = 0;
+    for (int s = 0; s < T; s++) {
+        uint64_t j = (uint64_t)(P - T + s);
+        uint64_t r = orc_hash64(seed, v, (uint32_t)s, ell, ORC_TAG_LIST);
+        uint64_t t = mul_high64(r, j + 1); /* uniform-ish in [0, j] */
+        int present = 0;
+        for (int i = 0; i < cnt; i++)
+            if (out[i] == (uint32_t)t) present = 1;
+        out[cnt++] = present ? (uint32_t)j : (uint32_t)t;
+    }
+    /* insertion sort, ascending */
+    for (int i = 1; i < cnt; i++) {
+        uint32_t key = out[i];
+        int k = i - 1;
+        while (k >= 0 && out[k] > key) {
+            out[k + 1] = out[k];
+            k--;
+        }
+        out[k + 1] = key;
+    }
+}
+
+/* Vertex priority for the random static order (Sec. IV-B, static schemes,
+ * "Random ordering").  Reading: u precedes v iff (prio(u), u) < (prio(v), v). */
+uint64_t orc_priority(uint64_t seed, uint32_t ell, uint32_t v)
+{
+    return orc_hash64(seed, v, 0, ell, ORC_TAG_PRIO);
+}
+
+/* Lists of the vertices ids[0..m) (original ids), row-major m x T. */
+void orc_sample_lists(uint64_t seed, uint32_t ell, int64_t m, const int32_t *ids, int64_t P, int32_t T,
+                      uint32_t *lists)
+{
+    for (int64_t i = 0; i < m; i++)
+        orc_sample_list(seed, ell, (uint32_t)ids[i], P, T, lists + i * T);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Conflict graph (Alg. 1 construct_conflict_graph; Sec. IV-A: an edge of the */
+/* relation graph is conflicting when the two endpoints' lists intersect).    */
+/* ------------------------------------------------------------------------ */
+
+/* 1 if two sorted lists share a colour. */
+static int lists_intersect(const uint32_t *a, const uint32_t *b, int T)
+{
+    int i = 0, j = 0;
+    while (i < T && j < T) {
+        if (a[i] == b[j]) return 1;
+        if (a[i] < b[j]) i++;
+        else j++;
+    }
+    return 0;
+}
+
+/* Smallest colour two sorted lists share, or UINT32_MAX if none. */
+static uint32_t min_shared(const uint32_t *a, const uint32_t *b, int T)
+{
+    int i = 0, j = 0;
+    while (i < T && j < T) {
+        if (a[i] == b[j]) return a[i];
+        if (a[i] < b[j]) i++;
+        else j++;
+    }
+    return UINT32_MAX;
+}
+
+/* Growable edge array of (u, v) local-index pairs. */
+typedef struct {
+    int32_t *uv;
+    int64_t count, cap;
+} edge_buf;
+
+static int edge_push(edge_buf *e, int32_t u, int32_t v)
+{
+    if (e->count == e->cap) {
+        int64_t nc = e->cap ? e->cap * 2 : 1024;
+        int32_t *p = (int32_t *)realloc(e->uv, (size_t)nc * 2 * sizeof(int32_t));
+        if (!p) return -1;
+        e->uv = p;
+        e->cap = nc;
+    }
+    e->uv[2 * e->count] = u;
+    e->uv[2 * e->count + 1] = v;
+    e->count++;
+    return 0;
+}
+
+static int cmp_edge(const void *pa, const void *pb)
+{
+    const int32_t *a = (const int32_t *)pa, *b = (const int32_t *)pb;
+    if (a[0] != b[0]) return a[0] < b[0] ? -1 : 1;
+    if (a[1] != b[1]) return a[1] < b[1] ? -1 : 1;
+    return 0;
+}
+
+/* The definition written out: every pair a < b of the m vertices is an edge
+ * iff the relation holds and their lists intersect.  `chars` holds the
+ * decoded strings of ALL n vertices; ids maps local index -> original id.
+ * Returns |E_c|; writes min(|E_c|, cap) pairs (a < b, lexicographic). */
+int64_t orc_conflict_edges_allpairs(int32_t q, int64_t m, const int32_t *ids, const char *chars,
+                                    const uint32_t *lists, int32_t T, int32_t rel, int32_t *out_uv,
+                                    int64_t cap)
+{
+    int64_t count = 0;
+    for (int64_t a = 0; a < m; a++)
+        for (int64_t b = a + 1; b < m; b++) {
+            if (!lists_intersect(lists + a * T, lists + b * T, T)) continue;
+            if (!orc_relation_chars(q, chars + (int64_t)ids[a] * q, chars + (int64_t)ids[b] * q, rel))
+                continue;
+            if (count < cap) {
+                out_uv[2 * count] = (int32_t)a;
+                out_uv[2 * count + 1] = (int32_t)b;
+            }
+            count++;
+        }
+    return count;
+}
+
+/* The same edge set enumerated colour by colour: the vertices holding colour
+ * c are the only candidates that conflict through c, and a pair sharing
+ * several colours is recorded once, at the smallest shared colour.  Only
+ * colours in [c_lo, c_hi) are visited (the whole palette by default), which
+ * lets a caller time a bounded slice.  Edges are returned sorted.
+ * *pair_tests receives sum over visited colours of C(|B_c|, 2). */
+static int64_t conflict_edges_by_colour(int32_t q, int64_t m, const int32_t *ids, const char *chars,
+                                        const uint32_t *lists, int32_t T, int64_t P, int32_t rel,
+                                        int64_t c_lo, int64_t c_hi, edge_buf *eb, int64_t *pair_tests)
+{
+    int64_t *start = (int64_t *)calloc((size_t)P + 1, sizeof(int64_t));
+    int32_t *members = (int32_t *)malloc((size_t)(m * T > 0 ? m * T : 1) * sizeof(int32_t));
+    int64_t *fill = (int64_t *)calloc((size_t)P, sizeof(int64_t));
+    if (!start || !members || !fill) {
+        free(start); free(members); free(fill);
+        return -1;
+    }
+    for (int64_t a = 0; a < m; a++)
+        for (int k = 0; k < T; k++) start[lists[a * T + k] + 1]++;
+    for (int64_t c = 0; c < P; c++) start[c + 1] += start[c];
+    for (int64_t a = 0; a < m; a++) /* ascending a: each bucket is sorted */
+        for (int k = 0; k < T; k++) {
+            uint32_t c = lists[a * T + k];
+            members[start[c] + fill[c]++] = (int32_t)a;
+        }
+    free(fill);
+    int64_t tests = 0;
+    if (c_lo < 0) c_lo = 0;
+    if (c_hi > P) c_hi = P;
+    for (int64_t c = c_lo; c < c_hi; c++) {
+        int64_t s = start[c], e = start[c + 1];
+        tests += (e - s) * (e - s - 1) / 2;
+        for (int64_t i = s; i < e; i++)
+            for (int64_t j = i + 1; j < e; j++) {
+                int32_t a = members[i], b = members[j];
+                if (!orc_relation_chars(q, chars + (int64_t)ids[a] * q, chars + (int64_t)ids[b] * q, rel))
+                    continue;
+                if (min_shared(lists + (int64_t)a * T, lists + (int64_t)b * T, T) != (uint32_t)c) continue;
+                if (edge_push(eb, a, b)) {
+                    free(start); free(members);
+                    return -1;
+                }
+            }
+    }
+    free(start);
+    free(members);
+    qsort(eb->uv, (size_t)eb->count, 2 * sizeof(int32_t), cmp_edge);
+    if (pair_tests) *pair_tests = tests;
+    return eb->count;
+}
+
+/* Exported wrapper: returns |E_c| over the colour slice, copies up to cap
+ * sorted pairs.  Returns -1 on allocation failure. */
+int64_t orc_conflict_edges_bucketed(int32_t q, int64_t m, const int32_t *ids, const char *chars,
+                                    const uint32_t *lists, int32_t T, int64_t P, int32_t rel,
+                                    int64_t c_lo, int64_t c_hi, int32_t *out_uv, int64_t cap,
+                                    int64_t *pair_tests)
+{
+    edge_buf eb = {0, 0, 0};
+    int64_t cnt = conflict_edges_by_colour(q, m, ids, chars, lists, T, P, rel, c_lo, c_hi, &eb, pair_tests);
+    if (cnt >= 0 && out_uv) {
+        int64_t k = cnt < cap ? cnt : cap;
+        memcpy(out_uv, eb.uv, (size_t)k * 2 * sizeof(int32_t));
+    }
+    free(eb.uv);
+    return cnt;
+}
+
+/* ------------------------------------------------------------------------ */
+/* List colouring of the conflict graph in a static random order (Sec. IV-B, */
+/* static order schemes: each vertex in turn takes the first colour of its    */
+/* list not already held by a neighbour; Alg. 1 also gives unconflicted       */
+/* vertices a colour of their list -- here the first one).                   */
+/* Vertices whose list is exhausted stay uncoloured (-1).                     */
+/* ------------------------------------------------------------------------ */
+static const uint64_t *g_sort_prio; /* qsort context (single-threaded) */
+
+static int cmp_order(const void *pa, const void *pb)
+{
+    int64_t a = *(const int64_t *)pa, b = *(const int64_t *)pb;
+    if (g_sort_prio[a] != g_sort_prio[b]) return g_sort_prio[a] < g_sort_prio[b] ? -1 : 1;
+    return a < b ? -1 : (a > b ? 1 : 0);
+}
+
+/* prio[m]: priorities; local index order equals original-id order, so the
+ * (prio, index) order is the (prio, id) order.  CSR (rowptr, adj) is the
+ * symmetric conflict graph.  col[m] receives palette colours or -1. */
+int32_t orc_greedy_list_color(int64_t m, const uint64_t *prio, const uint32_t *lists, int32_t T, int64_t P,
+                              const int64_t *rowptr, const int32_t *adj, int32_t *col)
+{
+    int64_t *order = (int64_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+    int64_t *rank = (int64_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+    int64_t *mark = (int64_t *)malloc((size_t)P * sizeof(int64_t));
+    if (!order || !rank || !mark) {
+        free(order); free(rank); free(mark);
+        return -1;
+    }
+    for (int64_t i = 0; i < m; i++) order[i] = i;
+    g_sort_prio = prio;
+    qsort(order, (size_t)m, sizeof(int64_t), cmp_order);
+    for (int64_t r = 0; r < m; r++) rank[order[r]] = r;
+    for (int64_t c = 0; c < P; c++) mark[c] = -1;
+    for (int64_t i = 0; i < m; i++) col[i] = -1;
+    for (int64_t r = 0; r < m; r++) {
+        int64_t v = order[r];
+        for (int64_t e = rowptr[v]; e < rowptr[v + 1]; e++) {
+            int64_t u = adj[e];
+            if (rank[u] < rank[v] && col[u] >= 0) mark[col[u]] = v; /* forbidden for v */
+        }
+        for (int k = 0; k < T; k++) {
+            uint32_t c = lists[v * T + k];
+            if (mark[c] != v) {
+                col[v] = (int32_t)c;
+                break;
+            }
+        }
+    }
+    free(order);
+    free(rank);
+    free(mark);
+    return 0;
+}
+
+/* Symmetric CSR from a sorted (a < b) edge list. */
+static int build_csr(int64_t m, const int32_t *uv, int64_t ne, int64_t **rowptr_out, int32_t **adj_out)
+{
+    int64_t *rowptr = (int64_t *)calloc((size_t)m + 1, sizeof(int64_t));
+    int32_t *adj = (int32_t *)malloc((size_t)(2 * ne > 0 ? 2 * ne : 1) * sizeof(int32_t));
+    int64_t *pos = (int64_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+    if (!rowptr || !adj || !pos) {
+        free(rowptr); free(adj); free(pos);
+        return -1;
+    }
+    for (int64_t e = 0; e < ne; e++) {
+        rowptr[uv[2 * e] + 1]++;
+        rowptr[uv[2 * e + 1] + 1]++;
+    }
+    for (int64_t i = 0; i < m; i++) rowptr[i + 1] += rowptr[i];
+    for (int64_t i = 0; i < m; i++) pos[i] = rowptr[i];
+    for (int64_t e = 0; e < ne; e++) {
+        int32_t a = uv[2 * e], b = uv[2 * e + 1];
+        adj[pos[a]++] = b;
+        adj[pos[b]++] = a;
+    }
+    free(pos);
+    *rowptr_out = rowptr;
+    *adj_out = adj;
+    return 0;
+}
+
+/* Exported: greedy on an edge list (for tests that supply their own graph). */
+int32_t orc_greedy_from_edges(int64_t m, const uint64_t *prio, const uint32_t *lists, int32_t T, int64_t P,
+                              const int32_t *uv, int64_t ne, int32_t *col)
+{
+    int64_t *rowptr;
+    int32_t *adj;
+    if (build_csr(m, uv, ne, &rowptr, &adj)) return -1;
+    int32_t rc = orc_greedy_list_color(m, prio, lists, T, P, rowptr, adj, col);
+    free(rowptr);
+    free(adj);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The iteration (Alg. 1): estimate (P, T), draw lists, build the conflict    */
+/* graph, colour it, and recurse on the uncoloured vertices with a fresh      */
+/* palette.  Reading of the garbled palette indices: iteration ell uses the  */
+/* half-open range [offset, offset + P_ell), offset = sum of earlier P.       */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t m, P, T, pair_tests, edges, colored, offset;
+} orc_iter_stat;
+
+/* Returns the number of distinct colours, or -1 on allocation failure.
+ * out_colors[n] receives global colour ids.  stats (may be NULL) receives
+ * up to max_stats per-iteration records; *n_iters the iteration count. */
+int64_t orc_color(int64_t n, int32_t q, const uint64_t *x, const uint64_t *z, uint64_t seed, double frac,
+                  double alpha, int32_t rel, int32_t fixed_T, int32_t *out_colors, orc_iter_stat *stats,
+                  int32_t max_stats, int32_t *n_iters)
+{
+    char *chars = (char *)malloc((size_t)(n * q > 0 ? n * q : 1));
+    int32_t *ids = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    if (!chars || !ids) {
+        free(chars); free(ids);
+        return -1;
+    }
+    orc_decode(n, q, x, z, chars);
+    for (int64_t i = 0; i < n; i++) {
+        ids[i] = (int32_t)i;
+        out_colors[i] = -1;
+    }
+    int64_t m = n, offset = 0, distinct = 0;
+    uint32_t ell = 1;
+    int32_t it = 0;
+    while (m > 0) {
+        int64_t P;
+        int32_t T;
+        orc_params(m, frac, alpha, fixed_T, &P, &T);
+        uint32_t *lists = (uint32_t *)malloc((size_t)(m * T) * sizeof(uint32_t));
+        uint64_t *prio = (uint64_t *)malloc((size_t)m * sizeof(uint64_t));
+        int32_t *col = (int32_t *)malloc((size_t)m * sizeof(int32_t));
+        char *used = (char *)calloc((size_t)P, 1);
+        if (!lists || !prio || !col || !used) {
+            free(lists); free(prio); free(col); free(used); free(chars); free(ids);
+            return -1;
+        }
+        orc_sample_lists(seed, ell, m, ids, P, T, lists);
+        for (int64_t i = 0; i < m; i++) prio[i] = orc_priority(seed, ell, (uint32_t)ids[i]);
+        edge_buf eb = {0, 0, 0};
+        int64_t tests = 0;
+        int64_t ne = conflict_edges_by_colour(q, m, ids, chars, lists, T, P, rel, 0, P, &eb, &tests);
+        if (ne < 0 || orc_greedy_from_edges(m, prio, lists, T, P, eb.uv, ne, col)) {
+            free(eb.uv); free(lists); free(prio); free(col); free(used); free(chars); free(ids);
+            return -1;
+        }
+        free(eb.uv);
+        int64_t next = 0, colored = 0;
+        for (int64_t i = 0; i < m; i++) {
+            if (col[i] >= 0) {
+                out_colors[ids[i]] = (int32_t)(offset + col[i]);
+                if (!used[col[i]]) {
+                    used[col[i]] = 1;
+                    distinct++;
+                }
+                colored++;
+            } else {
+                ids[next++] = ids[i]; /* ascending order is kept */
+            }
+        }
+        if (stats && it < max_stats) {
+            orc_iter_stat s = {m, P, T, tests, ne, colored, offset};
+            stats[it] = s;
+        }
+        it++;
+        free(lists);
+        free(prio);
+        free(col);
+        free(used);
+        offset += P;
+        m = next;
+        ell++;
+    }
+    if (n_iters) *n_iters = it;
+    free(chars);
+    free(ids);
+    return distinct;
+}
