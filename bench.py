@@ -1,0 +1,176 @@
+"""Benchmark: one step = one full palette colouring (every iteration of
+Alg. 1: lists, buckets, pair count + fill, list colouring, compaction) of a
+synthetic Pauli-string workload, with the strings already resident in HBM.
+
+Prints ONE JSON line (rank 0).  `value` is pair tests per second of
+end-to-end step time; the line also carries conflict edges per second,
+end-to-end seconds, the colour count, the roofline of the dominant kernel
+and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pair-tests/s + end-to-end s and #colours, learned vs fixed params, 1 GPU"
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # INT32 lanes per clock x clock: 39.3 Tops/s
+MFMA_I8_PEAK_TOPS = 5000.0  # dense int8 MFMA, 5.0 POP/s
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(cfg, x, z, budget_s: float):
+    """The oracle's conflict-graph build on a slice of iteration 1's colour
+    buckets (single thread), scaled to pair tests per second."""
+    import numpy as np
+
+    import oracle
+
+    oracle.build(force=False)
+    ch = oracle.decode(x, z, cfg.q)
+    ids = np.arange(cfg.n, dtype=np.int32)
+    P, T = oracle.params(cfg.n, cfg.frac, cfg.alpha)
+    lists = oracle.sample_lists(0, 1, ids, P, T)
+    # calibrate on a small slice, then size the timed slice to the budget
+    probe = max(1, P // 200)
+    t = time.perf_counter()
+    _, _, tests = oracle.conflict_edges_bucketed(ch, ids, lists, P, cfg.relation, 0, probe, want_edges=False)
+    rate = tests / max(time.perf_counter() - t, 1e-6)
+    want = int(budget_s * rate)
+    per_colour = max(tests / probe, 1.0)
+    hi = int(min(P, max(probe, want / per_colour)))
+    t = time.perf_counter()
+    _, edges, tests = oracle.conflict_edges_bucketed(ch, ids, lists, P, cfg.relation, 0, hi, want_edges=False)
+    dt = time.perf_counter() - t
+    return {
+        "value": tests / dt,
+        "unit": "pair-tests/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{cfg.name}: iteration-1 conflict build over colour buckets [0,{hi}) of {P} "
+                  f"({tests} pair tests, {edges} edges, {dt:.1f} s, single-threaded C oracle)",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="C2", choices=["C1", "C2", "C4"])
+    ap.add_argument("--path", default="auto", choices=["auto", "valu", "mfma"])
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the method runs on a single device); --gpus {args.gpus} "
+              "is not supported", file=sys.stderr)
+        sys.exit(2)
+    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs as a single process", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2401_06713_amd as pk
+    from paper_2401_06713_amd import workloads as wl
+
+    cfg = {"C1": wl.C1, "C2": wl.C2, "C4": wl.C4}[args.config]
+    log(f"bench: generating {cfg.name}")
+    x, z = wl.make(cfg)
+    torch.cuda.set_device(0)
+    xd = torch.from_numpy(x.view(np.int64)).cuda()
+    zd = torch.from_numpy(z.view(np.int64)).cuda()
+    out = torch.empty(cfg.n, dtype=torch.int32, device="cuda")
+    h = pk.Picasso(xd, zd, cfg.q)
+    h.set_option(pk.OPT_PAIR_PATH, {"auto": 0, "valu": 1, "mfma": 2}[args.path])
+    h.set_option(pk.OPT_TIMING, 1)
+
+    for i in range(args.warmup):
+        nc = h.color_device(out, args.seed, cfg.frac, cfg.alpha, cfg.relation)
+        log(f"bench: warmup {i + 1}/{args.warmup}: {nc} colours")
+    torch.cuda.synchronize()
+    per_step = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        nc = h.color_device(out, args.seed, cfg.frac, cfg.alpha, cfg.relation)
+        per_step.append(h.stats())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"bench: {args.steps} steps in {elapsed:.3f} s")
+    st = per_step[-1]
+    ms_step = elapsed * 1e3 / args.steps
+    pair_tests = st["pair_tests"]
+    edges = st["edges"]
+
+    # dominant kernel: the pair count pass (every pair test), timed with HIP
+    # events on the library's stream around each launch
+    count_ms = sum(it["ms_count"] for s in per_step for it in s["iters"])
+    fill_ms = sum(it["ms_fill"] for s in per_step for it in s["iters"])
+    color_ms = sum(it["ms_color"] for s in per_step for it in s["iters"])
+    launches = sum(len(s["iters"]) for s in per_step)
+    W = (cfg.q + 63) // 64
+    ops_per_test = 8 * W + 1
+    mfma = any(it["pair_path"] == pk.PATH_MFMA for it in st["iters"])
+    if mfma:
+        ops = sum(2 * (2 * cfg.q) * s["pair_tests"] for s in per_step)
+        achieved = ops / (count_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": MFMA_I8_PEAK_TOPS, "unit": "TOPS",
+                "frac": achieved / MFMA_I8_PEAK_TOPS, "traffic": None}
+    else:
+        ops = sum(ops_per_test * s["pair_tests"] for s in per_step)
+        achieved = ops / (count_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
+                "frac": achieved / VALU_PEAK_TOPS, "traffic": None}
+    roof["kernel"] = "pair count pass"
+    roof["avg_launch_ms"] = count_ms / max(launches, 1)
+    roof["launches"] = launches
+
+    line = {
+        "metric": METRIC,
+        "value": pair_tests / (ms_step * 1e-3),
+        "unit": "pair-tests/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": cfg.name, "n": cfg.n, "q": cfg.q, "probs": list(cfg.probs), "seed": args.seed,
+                   "palette_frac": cfg.frac, "list_size_alpha": cfg.alpha,
+                   "relation": ["anticommute", "qwc"][cfg.relation], "pair_path": args.path},
+        "end_to_end_s": ms_step * 1e-3,
+        "n_colors": nc,
+        "iterations": st["n_iters"],
+        "pair_tests": pair_tests,
+        "conflict_edges": edges,
+        "conflict_edges_per_s": edges / (ms_step * 1e-3),
+        "phase_ms_per_step": {"pair_count": count_ms / args.steps, "pair_fill": fill_ms / args.steps,
+                              "list_color": color_ms / args.steps},
+        "peak_device_bytes": st["peak_device_bytes"],
+        "roofline": roof,
+    }
+    h.close()
+    if not args.no_cpu_baseline:
+        log("bench: timing the CPU oracle on a bounded sample")
+        line["cpu_baseline"] = cpu_baseline(cfg, x, z, args.cpu_budget)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,181 @@
+/*
+ * picasso.h -- C ABI of the MI355X palette-colouring library (libpicasso.so).
+ *
+ * The library groups Pauli strings by colouring the graph whose edges are
+ * the pairs that FAIL the grouping relation, with the palette-sparsification
+ * method of Picasso (arXiv 2401.06713): each iteration draws a random colour
+ * list per vertex (Alg. 1, assign_rand_list_colors), builds the conflict
+ * graph of relation edges whose endpoints share a list colour (Alg. 1
+ * construct_conflict_graph; Sec. IV-A), list-colours it in a random static
+ * order (Sec. IV-B, static order schemes) and recurses on the uncoloured
+ * vertices with a fresh palette (Alg. 1).  A colour class is therefore a set
+ * of mutually commuting (ANTICOMMUTE relation) or qubit-wise commuting (QWC
+ * relation) strings.
+ *
+ * Conventions shared by every entry point:
+ *  - A Pauli string on q qubits is two bit-planes x and z of W = ceil(q/64)
+ *    uint64 words; qubit k is bit k%64 of word k/64; (x,z) = (0,0) I,
+ *    (1,0) X, (1,1) Y, (0,1) Z.  Arrays of n strings are row-major n x W.
+ *    Bits >= q of the last word must be zero.
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *    device memory of the current device (e.g. a torch tensor's data_ptr).
+ *  - Every call returns a negative PICASSO_E* code on failure and records a
+ *    message readable with picasso_last_error() on the same thread; no C++
+ *    exception crosses this boundary.
+ *  - A handle is not thread-safe: use one handle per host thread.  All work
+ *    of a handle runs on its stream; calls return after that stream has
+ *    finished the work unless stated otherwise.
+ */
+#ifndef PICASSO_H
+#define PICASSO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct picasso_ctx *picasso_handle;
+
+/* Grouping relations: an edge joins two strings that fail the relation. */
+enum {
+    PICASSO_REL_ANTICOMMUTE = 0, /* edge iff the strings anticommute: odd number of
+                                    anticommuting positions (Sec. IV-A, Eq. 5)      */
+    PICASSO_REL_QWC = 1          /* edge iff not qubit-wise commuting: some position
+                                    holds two different non-identity Paulis (Sec. III) */
+};
+
+/* Return codes. */
+enum {
+    PICASSO_OK = 0,
+    PICASSO_EINVAL = -1,   /* bad argument; nothing was changed                */
+    PICASSO_ENOMEM = -2,   /* the conflict graph does not fit the memory budget */
+    PICASSO_EDEVICE = -3,  /* a HIP call failed; the message names it           */
+    PICASSO_EINTERNAL = -4 /* internal invariant violated                        */
+};
+
+/* Options for picasso_set_option. */
+enum {
+    PICASSO_OPT_MEM_BUDGET = 1, /* max device bytes for one iteration's conflict
+                                   graph (CSR); 0 = no limit beyond the device  */
+    PICASSO_OPT_PAIR_PATH = 2,  /* 0 auto, 1 popcount VALU, 2 int8 MFMA          */
+    PICASSO_OPT_FIXED_T = 3,    /* >0: list size T fixed (clamped to P) instead of
+                                   ceil(alpha ln m); 0 restores the formula      */
+    PICASSO_OPT_STREAM = 4,     /* hipStream_t (cast to int64) to run on; 0 = the
+                                   handle's own stream.  The caller keeps the
+                                   stream alive while the handle uses it.        */
+    PICASSO_OPT_TIMING = 5      /* 1: record per-phase times (adds event syncs)  */
+};
+
+#define PICASSO_PATH_AUTO 0
+#define PICASSO_PATH_VALU 1
+#define PICASSO_PATH_MFMA 2
+
+#define PICASSO_MAX_T 256          /* largest list size the kernels accept   */
+#define PICASSO_MAX_ITER_STATS 256 /* per-iteration records kept in stats    */
+
+/* Per-iteration record. Times are milliseconds (0 unless PICASSO_OPT_TIMING). */
+typedef struct {
+    int64_t m;          /* uncoloured vertices entering the iteration         */
+    int64_t P;          /* palette size                                       */
+    int64_t T;          /* list size                                          */
+    int64_t pair_tests; /* sum over colours c of C(|B_c|, 2)                   */
+    int64_t edges;      /* |E_c|, undirected conflict edges                    */
+    int64_t colored;    /* vertices coloured in this iteration                 */
+    int64_t offset;     /* first global colour id of this iteration's palette  */
+    int32_t pair_path;  /* PICASSO_PATH_VALU or PICASSO_PATH_MFMA              */
+    int32_t jp_rounds;  /* colouring rounds                                    */
+    double ms_lists, ms_buckets, ms_count, ms_fill, ms_color, ms_compact;
+} picasso_iter_stats;
+
+/* Summary of the handle's last colouring call. */
+typedef struct {
+    int64_t n;
+    int64_t n_colors;      /* distinct colours used                            */
+    int64_t palette_total; /* sum of palette sizes (an upper bound)           */
+    int64_t pair_tests;    /* over all iterations                              */
+    int64_t edges;         /* over all iterations                              */
+    int64_t max_edges;     /* largest single-iteration |E_c|                   */
+    int64_t peak_device_bytes;
+    int32_t n_iters;
+    int32_t reserved;
+    double ms_total; /* wall time of the call                                */
+    picasso_iter_stats iters[PICASSO_MAX_ITER_STATS];
+} picasso_stats;
+
+/* Most recent error message of this host thread ("" if none). */
+const char *picasso_last_error(void);
+
+/* Create a handle holding a device copy of n strings on q qubits.
+ * x_words, z_words: host, n*W uint64 each (copied; the caller may free them).
+ * 0 <= n < 2^31, 1 <= q <= 256.  Duplicate strings are allowed (they are
+ * never joined by an edge).  Returns NULL on error (see picasso_last_error):
+ * bad sizes, NULL pointers with n > 0, or padding bits set. */
+picasso_handle picasso_create(int64_t n, int32_t q, const uint64_t *x_words, const uint64_t *z_words);
+
+/* As picasso_create, but x_words/z_words are device pointers (copied
+ * device-to-device; padding bits are checked on the device). */
+picasso_handle picasso_create_device(int64_t n, int32_t q, const uint64_t *x_words, const uint64_t *z_words);
+
+/* Release the handle and all device memory it owns.  NULL is ignored. */
+void picasso_destroy(picasso_handle h);
+
+/* Set an option (PICASSO_OPT_*).  Returns PICASSO_OK or PICASSO_EINVAL. */
+int32_t picasso_set_option(picasso_handle h, int32_t key, int64_t value);
+
+/* Colour all strings (Alg. 1).
+ * seed: keys every random draw (lists and priorities).
+ * palette_frac f in (0, 1]: iteration palette P = max(1, ceil(f m)).
+ * list_size alpha > 0 (a multiplier): T = clamp(ceil(alpha ln m), 1, P).
+ * relation: PICASSO_REL_*.
+ * out_colors: host, n int32, receives global colour ids (iteration l uses
+ * ids [offset_l, offset_l + P_l), offsets cumulative).
+ * Returns the number of distinct colours (>= 0) or a negative error. */
+int64_t picasso_color(picasso_handle h, uint64_t seed, double palette_frac, double list_size, int32_t relation,
+                      int32_t *out_colors);
+
+/* As picasso_color, but out_colors is a device pointer (n int32).  The
+ * result is complete when the call returns. */
+int64_t picasso_color_device(picasso_handle h, uint64_t seed, double palette_frac, double list_size,
+                             int32_t relation, int32_t *out_colors);
+
+/* Copy the last colouring call's statistics.  Returns PICASSO_OK. */
+int32_t picasso_get_stats(picasso_handle h, picasso_stats *out);
+
+/* ---- Single steps of one iteration, for tests and tools ---------------- */
+
+/* Colour lists and priorities of iteration `ell` for the vertices ids[0..m)
+ * (host, ascending original ids) with palette P and list size T
+ * (1 <= T <= min(P, PICASSO_MAX_T)).  out_lists: host, m*T uint32,
+ * row-major, each row sorted ascending (Floyd's sample of a uniform
+ * T-subset of [0,P), one Philox4x32-10 draw per step keyed by
+ * (seed; vertex, slot, ell)).  out_prio: host, m uint64 (may be NULL). */
+int32_t picasso_sample_lists(picasso_handle h, uint64_t seed, int32_t ell, int64_t m, const int32_t *ids,
+                             int64_t P, int32_t T, uint32_t *out_lists, uint64_t *out_prio);
+
+/* Conflict graph of iteration `ell` over ids[0..m) (host, ascending):
+ * {a, b} is an edge iff the relation holds and the lists share a colour
+ * (Alg. 1 construct_conflict_graph; Sec. IV-A).  Output is the symmetric
+ * CSR in local indices: out_rowptr host int64[m+1]; out_adj host int32,
+ * capacity adj_cap entries (2|E_c| are needed; rows are unordered).  Either
+ * output may be NULL to only count.  Returns |E_c| (undirected) or an error;
+ * if 2|E_c| > adj_cap nothing is written to out_adj. */
+int64_t picasso_conflict_graph(picasso_handle h, uint64_t seed, int32_t ell, int64_t m, const int32_t *ids,
+                               int64_t P, int32_t T, int32_t relation, int64_t *out_rowptr, int32_t *out_adj,
+                               int64_t adj_cap);
+
+/* List-colour a given conflict graph in the random static order: vertices
+ * taken by ascending (prio, index), each gets the smallest colour of its
+ * list held by no earlier neighbour, or -1 (Sec. IV-B).  Computed in
+ * parallel (Jones-Plassmann rounds) with the sequential result.
+ * prio host uint64[m]; lists host uint32[m*T] (rows sorted, values < P);
+ * rowptr host int64[m+1]; adj host int32[rowptr[m]] (symmetric CSR);
+ * out_col host int32[m].  Returns the number of coloured vertices. */
+int64_t picasso_list_color_csr(picasso_handle h, int64_t m, const uint64_t *prio, const uint32_t *lists, int32_t T,
+                               int64_t P, const int64_t *rowptr, const int32_t *adj, int32_t *out_col);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PICASSO_H */

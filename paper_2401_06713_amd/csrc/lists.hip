@@ -1,0 +1,175 @@
+// Random colour lists (Alg. 1 assign_rand_list_colors) and colour buckets.
+//
+// Lists: each vertex gets a uniform T-subset of the palette [0, P) (Sec. IV:
+// colours drawn uniformly at random), drawn with Floyd's algorithm, one
+// Philox4x32-10 value per step keyed by (seed; original vertex id, step,
+// iteration), kept sorted in LDS while it is built.  Keys use the original
+// id, so a list does not depend on where the vertex sits in the compacted
+// vertex set or on the thread that draws it.
+//
+// Buckets: B_c = {(vertex, slot) : L(vertex)[slot] = c}, built by a count
+// (one atomic per list entry), an exclusive scan and a scatter.  Only
+// vertices inside one bucket can conflict through colour c, so the pair
+// kernels test pairs inside buckets instead of all C(m,2) pairs.
+#include "common.h"
+
+namespace picasso {
+namespace {
+
+// One thread per vertex.  s[T][blockDim] holds each thread's sorted set
+// (slot-major, so consecutive threads hit consecutive LDS banks).
+__global__ void sample_lists_kernel(uint64_t seed, uint32_t ell, int64_t m, const int32_t *__restrict__ ids,
+                                    int64_t P, int32_t T, uint32_t *__restrict__ lists, uint64_t *__restrict__ prio)
+{
+    extern __shared__ uint32_t s[];
+    const int B = blockDim.x, t = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * B;
+    const int64_t i = r0 + t;
+    if (i < m) {
+        const uint32_t v = (uint32_t)ids[i];
+        int cnt = 0;
+        for (int step = 0; step < T; ++step) {
+            const uint64_t j = (uint64_t)(P - T + step);
+            const uint64_t r = philox_draw(seed, v, (uint32_t)step, ell, TAG_LIST);
+            const uint32_t cand = (uint32_t)__umul64hi(r, j + 1);  // in [0, j]
+            // binary search for cand among s[0..cnt)
+            int lo = 0, hi = cnt;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (s[mid * B + t] < cand) lo = mid + 1;
+                else hi = mid;
+            }
+            if (lo < cnt && s[lo * B + t] == cand) {
+                // present: take j, larger than every value drawn so far
+                s[cnt * B + t] = (uint32_t)j;
+            } else {
+                for (int k = cnt; k > lo; --k) s[k * B + t] = s[(k - 1) * B + t];
+                s[lo * B + t] = cand;
+            }
+            ++cnt;
+        }
+        if (prio) prio[i] = philox_draw(seed, v, 0, ell, TAG_PRIO);
+    }
+    __syncthreads();
+    const int64_t rows = (m - r0) < B ? (m - r0) : B;
+    const int64_t words = rows * T;
+    uint32_t *dst = lists + r0 * T;
+    for (int64_t e = t; e < words; e += B) {
+        const int64_t row = e / T, slot = e - row * T;
+        dst[e] = s[slot * B + row];
+    }
+}
+
+__global__ void bucket_count_kernel(const uint32_t *__restrict__ lists, int64_t entries, uint32_t *__restrict__ bcnt)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < entries; e += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&bcnt[lists[e]], 1u);
+}
+
+__global__ void bucket_scatter_kernel(const uint32_t *__restrict__ lists, int64_t m, int32_t T,
+                                      const int64_t *__restrict__ bstart, uint32_t *__restrict__ bfill,
+                                      uint32_t *__restrict__ bmem, uint8_t *__restrict__ bslot)
+{
+    const int64_t entries = m * T;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < entries;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t c = lists[e];
+        const int64_t at = bstart[c] + atomicAdd(&bfill[c], 1u);
+        const int64_t row = e / T;
+        bmem[at] = (uint32_t)row;
+        bslot[at] = (uint8_t)(e - row * T);
+    }
+}
+
+__global__ void check_padding_kernel(const uint64_t *x, const uint64_t *z, int64_t n, int32_t q, int32_t *bad)
+{
+    const int W = (q + 63) / 64, rem = q % 64;
+    if (rem == 0) return;
+    const uint64_t mask = ~((1ull << rem) - 1ull);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if ((x[i * W + W - 1] | z[i * W + W - 1]) & mask) atomicExch(bad, 1);
+}
+
+__global__ void bucket_pairs_kernel(const uint32_t *__restrict__ bcnt, int64_t P, unsigned long long *pairs)
+{
+    unsigned long long s = 0;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < P; c += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long k = bcnt[c];
+        s += k * (k - (k > 0)) / 2;
+    }
+    for (int d = 32; d > 0; d >>= 1) s += __shfl_down(s, d, 64);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd(pairs, s);
+}
+
+template <typename V>
+__global__ void fill_kernel(V *p, int64_t n, V v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+unsigned grid_for(int64_t work, int threads, unsigned cap = 65535u * 4)
+{
+    int64_t b = (work + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (unsigned)b;
+}
+
+}  // namespace
+
+void launch_sample_lists(uint64_t seed, uint32_t ell, int64_t m, const int32_t *ids, int64_t P, int32_t T,
+                         uint32_t *lists, uint64_t *prio, hipStream_t st)
+{
+    if (m <= 0) return;
+    const int B = T <= 64 ? 256 : (T <= 128 ? 128 : 64);
+    const size_t lds = (size_t)T * B * sizeof(uint32_t);
+    const int64_t blocks = (m + B - 1) / B;
+    sample_lists_kernel<<<(unsigned)blocks, B, lds, st>>>(seed, ell, m, ids, P, T, lists, prio);
+    PCHECK_LAUNCH();
+}
+
+void launch_bucket_count(const uint32_t *lists, int64_t entries, uint32_t *bcnt, hipStream_t st)
+{
+    if (entries <= 0) return;
+    bucket_count_kernel<<<grid_for(entries, 256), 256, 0, st>>>(lists, entries, bcnt);
+    PCHECK_LAUNCH();
+}
+
+void launch_bucket_scatter(const uint32_t *lists, int64_t m, int32_t T, const int64_t *bstart, uint32_t *bfill,
+                           uint32_t *bmem, uint8_t *bslot, hipStream_t st)
+{
+    if (m <= 0) return;
+    bucket_scatter_kernel<<<grid_for(m * T, 256), 256, 0, st>>>(lists, m, T, bstart, bfill, bmem, bslot);
+    PCHECK_LAUNCH();
+}
+
+void launch_check_padding(const uint64_t *x, const uint64_t *z, int64_t n, int32_t q, int32_t *bad, hipStream_t st)
+{
+    if (n <= 0) return;
+    check_padding_kernel<<<grid_for(n, 256), 256, 0, st>>>(x, z, n, q, bad);
+    PCHECK_LAUNCH();
+}
+
+void launch_bucket_pairs(const uint32_t *bcnt, int64_t P, unsigned long long *pairs, hipStream_t st)
+{
+    if (P <= 0) return;
+    bucket_pairs_kernel<<<grid_for(P, 256, 2048), 256, 0, st>>>(bcnt, P, pairs);
+    PCHECK_LAUNCH();
+}
+
+void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st)
+{
+    if (n <= 0) return;
+    fill_kernel<int32_t><<<grid_for(n, 256), 256, 0, st>>>(p, n, v);
+    PCHECK_LAUNCH();
+}
+
+void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st)
+{
+    if (n <= 0) return;
+    fill_kernel<uint32_t><<<grid_for(n, 256), 256, 0, st>>>(p, n, v);
+    PCHECK_LAUNCH();
+}
+
+}  // namespace picasso

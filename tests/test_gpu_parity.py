@@ -1,0 +1,232 @@
+"""HIP path vs the CPU oracle, element by element, through the C ABI.
+
+All integer work: the bar is bit-exact.  Conflict-graph rows come back
+unordered (the order of edges inside a CSR row carries no meaning), so
+edge sets are compared in canonical sorted form.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2401_06713_amd as pk
+from paper_2401_06713_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def strings(n, q, probs=(0.25, 0.25, 0.25, 0.25), seed=0):
+    return wl.pauli_strings(n, q, probs, seed=seed)
+
+
+# ---------------------------------------------------------------- lists
+@pytest.mark.parametrize("n,q,P,T,ell,sub", [
+    (2000, 16, 250, 16, 1, False),      # C1 sizes
+    (5000, 48, 25000, 25, 1, False),
+    (3000, 20, 300, 64, 2, True),
+    (1500, 20, 5000, 65, 3, True),      # 128-thread sampler blocks
+    (777, 20, 4000, 256, 5, True),      # largest T, 64-thread blocks
+    (300, 20, 7, 7, 1, False),          # T = P
+    (301, 20, 1, 1, 2, False),          # P = 1
+])
+def test_lists_bit_exact(orc, n, q, P, T, ell, sub):
+    say("lists", n, q, P, T, ell, sub)
+    x, z = strings(n, q, seed=n)
+    ids = np.arange(n, dtype=np.int32)
+    if sub:
+        ids = np.sort(np.random.default_rng(1).choice(n, n // 2 + 1, replace=False)).astype(np.int32)
+    with pk.Picasso(x, z, q) as h:
+        lists, prio = h.sample_lists(12345, ell, ids, P, T)
+    ref = orc.sample_lists(12345, ell, ids, P, T)
+    assert np.array_equal(lists, ref)
+    ref_prio = orc.priorities(12345, ell, ids)
+    assert np.array_equal(prio, ref_prio)
+
+
+# ---------------------------------------------------------------- conflict graph
+def gpu_edges(h, seed, ell, ids, P, T, rel):
+    rowptr, adj = h.conflict_graph(seed, ell, ids, P, T, rel)
+    e = pk.edges_from_csr(rowptr, adj)
+    # symmetric and duplicate-free rows
+    deg = np.diff(rowptr)
+    assert deg.sum() == 2 * len(e)
+    assert len(np.unique(e, axis=0)) == len(e)
+    return e
+
+
+@pytest.mark.parametrize("rel", [0, 1])
+@pytest.mark.parametrize("n,q,probs,P,T", [
+    (2000, 16, (0.25, 0.25, 0.25, 0.25), 250, 16),    # C1 iteration 1
+    (1500, 48, (0.7, 0.1, 0.1, 0.1), 120, 20),
+    (1200, 100, (0.8, 0.2 / 3, 0.2 / 3, 0.2 / 3), 60, 14),  # W = 2
+    (900, 150, (0.8, 0.2 / 3, 0.2 / 3, 0.2 / 3), 40, 9),    # W = 3
+    (800, 256, (0.85, 0.05, 0.05, 0.05), 30, 8),             # W = 4
+    (1100, 30, (0.6, 0.1, 0.2, 0.1), 2, 1),                 # buckets > 512 members (column chunks)
+    (700, 64, (0.5, 0.2, 0.2, 0.1), 9000, 3),               # mostly empty buckets
+])
+def test_conflict_graph_bit_exact(orc, rel, n, q, probs, P, T):
+    say("graph", rel, n, q, P, T)
+    x, z = strings(n, q, probs, seed=q)
+    ids = np.sort(np.random.default_rng(q).choice(n, n - n // 5, replace=False)).astype(np.int32)
+    with pk.Picasso(x, z, q) as h:
+        got = gpu_edges(h, 99, 2, ids, P, T, rel)
+    ch = orc.decode(x, z, q)
+    lists = orc.sample_lists(99, 2, ids, P, T)
+    ref, cnt, _ = orc.conflict_edges_bucketed(ch, ids, lists, P, rel)
+    assert cnt == len(got)
+    assert np.array_equal(got, ref)
+
+
+# ---------------------------------------------------------------- list colouring
+@pytest.mark.parametrize("seed", range(5))
+def test_jp_equals_sequential_greedy(orc, seed):
+    rng = np.random.default_rng(100 + seed)
+    m = int(rng.integers(50, 4000))
+    P = int(rng.integers(1, 200))
+    T = int(rng.integers(1, min(P, 130) + 1))
+    lists = np.sort(np.array([rng.choice(P, T, replace=False) for _ in range(m)]), axis=1).astype(np.uint32)
+    k = int(rng.integers(0, min(m * 30, 200_000)))
+    a = rng.integers(0, m, k)
+    b = rng.integers(0, m, k)
+    e = np.unique(np.stack([np.minimum(a, b), np.maximum(a, b)], 1)[a != b], axis=0).astype(np.int32)
+    prio = rng.integers(0, 2**63, m, dtype=np.int64).astype(np.uint64)
+    if seed == 3:
+        prio[:] = 5  # all tied: order by index
+    say("jp", m, P, T, len(e))
+    ref = orc.greedy_from_edges(prio, lists, P, e)
+    src = np.concatenate([e[:, 0], e[:, 1]])
+    dst = np.concatenate([e[:, 1], e[:, 0]])
+    order = np.argsort(src, kind="stable")
+    rowptr = np.zeros(m + 1, np.int64)
+    np.cumsum(np.bincount(src, minlength=m), out=rowptr[1:])
+    got = pk.list_color_csr(prio, lists, P, rowptr, dst[order])
+    assert np.array_equal(got, ref)
+
+
+# ---------------------------------------------------------------- whole method
+def run_both(orc, x, z, q, seed, frac, alpha, rel, fixed_T=0):
+    with pk.Picasso(x, z, q) as h:
+        if fixed_T:
+            h.set_option(pk.OPT_FIXED_T, fixed_T)
+        nc, col = h.color(seed, frac, alpha, rel)
+        st = h.stats()
+    rnc, rcol, rst = orc.color(x, z, q, seed, frac, alpha, rel, fixed_T=fixed_T)
+    assert nc == rnc
+    assert np.array_equal(col, rcol)
+    assert st["n_iters"] == len(rst)
+    for a, b in zip(st["iters"], rst):
+        for k in ("m", "P", "T", "pair_tests", "edges", "colored", "offset"):
+            assert a[k] == b[k], (k, a[k], b[k])
+    return nc, col, st
+
+
+def test_c1_bit_exact(orc):
+    say("C1")
+    cfg = wl.C1
+    x, z = wl.make(cfg)
+    for seed in range(3):
+        run_both(orc, x, z, cfg.q, seed, cfg.frac, cfg.alpha, cfg.relation)
+
+
+@pytest.mark.parametrize("rel", [0, 1])
+@pytest.mark.parametrize("n,q,probs,frac,alpha", [
+    (5000, 48, (0.7, 0.1, 0.1, 0.1), 0.125, 2.0),
+    (3000, 100, (0.8, 0.2 / 3, 0.2 / 3, 0.2 / 3), 0.05, 3.0),
+    (2500, 200, (0.75, 0.25 / 3, 0.25 / 3, 0.25 / 3), 0.25, 1.0),
+    (4000, 24, (0.5, 0.2, 0.2, 0.1), 0.02, 4.0),
+    (999, 64, (0.85, 0.05, 0.05, 0.05), 1.0, 0.5),
+])
+def test_color_bit_exact(orc, rel, n, q, probs, frac, alpha):
+    say("color", rel, n, q, frac, alpha)
+    x, z = strings(n, q, probs, seed=n + rel)
+    run_both(orc, x, z, q, 5, frac, alpha, rel)
+
+
+def test_edge_cases(orc):
+    say("edge cases")
+    # one string
+    x, z = strings(1, 7)
+    run_both(orc, x, z, 7, 0, 0.125, 2.0, 0)
+    # two anticommuting strings
+    run_both(orc, np.array([[1], [0]], np.uint64), np.array([[0], [1]], np.uint64), 1, 0, 0.125, 2.0, 0)
+    # complete graph: Jordan-Wigner Majoranas
+    x, z = wl.majorana_strings(40)
+    nc, _, _ = run_both(orc, x, z, 40, 1, 0.125, 2.0, 0)
+    assert nc == 80
+    # empty graph
+    x, z = wl.iz_strings(600, 16, seed=3)
+    for rel in (0, 1):
+        run_both(orc, x, z, 16, 2, 0.125, 2.0, rel)
+    # duplicates
+    x, z = strings(300, 10, seed=4)
+    x2, z2 = np.concatenate([x, x[:50]]), np.concatenate([z, z[:50]])
+    for rel in (0, 1):
+        run_both(orc, x2, z2, 10, 3, 0.125, 2.0, rel)
+    # fixed T and the full palette
+    x, z = strings(400, 12, seed=6)
+    run_both(orc, x, z, 12, 4, 1.0, 1.0, 0, fixed_T=256)
+    run_both(orc, x, z, 12, 4, 0.3, 1.0, 1, fixed_T=3)
+
+
+def test_empty_input():
+    with pk.Picasso(np.zeros((0, 1), np.uint64), np.zeros((0, 1), np.uint64), 5) as h:
+        nc, col = h.color(0, 0.125, 2.0, 0)
+        assert nc == 0 and col.size == 0
+
+
+def test_invalid_arguments():
+    x, z = strings(10, 5)
+    bad = x.copy()
+    bad[0, 0] |= np.uint64(1) << np.uint64(40)  # padding bit
+    with pytest.raises(pk.PicassoError):
+        pk.Picasso(bad, z, 5)
+    with pytest.raises(pk.PicassoError):
+        pk.Picasso(x, z, 0)
+    with pk.Picasso(x, z, 5) as h:
+        for args in ((0, 0.0, 2.0, 0), (0, 1.5, 2.0, 0), (0, 0.1, 0.0, 0), (0, 0.1, 2.0, 7)):
+            with pytest.raises(pk.PicassoError) as ei:
+                h.color(*args)
+            assert ei.value.code == pk.EINVAL
+        with pytest.raises(pk.PicassoError):
+            h.set_option(99, 1)
+
+
+def test_memory_budget_enomem():
+    x, z = strings(3000, 16)
+    with pk.Picasso(x, z, 16) as h:
+        h.set_option(pk.OPT_MEM_BUDGET, 1024)
+        with pytest.raises(pk.PicassoError) as ei:
+            h.color(0, 0.125, 2.0, 0)
+        assert ei.value.code == pk.ENOMEM
+        h.set_option(pk.OPT_MEM_BUDGET, 0)
+        nc, _ = h.color(0, 0.125, 2.0, 0)
+        assert nc > 0
+
+
+def test_device_io_matches_host_io(orc):
+    import torch
+
+    x, z = strings(3000, 40, (0.7, 0.1, 0.1, 0.1), seed=9)
+    with pk.Picasso(x, z, 40) as h:
+        nc, col = h.color(7, 0.125, 2.0, 0)
+    xd = torch.from_numpy(x.view(np.int64)).cuda()
+    zd = torch.from_numpy(z.view(np.int64)).cuda()
+    out = torch.empty(3000, dtype=torch.int32, device="cuda")
+    with pk.Picasso(xd, zd, 40) as h:
+        nc2 = h.color_device(out, 7, 0.125, 2.0, 0)
+    assert nc2 == nc
+    assert np.array_equal(out.cpu().numpy(), col)
+
+
+def test_repeat_calls_deterministic():
+    x, z = strings(4000, 32, (0.7, 0.1, 0.1, 0.1), seed=10)
+    with pk.Picasso(x, z, 32) as h:
+        a = h.color(3, 0.125, 2.0, 1)
+        b = h.color(3, 0.125, 2.0, 1)
+    assert a[0] == b[0] and np.array_equal(a[1], b[1])
