@@ -104,6 +104,14 @@ def lib() -> ctypes.CDLL:
             f"{LIB_PATH} is missing: build it with `python -m paper_2401_06713_amd.build_lib` "
             "(the HIP library is required; there is no fallback)"
         )
+    # One HIP runtime per process: torch ships its own libamdhip64.so.7.  If it
+    # is imported first, the library's dependency resolves to that same copy;
+    # loaded the other way round, torch would bring a second runtime that
+    # cannot initialise the device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     p, i32, i64, u64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
     L.picasso_last_error.restype = ctypes.c_char_p

@@ -73,8 +73,9 @@ struct picasso_ctx {
     Arena arena;
     DevBuf x, z;
     // iteration buffers
-    DevBuf ids, next_ids, lists, prio, bcnt, bstart, bmem, bslot, deg, rowptr, adj, cursor32, col, cursor64, forbid,
-        flags, pos, used, scan_tmp, scalars, out_colors;
+    DevBuf ids, next_ids, lists, prio, bcnt, bstart, bmem, bslot, pos_of, tmp_mem, tmp_slot, tiles, words, tile_off,
+        rb_off, R, D, nslow, slow, slot_cnt, slot_off, rowptr, adj, col, blk, fre, nblk, st, done, flags, pos, used,
+        scan_tmp, scalars, out_colors;
     picasso_stats stats;
 };
 
@@ -134,113 +135,190 @@ T read_scalar(picasso_ctx *h, const T *dptr)
     return v;
 }
 
-// Lists, priorities and buckets of one iteration.  Returns pair tests.
-int64_t build_lists_and_buckets(picasso_ctx *h, uint64_t seed, uint32_t ell, int64_t m, const int32_t *d_ids,
-                                int64_t P, int32_t T)
+struct BucketInfo {
+    int64_t pair_tests = 0;  // sum over colours of C(|B_c|, 2)
+    int64_t max_size = 0;    // largest bucket
+    int64_t row_tiles = 0;   // sum of ceil(|B_c|/64)
+    int64_t words = 0;       // sum of |B_c| * ceil(|B_c|/64)
+};
+
+// Buckets of the lists already in h->lists: count, scan, scatter, sort by
+// priority (h->prio), and the shapes of the per-bucket bit matrices.
+BucketInfo buckets_from_lists(picasso_ctx *h, int64_t m, int64_t P, int32_t T)
 {
     hipStream_t st = h->stream;
-    uint32_t *lists = buf<uint32_t>(h, h->lists, (size_t)m * T);
-    uint64_t *prio = buf<uint64_t>(h, h->prio, (size_t)m);
-    launch_sample_lists(seed, ell, m, d_ids, P, T, lists, prio, st);
+    const uint32_t *lists = static_cast<const uint32_t *>(h->lists.p);
+    const uint64_t *prio = static_cast<const uint64_t *>(h->prio.p);
     uint32_t *bcnt = buf<uint32_t>(h, h->bcnt, (size_t)P);
     int64_t *bstart = buf<int64_t>(h, h->bstart, (size_t)P + 1);
     unsigned long long *sc = buf<unsigned long long>(h, h->scalars, 8);
     launch_fill_u32(bcnt, P, 0u, st);
-    launch_fill_u32(reinterpret_cast<uint32_t *>(sc), 16, 0u, st);
+    launch_fill_u64(reinterpret_cast<uint64_t *>(sc), 8, 0ull, st);
     launch_bucket_count(lists, m * T, bcnt, st);
-    launch_bucket_pairs(bcnt, P, sc + 0, st);
-    void *tmp = h->arena.ensure(h->scan_tmp, scan_tmp_bytes(std::max<int64_t>(P, m)));
+    launch_bucket_pairs(bcnt, P, sc, st);
+    void *tmp = h->arena.ensure(h->scan_tmp, scan_tmp_bytes(std::max<int64_t>(P, m * T) + 1));
     exclusive_scan_u32_to_i64(bcnt, bstart, P, true, tmp, st);
     launch_fill_u32(bcnt, P, 0u, st);
     uint32_t *bmem = buf<uint32_t>(h, h->bmem, (size_t)m * T);
     uint8_t *bslot = buf<uint8_t>(h, h->bslot, (size_t)m * T);
     launch_bucket_scatter(lists, m, T, bstart, bcnt, bmem, bslot, st);
-    return (int64_t)read_scalar(h, sc + 0);
+    unsigned long long hs[2];
+    PCHECK_HIP(hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, st));
+    PCHECK_HIP(hipStreamSynchronize(st));
+    BucketInfo bi;
+    bi.pair_tests = (int64_t)hs[0];
+    bi.max_size = (int64_t)hs[1];
+    if (bi.max_size > (int64_t)1 << 17)
+        throw Error(PICASSO_EINVAL, "a colour bucket holds " + std::to_string(bi.max_size) +
+                                        " vertices (limit 131072): palette too small for this many vertices");
+    const bool large = bi.max_size > 2048;
+    uint32_t *tmem = large ? buf<uint32_t>(h, h->tmp_mem, (size_t)m * T) : nullptr;
+    uint8_t *tslot = large ? buf<uint8_t>(h, h->tmp_slot, (size_t)m * T) : nullptr;
+    int64_t *pos_of = buf<int64_t>(h, h->pos_of, (size_t)m * T);
+    launch_bucket_sort(bstart, P, bmem, bslot, prio, pos_of, T, large, tmem, tslot, st);
+    int64_t *tiles = buf<int64_t>(h, h->tiles, (size_t)P);
+    int64_t *words = buf<int64_t>(h, h->words, (size_t)P);
+    int64_t *tile_off = buf<int64_t>(h, h->tile_off, (size_t)P + 1);
+    int64_t *rb_off = buf<int64_t>(h, h->rb_off, (size_t)P + 1);
+    launch_bucket_shapes(bstart, P, tiles, words, st);
+    exclusive_scan_i64(tiles, tile_off, P, true, tmp, st);
+    exclusive_scan_i64(words, rb_off, P, true, tmp, st);
+    int64_t t2[2];
+    PCHECK_HIP(hipMemcpyAsync(&t2[0], tile_off + P, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    PCHECK_HIP(hipMemcpyAsync(&t2[1], rb_off + P, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    PCHECK_HIP(hipStreamSynchronize(st));
+    bi.row_tiles = t2[0];
+    bi.words = t2[1];
+    return bi;
 }
 
-PairArgs pair_args(picasso_ctx *h, int64_t m, int64_t P, int32_t T, int32_t rel)
+// Lists, priorities and buckets of one iteration.
+BucketInfo build_lists_and_buckets(picasso_ctx *h, uint64_t seed, uint32_t ell, int64_t m, const int32_t *d_ids,
+                                   int64_t P, int32_t T)
 {
-    PairArgs a{};
-    a.bstart = static_cast<const int64_t *>(h->bstart.p);
-    a.bmem = static_cast<const uint32_t *>(h->bmem.p);
-    a.bslot = static_cast<const uint8_t *>(h->bslot.p);
-    a.P = P;
-    a.ids = static_cast<const int32_t *>(h->ids.p);
-    a.x = static_cast<const uint64_t *>(h->x.p);
-    a.z = static_cast<const uint64_t *>(h->z.p);
-    a.W = h->W;
-    a.lists = static_cast<const uint32_t *>(h->lists.p);
-    a.T = T;
-    a.relation = rel;
-    a.m = m;
-    return a;
+    uint32_t *lists = buf<uint32_t>(h, h->lists, (size_t)m * T);
+    uint64_t *prio = buf<uint64_t>(h, h->prio, (size_t)m);
+    launch_sample_lists(seed, ell, m, d_ids, P, T, lists, prio, h->stream);
+    return buckets_from_lists(h, m, P, T);
 }
 
-// Count pass, scan, fill pass.  Returns |E_c|; the CSR is in h->rowptr/adj.
-int64_t build_conflict_graph(picasso_ctx *h, int64_t m, int64_t P, int32_t T, int32_t rel, double *ms_count,
-                             double *ms_fill)
+// Relation matrices, duplicate-pair matrices, CSR counts, scan and fill.
+// Returns |E_c|; the CSR is in h->rowptr / h->adj.
+int64_t build_conflict_graph(picasso_ctx *h, int64_t m, int64_t P, int32_t T, int32_t rel, const BucketInfo &bi,
+                             double *ms_relate, double *ms_csr)
 {
     hipStream_t st = h->stream;
     Timer tm(h);
-    PairArgs a = pair_args(h, m, P, T, rel);
-    int32_t *deg = buf<int32_t>(h, h->deg, (size_t)m);
-    launch_fill_i32(deg, m, 0, st);
-    a.deg = deg;
+    uint64_t *R = buf<uint64_t>(h, h->R, (size_t)std::max<int64_t>(bi.words, 1));
+    uint64_t *D = buf<uint64_t>(h, h->D, (size_t)std::max<int64_t>(bi.words, 1));
+    RelateArgs ra{};
+    ra.bstart = static_cast<const int64_t *>(h->bstart.p);
+    ra.bmem = static_cast<const uint32_t *>(h->bmem.p);
+    ra.P = P;
+    ra.tile_off = static_cast<const int64_t *>(h->tile_off.p);
+    ra.total_row_tiles = bi.row_tiles;
+    ra.rb_off = static_cast<const int64_t *>(h->rb_off.p);
+    ra.ids = static_cast<const int32_t *>(h->ids.p);
+    ra.x = static_cast<const uint64_t *>(h->x.p);
+    ra.z = static_cast<const uint64_t *>(h->z.p);
+    ra.W = h->W;
+    ra.relation = rel;
+    ra.R = R;
     tm.mark();
-    launch_pair_count(a, st);
+    launch_relate(ra, st);
     tm.mark();
+    // pairs sharing a smaller colour
+    launch_fill_u64(D, bi.words, 0ull, st);
+    int32_t *nslow = buf<int32_t>(h, h->nslow, 16);
+    launch_fill_i32(nslow, 1, 0, st);
+    DupArgs da{};
+    da.bstart = ra.bstart;
+    da.bmem = ra.bmem;
+    da.bslot = static_cast<const uint8_t *>(h->bslot.p);
+    da.P = P;
+    da.rb_off = ra.rb_off;
+    da.lists = static_cast<const uint32_t *>(h->lists.p);
+    da.T = T;
+    da.D = D;
+    da.slow = buf<uint32_t>(h, h->slow, (size_t)P);
+    da.n_slow = nslow;
+    if (T > 1) {
+        launch_dup(da, st);
+        const int32_t n_slow = read_scalar(h, nslow);
+        launch_dup_slow(da, n_slow, st);
+    }
+    // edge counts per (vertex, slot), scan, row pointers
+    CsrArgs ca{};
+    ca.bstart = ra.bstart;
+    ca.bmem = ra.bmem;
+    ca.bslot = da.bslot;
+    ca.P = P;
+    ca.rb_off = ra.rb_off;
+    ca.R = R;
+    ca.D = D;
+    ca.T = T;
+    ca.slot_cnt = buf<int32_t>(h, h->slot_cnt, (size_t)m * T);
+    launch_count(ca, st);
+    int64_t *slot_off = buf<int64_t>(h, h->slot_off, (size_t)m * T + 1);
+    void *tmp = h->arena.ensure(h->scan_tmp, scan_tmp_bytes(std::max<int64_t>(P, m * T) + 1));
+    exclusive_scan_i32_to_i64(ca.slot_cnt, slot_off, m * T, true, tmp, st);
     int64_t *rowptr = buf<int64_t>(h, h->rowptr, (size_t)m + 1);
-    void *tmp = h->arena.ensure(h->scan_tmp, scan_tmp_bytes(std::max<int64_t>(P, m)));
-    exclusive_scan_i32_to_i64(deg, rowptr, m, true, tmp, st);
-    const int64_t total = read_scalar(h, rowptr + m);
+    launch_rowptr(slot_off, m, T, rowptr, st);
+    const int64_t total = read_scalar(h, slot_off + m * T);
     if (total % 2) throw Error(PICASSO_EINTERNAL, "odd CSR size");
     const int64_t bytes = total * (int64_t)sizeof(int32_t);
     if (h->mem_budget > 0 && bytes > h->mem_budget)
         throw Error(PICASSO_ENOMEM, "conflict graph needs " + std::to_string(bytes) + " bytes, budget " +
                                         std::to_string(h->mem_budget));
-    int32_t *adj = buf<int32_t>(h, h->adj, (size_t)std::max<int64_t>(total, 1));
-    int32_t *cursor = buf<int32_t>(h, h->cursor32, (size_t)m);
-    launch_fill_i32(cursor, m, 0, st);
-    a.rowptr = rowptr;
-    a.cursor = cursor;
-    a.adj = adj;
+    ca.slot_off = slot_off;
+    ca.adj = buf<int32_t>(h, h->adj, (size_t)std::max<int64_t>(total, 1));
     tm.mark();
-    launch_pair_fill(a, st);
+    launch_fill(ca, st);
     tm.mark();
-    if (ms_count) *ms_count = tm.ms(0, 1);
-    if (ms_fill) *ms_fill = tm.ms(2, 3);
+    if (ms_relate) *ms_relate = tm.ms(0, 1);
+    if (ms_csr) *ms_csr = tm.ms(2, 3);
     return total / 2;
 }
 
-// Jones-Plassmann rounds until every vertex is decided.  Result in h->col.
-int32_t color_graph(picasso_ctx *h, int64_t m, int32_t T)
+// List colouring rounds until every vertex is decided.  Result in h->col.
+int32_t color_buckets(picasso_ctx *h, int64_t m, int64_t P, int32_t T, const BucketInfo &bi)
 {
     hipStream_t st = h->stream;
-    ColorArgs c{};
-    c.m = m;
-    c.rowptr = static_cast<const int64_t *>(h->rowptr.p);
-    c.adj = static_cast<const int32_t *>(h->adj.p);
-    c.prio = static_cast<const uint64_t *>(h->prio.p);
-    c.lists = static_cast<const uint32_t *>(h->lists.p);
-    c.T = T;
-    c.col = buf<int32_t>(h, h->col, (size_t)m);
-    c.cursor = buf<int64_t>(h, h->cursor64, (size_t)m);
-    c.fw = (T + 63) / 64;
-    c.forbid = buf<uint64_t>(h, h->forbid, (size_t)m * c.fw);
+    JpArgs j{};
+    j.P = P;
+    j.bstart = static_cast<const int64_t *>(h->bstart.p);
+    j.bmem = static_cast<const uint32_t *>(h->bmem.p);
+    j.bslot = static_cast<const uint8_t *>(h->bslot.p);
+    j.rb_off = static_cast<const int64_t *>(h->rb_off.p);
+    j.R = static_cast<const uint64_t *>(h->R.p);
+    j.nw_max = std::max<int64_t>((bi.max_size + 63) / 64, 1);
+    j.T = T;
+    j.fw = (T + 63) / 64;
+    j.col = buf<int32_t>(h, h->col, (size_t)m);
+    j.blk = buf<uint64_t>(h, h->blk, (size_t)m * j.fw);
+    j.fre = buf<uint64_t>(h, h->fre, (size_t)m * j.fw);
+    j.nblk = buf<int32_t>(h, h->nblk, (size_t)m);
+    j.st = buf<uint8_t>(h, h->st, (size_t)m * T);
+    j.done = buf<uint8_t>(h, h->done, (size_t)P);
     unsigned long long *sc = buf<unsigned long long>(h, h->scalars, 8);
-    c.progress = sc + 1;
-    launch_fill_u32(reinterpret_cast<uint32_t *>(sc + 1), 2, 0u, st);
-    launch_color_init(c, st);
+    j.progress = sc + 2;
+    launch_fill_i32(j.col, m, COL_UNDECIDED, st);
+    launch_fill_u64(j.blk, m * j.fw, 0ull, st);
+    launch_fill_u64(j.fre, m * j.fw, 0ull, st);
+    launch_fill_i32(j.nblk, m, 0, st);
+    launch_fill_u8(j.st, m * T, 0, st);
+    launch_fill_u8(j.done, P, 0, st);
+    launch_fill_u64(reinterpret_cast<uint64_t *>(j.progress), 1, 0ull, st);
     int32_t rounds = 0;
-    int batch = 4;
+    int batch = 1;
     while (true) {
-        for (int r = 0; r < batch; ++r) launch_color_round(c, st);
+        for (int r = 0; r < batch; ++r) launch_jp_round(j, st);
         rounds += batch;
-        const unsigned long long done = read_scalar(h, c.progress);
+        const unsigned long long done = read_scalar(h, j.progress);
         if ((int64_t)done >= m) break;
-        // every round decides at least the first undecided vertex in the order
-        if (rounds > m + 64) throw Error(PICASSO_EINTERNAL, "list colouring made no progress");
-        if (batch < 64) batch *= 2;
+        // every round decides at least the first undecided vertex of the order
+        if (rounds > 2 * m + 64) throw Error(PICASSO_EINTERNAL, "list colouring made no progress");
+        if (batch < 8) batch *= 2;
     }
     return rounds;
 }
@@ -285,19 +363,20 @@ int64_t color_all(picasso_ctx *h, uint64_t seed, double frac, double alpha, int3
         Timer tm(h);
         tm.mark();
         const int32_t *d_ids = static_cast<const int32_t *>(h->ids.p);
-        it.pair_tests = build_lists_and_buckets(h, seed, ell, m, d_ids, P, T);
+        const BucketInfo bi = build_lists_and_buckets(h, seed, ell, m, d_ids, P, T);
+        it.pair_tests = bi.pair_tests;
         tm.mark();
-        it.edges = build_conflict_graph(h, m, P, T, rel, &it.ms_count, &it.ms_fill);
+        it.edges = build_conflict_graph(h, m, P, T, rel, bi, &it.ms_count, &it.ms_fill);
         tm.mark();
-        it.jp_rounds = color_graph(h, m, T);
+        it.jp_rounds = color_buckets(h, m, P, T, bi);
         tm.mark();
         // global colours, used-colour count, next vertex set
         uint32_t *used = buf<uint32_t>(h, h->used, (size_t)(P + 31) / 32);
         launch_fill_u32(used, (P + 31) / 32, 0u, st);
         unsigned long long *sc = buf<unsigned long long>(h, h->scalars, 8);
-        launch_fill_u32(reinterpret_cast<uint32_t *>(sc + 2), 2, 0u, st);
+        launch_fill_u64(reinterpret_cast<uint64_t *>(sc + 3), 1, 0ull, st);
         int32_t *flags = buf<int32_t>(h, h->flags, (size_t)m);
-        launch_finish_iteration(m, static_cast<const int32_t *>(h->col.p), d_ids, offset, d_out, used, sc + 2, flags,
+        launch_finish_iteration(m, static_cast<const int32_t *>(h->col.p), d_ids, offset, d_out, used, sc + 3, flags,
                                 st);
         int64_t *pos = buf<int64_t>(h, h->pos, (size_t)m + 1);
         void *tmp = h->arena.ensure(h->scan_tmp, scan_tmp_bytes(std::max<int64_t>(P, m)));
@@ -306,9 +385,9 @@ int64_t color_all(picasso_ctx *h, uint64_t seed, double frac, double alpha, int3
         launch_compact_ids(m, d_ids, flags, pos, next, st);
         tm.mark();
         const int64_t m_next = read_scalar(h, pos + m);
-        const int64_t used_now = (int64_t)read_scalar(h, sc + 2);
+        const int64_t used_now = (int64_t)read_scalar(h, sc + 3);
         it.colored = m - m_next;
-        it.ms_lists = tm.ms(0, 1);
+        it.ms_buckets = tm.ms(0, 1);
         it.ms_color = tm.ms(2, 3);
         it.ms_compact = tm.ms(3, 4);
         if (it.colored <= 0) throw Error(PICASSO_EINTERNAL, "iteration coloured no vertex");
@@ -456,9 +535,11 @@ void picasso_destroy(picasso_handle h)
     if (!h) return;
     (void)hipSetDevice(h->device);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
-    DevBuf *all[] = {&h->x,      &h->z,       &h->ids,     &h->next_ids, &h->lists,    &h->prio,     &h->bcnt,
-                     &h->bstart, &h->bmem,    &h->bslot,   &h->deg,      &h->rowptr,   &h->adj,      &h->cursor32,
-                     &h->col,    &h->cursor64, &h->forbid, &h->flags,    &h->pos,      &h->used,     &h->scan_tmp,
+    DevBuf *all[] = {&h->x,       &h->z,        &h->ids,     &h->next_ids, &h->lists,   &h->prio,     &h->bcnt,
+                     &h->bstart,  &h->bmem,     &h->bslot,   &h->pos_of,   &h->tmp_mem, &h->tmp_slot, &h->tiles,
+                     &h->words,   &h->tile_off, &h->rb_off,  &h->R,        &h->D,       &h->nslow,    &h->slow,
+                     &h->slot_cnt, &h->slot_off, &h->rowptr, &h->adj,      &h->col,     &h->blk,      &h->fre,
+                     &h->nblk,    &h->st,       &h->done,    &h->flags,    &h->pos,     &h->used,     &h->scan_tmp,
                      &h->scalars, &h->out_colors};
     for (DevBuf *b : all) h->arena.release(*b);
     if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
@@ -595,8 +676,8 @@ int64_t picasso_conflict_graph(picasso_handle h, uint64_t seed, int32_t ell, int
             }
             int32_t *d_ids = buf<int32_t>(h, h->ids, (size_t)m);
             upload(h, d_ids, ids, (size_t)m * sizeof(int32_t));
-            build_lists_and_buckets(h, seed, (uint32_t)ell, m, d_ids, P, T);
-            const int64_t edges = build_conflict_graph(h, m, P, T, relation, nullptr, nullptr);
+            const BucketInfo bi = build_lists_and_buckets(h, seed, (uint32_t)ell, m, d_ids, P, T);
+            const int64_t edges = build_conflict_graph(h, m, P, T, relation, bi, nullptr, nullptr);
             if (out_rowptr) download(h, out_rowptr, h->rowptr.p, (size_t)(m + 1) * sizeof(int64_t));
             if (out_adj && 2 * edges <= adj_cap) download(h, out_adj, h->adj.p, (size_t)(2 * edges) * sizeof(int32_t));
             return edges;
@@ -622,12 +703,22 @@ int64_t picasso_list_color_csr(picasso_handle h, int64_t m, const uint64_t *prio
                 if (adj[e] < 0 || adj[e] >= m) throw Error(PICASSO_EINVAL, "CSR index out of range");
             for (int64_t e = 0; e < m * T; ++e)
                 if (lists[e] >= (uint64_t)P) throw Error(PICASSO_EINVAL, "list colour out of range");
+            for (int64_t i = 0; i < m; ++i)
+                for (int k = 1; k < T; ++k)
+                    if (lists[i * T + k] <= lists[i * T + k - 1]) throw Error(PICASSO_EINVAL, "list rows must be sorted");
             upload(h, buf<uint64_t>(h, h->prio, (size_t)m), prio, (size_t)m * sizeof(uint64_t));
             upload(h, buf<uint32_t>(h, h->lists, (size_t)m * T), lists, (size_t)m * T * sizeof(uint32_t));
-            upload(h, buf<int64_t>(h, h->rowptr, (size_t)m + 1), rowptr, (size_t)(m + 1) * sizeof(int64_t));
-            upload(h, buf<int32_t>(h, h->adj, (size_t)std::max<int64_t>(total, 1)), adj,
-                   (size_t)total * sizeof(int32_t));
-            color_graph(h, m, T);
+            int64_t *d_rowptr = buf<int64_t>(h, h->rowptr, (size_t)m + 1);
+            int32_t *d_adj = buf<int32_t>(h, h->adj, (size_t)std::max<int64_t>(total, 1));
+            upload(h, d_rowptr, rowptr, (size_t)(m + 1) * sizeof(int64_t));
+            upload(h, d_adj, adj, (size_t)total * sizeof(int32_t));
+            const BucketInfo bi = buckets_from_lists(h, m, P, T);
+            uint64_t *R = buf<uint64_t>(h, h->R, (size_t)std::max<int64_t>(bi.words, 1));
+            launch_fill_u64(R, bi.words, 0ull, h->stream);
+            launch_csr_to_relation(m, d_rowptr, d_adj, static_cast<const uint32_t *>(h->lists.p), T,
+                                   static_cast<const int64_t *>(h->pos_of.p), static_cast<const int64_t *>(h->bstart.p),
+                                   static_cast<const int64_t *>(h->rb_off.p), R, h->stream);
+            color_buckets(h, m, P, T, bi);
             download(h, out_col, h->col.p, (size_t)m * sizeof(int32_t));
             int64_t colored = 0;
             for (int64_t i = 0; i < m; ++i) colored += out_col[i] >= 0;

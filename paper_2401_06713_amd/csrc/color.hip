@@ -1,76 +1,177 @@
-// List colouring of the conflict graph in a random static order
-// (Sec. IV-B, static order schemes; Alg. 1 colour step) and the hand-over
-// to the next iteration (Alg. 1: recurse on the uncoloured vertices with a
-// fresh palette).
+// List colouring of the conflict graph in a random static order (Sec. IV-B,
+// static order schemes; Alg. 1 colour step), evaluated in parallel.
 //
-// Sequential rule: take the vertices by ascending (priority, index); each
-// takes the smallest colour of its list that no earlier neighbour holds, or
-// stays uncoloured.  Jones-Plassmann evaluates the same rule in parallel: a
-// vertex is decided once every earlier neighbour is decided, so its choice
-// sees exactly the colours the sequential order would have shown it.
+// Sequential rule: vertices in ascending (priority, index) order; each takes
+// the smallest colour of its list that no earlier neighbour holds, or stays
+// uncoloured.  An earlier neighbour u can only take a colour c from v's
+// list if c is in L(u) too, i.e. u and v meet in the bucket of c.  So the
+// fate of v's slot k (colour c = L(v)[k]) is decided inside bucket c alone:
+//   blocked  -- an earlier relation-neighbour in bucket c took c;
+//   free     -- every earlier relation-neighbour in bucket c is known not to
+//               take c.
+// v takes the colour of its first free slot once all smaller slots are
+// blocked, and fails when every slot is blocked.  Buckets are sorted by
+// priority, so "earlier" is the lower triangle of the bucket's relation
+// matrix.  This is Jones-Plassmann with decisions made per list slot: a
+// vertex need not wait for earlier neighbours that cannot affect its
+// choice, which cuts the number of rounds from the longest monotone path of
+// the conflict graph to a few tens, and the result is the sequential one.
 //
-// Each vertex keeps a cursor into its CSR row: earlier neighbours already
-// seen decided are never re-read, their colours accumulated into a bit
-// mask over the vertex's list slots.
+// Each round is one kernel over the unfinished buckets; a wave resolves its
+// bucket's members in repeated passes until nothing changes, publishing
+// blocked/free slots and colours in per-vertex words that other buckets read.
 #include "common.h"
 
 namespace picasso {
 namespace {
 
-__device__ __forceinline__ bool earlier(uint64_t pj, int64_t j, uint64_t pi, int64_t i)
-{
-    return pj < pi || (pj == pi && j < i);
-}
+constexpr int kWave = 64;
+constexpr uint8_t ST_UNKNOWN = 0, ST_TAKEN = 1, ST_NOT = 2;
 
-__device__ __forceinline__ int32_t load_col(const int32_t *p)
+__device__ __forceinline__ int32_t load_i32(const int32_t *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void color_init_kernel(ColorArgs a)
+__device__ __forceinline__ uint64_t load_u64(const uint64_t *p)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.m; i += (int64_t)gridDim.x * blockDim.x) {
-        a.col[i] = COL_UNDECIDED;
-        a.cursor[i] = a.rowptr[i];
-        for (int w = 0; w < a.fw; ++w) a.forbid[i * a.fw + w] = 0;
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bits [0, k) of a multi-word mask: all set / any set.
+__device__ __forceinline__ bool all_below(const uint64_t *m, int k)
+{
+    for (int w = 0; w < (k >> 6); ++w)
+        if (load_u64(&m[w]) != ~0ull) return false;
+    if (k & 63) {
+        const uint64_t need = (1ull << (k & 63)) - 1ull;
+        if ((load_u64(&m[k >> 6]) & need) != need) return false;
+    }
+    return true;
+}
+
+__device__ __forceinline__ bool any_below(const uint64_t *m, int k)
+{
+    for (int w = 0; w < (k >> 6); ++w)
+        if (load_u64(&m[w])) return true;
+    if (k & 63)
+        if (load_u64(&m[k >> 6]) & ((1ull << (k & 63)) - 1ull)) return true;
+    return false;
+}
+
+__global__ void __launch_bounds__(kWave) jp_round_kernel(JpArgs a)
+{
+    extern __shared__ uint64_t sbits[];  // taken[nw_max], unknown[nw_max]
+    uint64_t *tak = sbits;
+    uint64_t *unk = sbits + a.nw_max;
+    __shared__ int changed_any;
+    const int lane = threadIdx.x;
+    for (int64_t c = blockIdx.x; c < a.P; c += gridDim.x) {
+        if (a.done[c]) continue;
+        const int64_t base = a.bstart[c];
+        const int64_t S = a.bstart[c + 1] - base;
+        const int64_t nw = (S + 63) >> 6;
+        const uint64_t *Rm = a.R + a.rb_off[c];
+        __syncthreads();
+        for (int64_t w = lane; w < nw; w += kWave) tak[w] = unk[w] = 0ull;
+        __syncthreads();
+        for (int64_t p = lane; p < S; p += kWave) {
+            const uint8_t s = a.st[base + p];
+            if (s == ST_UNKNOWN) atomicOr((unsigned long long *)&unk[p >> 6], 1ull << (p & 63));
+            else if (s == ST_TAKEN) atomicOr((unsigned long long *)&tak[p >> 6], 1ull << (p & 63));
+        }
+        __syncthreads();
+        while (true) {
+            if (lane == 0) changed_any = 0;
+            __syncthreads();
+            int changed = 0;
+            for (int64_t p = lane; p < S; p += kWave) {
+                const uint64_t bit = 1ull << (p & 63);
+                if (!(unk[p >> 6] & bit)) continue;
+                const int64_t v = a.bmem[base + p];
+                const int k = a.bslot[base + p];
+                const int32_t cv = load_i32(&a.col[v]);
+                uint8_t ns = ST_UNKNOWN;
+                if (cv != COL_UNDECIDED) {
+                    ns = cv == (int32_t)c ? ST_TAKEN : ST_NOT;
+                } else {
+                    bool hit_tak = false, hit_unk = false;
+                    const int64_t pw = p >> 6;
+                    for (int64_t w = 0; w <= pw; ++w) {
+                        uint64_t r = Rm[p * nw + w];
+                        if (w == pw) r &= bit - 1ull;  // earlier members only
+                        hit_tak |= (r & tak[w]) != 0ull;
+                        hit_unk |= (r & unk[w]) != 0ull;
+                    }
+                    uint64_t *blk = a.blk + v * a.fw;
+                    uint64_t *fre = a.fre + v * a.fw;
+                    if (hit_tak) {
+                        ns = ST_NOT;
+                        atomicOr((unsigned long long *)&blk[k >> 6], 1ull << (k & 63));
+                        if (atomicAdd(&a.nblk[v], 1) == a.T - 1) {  // the last slot was blocked
+                            __hip_atomic_store(&a.col[v], COL_FAILED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            atomicAdd(a.progress, 1ull);
+                        }
+                    } else if (any_below(fre, k)) {
+                        ns = ST_NOT;  // an earlier slot is free: v takes that colour or an earlier one
+                    } else if (!hit_unk) {
+                        atomicOr((unsigned long long *)&fre[k >> 6], 1ull << (k & 63));
+                        if (all_below(blk, k)) {
+                            __hip_atomic_store(&a.col[v], (int32_t)c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            atomicAdd(a.progress, 1ull);
+                            ns = ST_TAKEN;
+                        }
+                    }
+                }
+                if (ns != ST_UNKNOWN) {
+                    a.st[base + p] = ns;
+                    atomicAnd((unsigned long long *)&unk[p >> 6], ~bit);
+                    if (ns == ST_TAKEN) atomicOr((unsigned long long *)&tak[p >> 6], bit);
+                    changed = 1;
+                }
+            }
+            if (changed) changed_any = 1;
+            __syncthreads();
+            if (!changed_any) break;
+            __syncthreads();
+        }
+        int left = 0;
+        for (int64_t w = lane; w < nw; w += kWave) left |= unk[w] != 0ull;
+        if (!__any(left) && lane == 0) a.done[c] = 1;
     }
 }
 
-__global__ void color_round_kernel(ColorArgs a)
+// Relation bits of a bucket from a given symmetric CSR: for every edge
+// {u, v} and every colour c in L(u) and L(v), set the pair's bits in bucket
+// c (members located through pos_of[(vertex, slot)]).
+__global__ void csr_to_relation_kernel(int64_t m, const int64_t *rowptr, const int32_t *adj, const uint32_t *lists,
+                                       int32_t T, const int64_t *pos_of, const int64_t *bstart, const int64_t *rb_off,
+                                       uint64_t *R)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.m; i += (int64_t)gridDim.x * blockDim.x) {
-        if (load_col(&a.col[i]) != COL_UNDECIDED) continue;
-        const uint64_t pi = a.prio[i];
-        const uint32_t *Li = a.lists + i * a.T;
-        const int64_t end = a.rowptr[i + 1];
-        int64_t e = a.cursor[i];
-        for (; e < end; ++e) {
-            const int64_t j = a.adj[e];
-            if (!earlier(a.prio[j], j, pi, i)) continue;
-            const int32_t cj = load_col(&a.col[j]);
-            if (cj == COL_UNDECIDED) break;
-            if (cj < 0) continue;  // failed neighbour holds no colour
-            int lo = 0, hi = a.T;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (Li[mid] < (uint32_t)cj) lo = mid + 1;
-                else hi = mid;
-            }
-            if (lo < a.T && Li[lo] == (uint32_t)cj) a.forbid[i * a.fw + (lo >> 6)] |= 1ull << (lo & 63);
-        }
-        a.cursor[i] = e;
-        if (e < end) continue;
-        int32_t pick = COL_FAILED;
-        for (int w = 0; w < a.fw; ++w) {
-            const uint64_t freebits = ~a.forbid[i * a.fw + w];
-            if (freebits) {
-                const int slot = w * 64 + __builtin_ctzll(freebits);
-                if (slot < a.T) pick = (int32_t)Li[slot];
-                break;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < m; u += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t *Lu = lists + u * T;
+        for (int64_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
+            const int64_t v = adj[e];
+            if (v == u) continue;
+            const uint32_t *Lv = lists + v * T;
+            int x = 0, y = 0;
+            while (x < T && y < T) {
+                if (Lu[x] == Lv[y]) {
+                    const uint32_t c = Lu[x];
+                    const int64_t S = bstart[c + 1] - bstart[c];
+                    const int64_t nw = (S + 63) >> 6;
+                    const int64_t pu = pos_of[u * T + x] - bstart[c];
+                    const int64_t pv = pos_of[v * T + y] - bstart[c];
+                    atomicOr((unsigned long long *)&R[rb_off[c] + pu * nw + (pv >> 6)], 1ull << (pv & 63));
+                    ++x;
+                    ++y;
+                } else if (Lu[x] < Lv[y]) {
+                    ++x;
+                } else {
+                    ++y;
+                }
             }
         }
-        __hip_atomic_store(&a.col[i], pick, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        atomicAdd(a.progress, 1ull);
     }
 }
 
@@ -81,7 +182,7 @@ __global__ void finish_kernel(int64_t m, const int32_t *col, const int32_t *ids,
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t c = col[i];
         if (c >= 0) {
-            out_colors[ids[i]] = (int32_t)(offset + c);
+            if (out_colors) out_colors[ids[i]] = (int32_t)(offset + c);
             const uint32_t bit = 1u << (c & 31);
             if (!(atomicOr(&used_bits[c >> 5], bit) & bit)) atomicAdd(n_used, 1ull);
             uncol_flag[i] = 0;
@@ -98,27 +199,30 @@ __global__ void compact_kernel(int64_t m, const int32_t *ids, const int32_t *fla
         if (flag[i]) next_ids[pos[i]] = ids[i];
 }
 
-unsigned grid_for(int64_t work, int threads)
+unsigned grid_for(int64_t work, int threads, int64_t cap = 65535 * 16)
 {
     int64_t b = (work + threads - 1) / threads;
     if (b < 1) b = 1;
-    if (b > 65535 * 16) b = 65535 * 16;
+    if (b > cap) b = cap;
     return (unsigned)b;
 }
 
 }  // namespace
 
-void launch_color_init(const ColorArgs &a, hipStream_t st)
+void launch_jp_round(const JpArgs &a, hipStream_t st)
 {
-    if (a.m <= 0) return;
-    color_init_kernel<<<grid_for(a.m, 256), 256, 0, st>>>(a);
+    if (a.P <= 0) return;
+    const size_t lds = (size_t)2 * a.nw_max * sizeof(uint64_t);
+    jp_round_kernel<<<grid_for(a.P, 1, 1 << 20), kWave, lds, st>>>(a);
     PCHECK_LAUNCH();
 }
 
-void launch_color_round(const ColorArgs &a, hipStream_t st)
+void launch_csr_to_relation(int64_t m, const int64_t *rowptr, const int32_t *adj, const uint32_t *lists, int32_t T,
+                            const int64_t *pos_of, const int64_t *bstart, const int64_t *rb_off, uint64_t *R,
+                            hipStream_t st)
 {
-    if (a.m <= 0) return;
-    color_round_kernel<<<grid_for(a.m, 256), 256, 0, st>>>(a);
+    if (m <= 0) return;
+    csr_to_relation_kernel<<<grid_for(m, 256), 256, 0, st>>>(m, rowptr, adj, lists, T, pos_of, bstart, rb_off, R);
     PCHECK_LAUNCH();
 }
 

@@ -89,50 +89,92 @@ void launch_bucket_scatter(const uint32_t *lists, int64_t m, int32_t T, const in
 void launch_check_padding(const uint64_t *x, const uint64_t *z, int64_t n, int32_t q, int32_t *bad,
                           hipStream_t st);
 
-// pairs.hip: the intra-bucket pair kernels.
-struct PairArgs {
-    const int64_t *bstart;  // [P+1]
-    const uint32_t *bmem;   // local vertex index of each bucket entry
-    const uint8_t *bslot;   // slot of the bucket colour in that vertex's list
-    int64_t P;
-    const int32_t *ids;     // local -> original id
-    const uint64_t *x, *z;  // all n strings, n x W
-    int32_t W;
-    const uint32_t *lists;  // m x T, rows sorted
-    int32_t T;
-    int32_t relation;
-    int64_t m;
-    // count pass
-    int32_t *deg;
-    // fill pass
-    const int64_t *rowptr;
-    int32_t *cursor;
-    int32_t *adj;
-};
-void launch_pair_count(const PairArgs &a, hipStream_t st);
-void launch_pair_fill(const PairArgs &a, hipStream_t st);
-
-// color.hip
-struct ColorArgs {
-    int64_t m;
-    const int64_t *rowptr;
-    const int32_t *adj;
-    const uint64_t *prio;
-    const uint32_t *lists;
-    int32_t T;
-    int32_t *col;       // local palette colour, -1 failed, -2 undecided
-    int64_t *cursor;    // per-vertex resume position in its row
-    uint64_t *forbid;   // m x FW words, bit k = slot k taken by an earlier neighbour
-    int32_t fw;         // words per forbid mask = ceil(T/64)
-    unsigned long long *progress;  // count of decided vertices
-};
-void launch_color_init(const ColorArgs &a, hipStream_t st);
-void launch_color_round(const ColorArgs &a, hipStream_t st);
-void launch_finish_iteration(int64_t m, const int32_t *col, const int32_t *ids, int64_t offset, int32_t *out_colors,
-                             uint32_t *used_bits, unsigned long long *n_used, int32_t *uncol_flag, hipStream_t st);
+// lists.hip: bucket order.  Sorts each bucket's members by (priority,
+// local index); pos_of[v*T + k] receives the bucket position of (v, k).
+void launch_bucket_sort(const int64_t *bstart, int64_t P, uint32_t *bmem, uint8_t *bslot, const uint64_t *prio,
+                        int64_t *pos_of, int32_t T, bool has_large, uint32_t *tmp_mem, uint8_t *tmp_slot,
+                        hipStream_t st);
+// Sum of C(|B_c|, 2) into pairs[0], largest |B_c| into pairs[1].
 void launch_bucket_pairs(const uint32_t *bcnt, int64_t P, unsigned long long *pairs, hipStream_t st);
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
 void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
+void launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t st);
+void launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t st);
+// Per-bucket words: tiles[c] = ceil(S/64) row tiles, words[c] = S*ceil(S/64).
+void launch_bucket_shapes(const int64_t *bstart, int64_t P, int64_t *tiles, int64_t *words, hipStream_t st);
+void exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, bool with_total, void *tmp, hipStream_t st);
+
+// pairs.hip: the intra-bucket pair kernels.
+struct RelateArgs {
+    const int64_t *bstart;    // [P+1]
+    const uint32_t *bmem;     // local vertex of each bucket entry (priority order)
+    int64_t P;
+    const int64_t *tile_off;  // [P+1] exclusive scan of ceil(S_c/64)
+    int64_t total_row_tiles;
+    const int64_t *rb_off;    // [P+1] word offset of each bucket's bit matrix
+    const int32_t *ids;       // local -> original id
+    const uint64_t *x, *z;    // all n strings, n x W
+    int32_t W;
+    int32_t relation;
+    uint64_t *R;              // relation bit matrices
+};
+void launch_relate(const RelateArgs &a, hipStream_t st);
+
+struct DupArgs {
+    const int64_t *bstart;
+    const uint32_t *bmem;
+    const uint8_t *bslot;
+    int64_t P;
+    const int64_t *rb_off;
+    const uint32_t *lists;  // m x T, rows sorted
+    int32_t T;
+    uint64_t *D;            // pairs sharing a smaller colour (zeroed by the caller)
+    uint32_t *slow;         // buckets left to the exact per-pair check
+    int32_t *n_slow;
+};
+void launch_dup(const DupArgs &a, hipStream_t st);
+void launch_dup_slow(const DupArgs &a, int64_t n_slow, hipStream_t st);
+
+struct CsrArgs {
+    const int64_t *bstart;
+    const uint32_t *bmem;
+    const uint8_t *bslot;
+    int64_t P;
+    const int64_t *rb_off;
+    const uint64_t *R, *D;
+    int32_t T;
+    int32_t *slot_cnt;       // count pass: m*T edge counts per (vertex, slot)
+    const int64_t *slot_off; // fill pass: exclusive scan of slot_cnt
+    int32_t *adj;            // fill pass: CSR column indices
+};
+void launch_count(const CsrArgs &a, hipStream_t st);
+void launch_fill(const CsrArgs &a, hipStream_t st);
+void launch_rowptr(const int64_t *slot_off, int64_t m, int32_t T, int64_t *rowptr, hipStream_t st);
+
+// color.hip
+struct JpArgs {
+    int64_t P;
+    const int64_t *bstart;
+    const uint32_t *bmem;
+    const uint8_t *bslot;
+    const int64_t *rb_off;
+    const uint64_t *R;
+    int64_t nw_max;       // words per row of the largest bucket
+    int32_t T;
+    int32_t fw;           // words per slot mask = ceil(T/64)
+    int32_t *col;         // local palette colour, -1 failed, -2 undecided
+    uint64_t *blk, *fre;  // m x fw: slots known blocked / known free
+    int32_t *nblk;        // blocked-slot count per vertex
+    uint8_t *st;          // per bucket entry: unknown / taken / not taken
+    uint8_t *done;        // per bucket: every member resolved
+    unsigned long long *progress;  // decided vertices
+};
+void launch_jp_round(const JpArgs &a, hipStream_t st);
+void launch_csr_to_relation(int64_t m, const int64_t *rowptr, const int32_t *adj, const uint32_t *lists, int32_t T,
+                            const int64_t *pos_of, const int64_t *bstart, const int64_t *rb_off, uint64_t *R,
+                            hipStream_t st);
+void launch_finish_iteration(int64_t m, const int32_t *col, const int32_t *ids, int64_t offset, int32_t *out_colors,
+                             uint32_t *used_bits, unsigned long long *n_used, int32_t *uncol_flag, hipStream_t st);
 void launch_compact_ids(int64_t m, const int32_t *ids, const int32_t *flag, const int64_t *pos, int32_t *next_ids,
                         hipStream_t st);
 

@@ -92,13 +92,154 @@ __global__ void check_padding_kernel(const uint64_t *x, const uint64_t *z, int64
 
 __global__ void bucket_pairs_kernel(const uint32_t *__restrict__ bcnt, int64_t P, unsigned long long *pairs)
 {
-    unsigned long long s = 0;
+    unsigned long long s = 0, mx = 0;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < P; c += (int64_t)gridDim.x * blockDim.x) {
         const unsigned long long k = bcnt[c];
         s += k * (k - (k > 0)) / 2;
+        mx = k > mx ? k : mx;
     }
-    for (int d = 32; d > 0; d >>= 1) s += __shfl_down(s, d, 64);
-    if ((threadIdx.x & 63) == 0 && s) atomicAdd(pairs, s);
+    for (int d = 32; d > 0; d >>= 1) {
+        s += __shfl_down(s, d, 64);
+        const unsigned long long o = __shfl_down(mx, d, 64);
+        mx = o > mx ? o : mx;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (s) atomicAdd(&pairs[0], s);
+        atomicMax(&pairs[1], mx);
+    }
+}
+
+// ---- bucket order ----------------------------------------------------------
+// Members of a bucket sorted by (priority, local index): the order in which
+// the sequential colouring visits them.  Buckets up to kSortCap members are
+// sorted in LDS by a bitonic network; larger ones rank each member by
+// counting the members before it.
+constexpr int kSortThreads = 256;
+constexpr int kSortCap = 2048;
+
+__device__ __forceinline__ bool key_less(uint64_t pa, uint32_t va, uint64_t pb, uint32_t vb)
+{
+    return pa < pb || (pa == pb && va < vb);
+}
+
+__global__ void __launch_bounds__(kSortThreads) bucket_sort_kernel(const int64_t *__restrict__ bstart, int64_t P,
+                                                                   uint32_t *__restrict__ bmem,
+                                                                   uint8_t *__restrict__ bslot,
+                                                                   const uint64_t *__restrict__ prio,
+                                                                   int64_t *__restrict__ pos_of, int32_t T)
+{
+    __shared__ uint64_t key[kSortCap];
+    __shared__ uint32_t vid[kSortCap];
+    __shared__ uint8_t sl[kSortCap];
+    const int t = threadIdx.x;
+    for (int64_t c = blockIdx.x; c < P; c += gridDim.x) {
+        const int64_t base = bstart[c];
+        const int64_t S = bstart[c + 1] - base;
+        if (S > kSortCap) continue;
+        if (S == 1 && t == 0) pos_of[(int64_t)bmem[base] * T + bslot[base]] = base;
+        if (S < 2) continue;
+        int N = 2;
+        while (N < S) N <<= 1;
+        __syncthreads();
+        for (int e = t; e < N; e += kSortThreads) {
+            if (e < S) {
+                const uint32_t v = bmem[base + e];
+                key[e] = prio[v];
+                vid[e] = v;
+                sl[e] = bslot[base + e];
+            } else {
+                key[e] = ~0ull;
+                vid[e] = 0xFFFFFFFFu;
+                sl[e] = 0;
+            }
+        }
+        __syncthreads();
+        for (int k = 2; k <= N; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int e = t; e < N; e += kSortThreads) {
+                    const int f = e ^ j;
+                    if (f > e) {
+                        const bool up = (e & k) == 0;
+                        const bool gt = key_less(key[f], vid[f], key[e], vid[e]);
+                        if (gt == up) {
+                            const uint64_t tk = key[e];
+                            key[e] = key[f];
+                            key[f] = tk;
+                            const uint32_t tv = vid[e];
+                            vid[e] = vid[f];
+                            vid[f] = tv;
+                            const uint8_t ts = sl[e];
+                            sl[e] = sl[f];
+                            sl[f] = ts;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int e = t; e < S; e += kSortThreads) {
+            bmem[base + e] = vid[e];
+            bslot[base + e] = sl[e];
+            pos_of[(int64_t)vid[e] * T + sl[e]] = base + e;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kSortThreads) bucket_rank_kernel(const int64_t *__restrict__ bstart, int64_t P,
+                                                                   const uint32_t *__restrict__ bmem,
+                                                                   const uint8_t *__restrict__ bslot,
+                                                                   const uint64_t *__restrict__ prio,
+                                                                   uint32_t *__restrict__ out_mem,
+                                                                   uint8_t *__restrict__ out_slot)
+{
+    for (int64_t c = blockIdx.x; c < P; c += gridDim.x) {
+        const int64_t base = bstart[c];
+        const int64_t S = bstart[c + 1] - base;
+        if (S <= kSortCap) continue;
+        for (int64_t p = threadIdx.x; p < S; p += blockDim.x) {
+            const uint32_t vp = bmem[base + p];
+            const uint64_t kp = prio[vp];
+            int64_t rank = 0;
+            for (int64_t q = 0; q < S; ++q) {
+                const uint32_t vq = bmem[base + q];
+                rank += key_less(prio[vq], vq, kp, vp);
+            }
+            out_mem[base + rank] = vp;
+            out_slot[base + rank] = bslot[base + p];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kSortThreads) bucket_rank_copy_kernel(const int64_t *__restrict__ bstart, int64_t P,
+                                                                        uint32_t *__restrict__ bmem,
+                                                                        uint8_t *__restrict__ bslot,
+                                                                        const uint32_t *__restrict__ tmp_mem,
+                                                                        const uint8_t *__restrict__ tmp_slot,
+                                                                        int64_t *__restrict__ pos_of, int32_t T)
+{
+    for (int64_t c = blockIdx.x; c < P; c += gridDim.x) {
+        const int64_t base = bstart[c];
+        const int64_t S = bstart[c + 1] - base;
+        if (S <= kSortCap) continue;
+        for (int64_t p = threadIdx.x; p < S; p += blockDim.x) {
+            const uint32_t v = tmp_mem[base + p];
+            const uint8_t k = tmp_slot[base + p];
+            bmem[base + p] = v;
+            bslot[base + p] = k;
+            pos_of[(int64_t)v * T + k] = base + p;
+        }
+    }
+}
+
+__global__ void bucket_shapes_kernel(const int64_t *__restrict__ bstart, int64_t P, int64_t *__restrict__ tiles,
+                                     int64_t *__restrict__ words)
+{
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < P; c += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t S = bstart[c + 1] - bstart[c];
+        const int64_t nw = (S + 63) >> 6;
+        tiles[c] = nw;
+        words[c] = S * nw;
+    }
 }
 
 template <typename V>
@@ -169,6 +310,43 @@ void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st)
 {
     if (n <= 0) return;
     fill_kernel<uint32_t><<<grid_for(n, 256), 256, 0, st>>>(p, n, v);
+    PCHECK_LAUNCH();
+}
+
+void launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t st)
+{
+    if (n <= 0) return;
+    fill_kernel<uint64_t><<<grid_for(n, 256), 256, 0, st>>>(p, n, v);
+    PCHECK_LAUNCH();
+}
+
+void launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t st)
+{
+    if (n <= 0) return;
+    fill_kernel<uint8_t><<<grid_for(n, 256), 256, 0, st>>>(p, n, v);
+    PCHECK_LAUNCH();
+}
+
+void launch_bucket_sort(const int64_t *bstart, int64_t P, uint32_t *bmem, uint8_t *bslot, const uint64_t *prio,
+                        int64_t *pos_of, int32_t T, bool has_large, uint32_t *tmp_mem, uint8_t *tmp_slot,
+                        hipStream_t st)
+{
+    if (P <= 0) return;
+    const unsigned grid = (unsigned)(P < (1 << 20) ? P : (1 << 20));
+    bucket_sort_kernel<<<grid, kSortThreads, 0, st>>>(bstart, P, bmem, bslot, prio, pos_of, T);
+    PCHECK_LAUNCH();
+    if (has_large) {
+        bucket_rank_kernel<<<grid, kSortThreads, 0, st>>>(bstart, P, bmem, bslot, prio, tmp_mem, tmp_slot);
+        PCHECK_LAUNCH();
+        bucket_rank_copy_kernel<<<grid, kSortThreads, 0, st>>>(bstart, P, bmem, bslot, tmp_mem, tmp_slot, pos_of, T);
+        PCHECK_LAUNCH();
+    }
+}
+
+void launch_bucket_shapes(const int64_t *bstart, int64_t P, int64_t *tiles, int64_t *words, hipStream_t st)
+{
+    if (P <= 0) return;
+    bucket_shapes_kernel<<<grid_for(P, 256), 256, 0, st>>>(bstart, P, tiles, words);
     PCHECK_LAUNCH();
 }
 

@@ -84,11 +84,16 @@ __global__ void __launch_bounds__(kThreads) tile_scan(const In *in, int64_t n, c
 
 int64_t tiles(int64_t n) { return (n + kTile - 1) / kTile; }
 
+__global__ void zero_one(int64_t *p) { *p = 0; }
+
 template <typename In>
 void scan_impl(const In *in, int64_t *out, int64_t n, bool with_total, char *tmp, hipStream_t st)
 {
     if (n <= 0) {
-        if (with_total) PCHECK_HIP(hipMemsetAsync(out, 0, sizeof(int64_t), st));
+        if (with_total) {
+            zero_one<<<1, 1, 0, st>>>(out);
+            PCHECK_LAUNCH();
+        }
         return;
     }
     const int64_t nb = tiles(n);
@@ -129,6 +134,11 @@ void exclusive_scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, bool 
                                hipStream_t st)
 {
     scan_impl<int32_t>(in, out, n, with_total, static_cast<char *>(tmp), st);
+}
+
+void exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, bool with_total, void *tmp, hipStream_t st)
+{
+    scan_impl<int64_t>(in, out, n, with_total, static_cast<char *>(tmp), st);
 }
 
 }  // namespace picasso
