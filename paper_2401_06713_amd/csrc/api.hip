@@ -74,8 +74,8 @@ struct picasso_ctx {
     DevBuf x, z;
     // iteration buffers
     DevBuf ids, next_ids, lists, prio, bcnt, bstart, bmem, bslot, pos_of, tmp_mem, tmp_slot, tiles, words, tile_off,
-        rb_off, R, D, nslow, slow, slot_cnt, slot_off, rowptr, adj, col, blk, fre, nblk, st, done, flags, pos, used,
-        scan_tmp, scalars, out_colors;
+        rb_off, R, D, bx, bz, tile_bucket, nslow, slow, slot_cnt, slot_off, rowptr, adj, col, blk, fre, nblk, st, dirty, wl, flags, pos,
+        used, scan_tmp, scalars, out_colors;
     picasso_stats stats;
 };
 
@@ -224,6 +224,9 @@ int64_t build_conflict_graph(picasso_ctx *h, int64_t m, int64_t P, int32_t T, in
     ra.W = h->W;
     ra.relation = rel;
     ra.R = R;
+    launch_relate_prep(ra, m * T, buf<uint64_t>(h, h->bx, (size_t)m * T * h->W),
+                       buf<uint64_t>(h, h->bz, (size_t)m * T * h->W),
+                       buf<int32_t>(h, h->tile_bucket, (size_t)std::max<int64_t>(bi.row_tiles, 1)), st);
     tm.mark();
     launch_relate(ra, st);
     tm.mark();
@@ -239,6 +242,7 @@ int64_t build_conflict_graph(picasso_ctx *h, int64_t m, int64_t P, int32_t T, in
     da.rb_off = ra.rb_off;
     da.lists = static_cast<const uint32_t *>(h->lists.p);
     da.T = T;
+    da.R = R;
     da.D = D;
     da.slow = buf<uint32_t>(h, h->slow, (size_t)P);
     da.n_slow = nslow;
@@ -280,7 +284,7 @@ int64_t build_conflict_graph(picasso_ctx *h, int64_t m, int64_t P, int32_t T, in
     return total / 2;
 }
 
-// List colouring rounds until every vertex is decided.  Result in h->col.
+// List colouring until every vertex is decided.  Result in h->col.
 int32_t color_buckets(picasso_ctx *h, int64_t m, int64_t P, int32_t T, const BucketInfo &bi)
 {
     hipStream_t st = h->stream;
@@ -291,6 +295,8 @@ int32_t color_buckets(picasso_ctx *h, int64_t m, int64_t P, int32_t T, const Buc
     j.bslot = static_cast<const uint8_t *>(h->bslot.p);
     j.rb_off = static_cast<const int64_t *>(h->rb_off.p);
     j.R = static_cast<const uint64_t *>(h->R.p);
+    j.lists = static_cast<const uint32_t *>(h->lists.p);
+    j.pos_of = static_cast<const int64_t *>(h->pos_of.p);
     j.nw_max = std::max<int64_t>((bi.max_size + 63) / 64, 1);
     j.T = T;
     j.fw = (T + 63) / 64;
@@ -299,28 +305,55 @@ int32_t color_buckets(picasso_ctx *h, int64_t m, int64_t P, int32_t T, const Buc
     j.fre = buf<uint64_t>(h, h->fre, (size_t)m * j.fw);
     j.nblk = buf<int32_t>(h, h->nblk, (size_t)m);
     j.st = buf<uint8_t>(h, h->st, (size_t)m * T);
-    j.done = buf<uint8_t>(h, h->done, (size_t)P);
+    j.dirty = buf<uint32_t>(h, h->dirty, (size_t)P);
+    int32_t *wl = buf<int32_t>(h, h->wl, (size_t)2 * P + 2);
+    j.wl[0] = wl;
+    j.wl[1] = wl + P;
+    j.wl_count = wl + 2 * P;
     unsigned long long *sc = buf<unsigned long long>(h, h->scalars, 8);
     j.progress = sc + 2;
+    j.m = m;
     launch_fill_i32(j.col, m, COL_UNDECIDED, st);
     launch_fill_u64(j.blk, m * j.fw, 0ull, st);
     launch_fill_u64(j.fre, m * j.fw, 0ull, st);
     launch_fill_i32(j.nblk, m, 0, st);
     launch_fill_u8(j.st, m * T, 0, st);
-    launch_fill_u8(j.done, P, 0, st);
     launch_fill_u64(reinterpret_cast<uint64_t *>(j.progress), 1, 0ull, st);
+    launch_jp_all(j, st);
     int32_t rounds = 0;
-    int batch = 1;
+    int cur = 0, batch = 2;
+    unsigned long long at_restart = 0;
+    bool fresh = true;  // the lists hold every bucket
     while (true) {
-        for (int r = 0; r < batch; ++r) launch_jp_round(j, st);
+        for (int r = 0; r < batch; ++r) {
+            launch_jp_round(j, cur, st);
+            cur ^= 1;
+        }
         rounds += batch;
-        const unsigned long long done = read_scalar(h, j.progress);
-        if ((int64_t)done >= m) break;
-        // every round decides at least the first undecided vertex of the order
-        if (rounds > 2 * m + 64) throw Error(PICASSO_EINTERNAL, "list colouring made no progress");
-        if (batch < 8) batch *= 2;
+        struct {
+            unsigned long long done;
+        } hs;
+        int32_t pending = 0;
+        PCHECK_HIP(hipMemcpyAsync(&hs.done, j.progress, sizeof(hs.done), hipMemcpyDeviceToHost, st));
+        PCHECK_HIP(hipMemcpyAsync(&pending, &j.wl_count[cur], sizeof(pending), hipMemcpyDeviceToHost, st));
+        PCHECK_HIP(hipStreamSynchronize(st));
+        if ((int64_t)hs.done >= m) break;
+        if (pending == 0) {
+            // Nothing left on the worklist but vertices remain: start again
+            // from every bucket.  Rounds that start from every bucket decide
+            // at least the first undecided vertex of the order.
+            if (fresh && hs.done == at_restart) throw Error(PICASSO_EINTERNAL, "list colouring made no progress");
+            at_restart = hs.done;
+            launch_jp_all(j, st);
+            cur = 0;
+            fresh = true;
+        } else {
+            fresh = false;
+        }
+        if (batch < 16) batch *= 2;
     }
-    return rounds;
+    const int32_t launches = rounds;
+    return launches;
 }
 
 void upload(picasso_ctx *h, void *dst, const void *src, size_t bytes)
@@ -539,7 +572,8 @@ void picasso_destroy(picasso_handle h)
                      &h->bstart,  &h->bmem,     &h->bslot,   &h->pos_of,   &h->tmp_mem, &h->tmp_slot, &h->tiles,
                      &h->words,   &h->tile_off, &h->rb_off,  &h->R,        &h->D,       &h->nslow,    &h->slow,
                      &h->slot_cnt, &h->slot_off, &h->rowptr, &h->adj,      &h->col,     &h->blk,      &h->fre,
-                     &h->nblk,    &h->st,       &h->done,    &h->flags,    &h->pos,     &h->used,     &h->scan_tmp,
+                     &h->nblk,    &h->st,       &h->dirty,   &h->wl,       &h->flags,   &h->pos,      &h->used,
+                     &h->scan_tmp, &h->bx,      &h->bz,      &h->tile_bucket,
                      &h->scalars, &h->out_colors};
     for (DevBuf *b : all) h->arena.release(*b);
     if (h->own_stream) (void)hipStreamDestroy(h->own_stream);

@@ -17,10 +17,14 @@
 // choice, which cuts the number of rounds from the longest monotone path of
 // the conflict graph to a few tens, and the result is the sequential one.
 //
-// Each round is one kernel over the unfinished buckets; a wave resolves its
-// bucket's members in repeated passes until nothing changes, publishing
-// blocked/free slots and colours in per-vertex words that other buckets read.
+// A wave resolves its bucket's members in repeated passes until nothing
+// changes, publishing blocked/free slots and colours in per-vertex words that
+// other buckets read.  Rounds visit only the buckets that a state change may
+// have unblocked (a worklist).
+#include <algorithm>
+
 #include "common.h"
+
 
 namespace picasso {
 namespace {
@@ -59,85 +63,158 @@ __device__ __forceinline__ bool any_below(const uint64_t *m, int k)
     return false;
 }
 
-__global__ void __launch_bounds__(kWave) jp_round_kernel(JpArgs a)
+__device__ __forceinline__ uint8_t load_st(const uint8_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Put bucket c2 on the next round's worklist unless it is already waiting.
+__device__ __forceinline__ void wake(const JpArgs &a, int64_t c2, int32_t *out, int32_t *out_count)
+{
+    if (__hip_atomic_exchange(&a.dirty[c2], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+        out[atomicAdd(out_count, 1)] = (int32_t)c2;
+}
+
+// Wake the buckets of v's still-unresolved slots in [from, T) other than skip.
+__device__ void wake_open_slots(const JpArgs &a, int64_t v, int from, int skip, int32_t *out, int32_t *out_count)
+{
+    for (int k2 = from; k2 < a.T; ++k2) {
+        if (k2 == skip) continue;
+        if (load_st(&a.st[a.pos_of[v * a.T + k2]]) == ST_UNKNOWN) wake(a, a.lists[v * a.T + k2], out, out_count);
+    }
+}
+
+// First slot of v not known blocked (T if all are).
+__device__ __forceinline__ int first_open(const uint64_t *blk, int T)
+{
+    for (int w = 0; w * 64 < T; ++w) {
+        const uint64_t free_bits = ~load_u64(&blk[w]);
+        if (free_bits) {
+            const int k = w * 64 + __builtin_ctzll(free_bits);
+            return k < T ? k : T;
+        }
+    }
+    return T;
+}
+
+// Resolve what can be resolved in bucket c (passes until nothing changes);
+// state changes that may unblock other buckets wake them.
+__device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t *tak, uint64_t *unk, int *changed_any,
+                               int32_t *out, int32_t *out_count)
+{
+    const int lane = threadIdx.x;
+    const int64_t base = a.bstart[c];
+    const int64_t S = a.bstart[c + 1] - base;
+    const int64_t nw = (S + 63) >> 6;
+    const uint64_t *Rm = a.R + a.rb_off[c];
+    __syncthreads();
+    for (int64_t w = lane; w < nw; w += kWave) tak[w] = unk[w] = 0ull;
+    __syncthreads();
+    for (int64_t p = lane; p < S; p += kWave) {
+        const uint8_t s = a.st[base + p];
+        if (s == ST_UNKNOWN) atomicOr((unsigned long long *)&unk[p >> 6], 1ull << (p & 63));
+        else if (s == ST_TAKEN) atomicOr((unsigned long long *)&tak[p >> 6], 1ull << (p & 63));
+    }
+    while (true) {
+        if (lane == 0) *changed_any = 0;
+        __syncthreads();
+        int changed = 0;
+        for (int64_t p = lane; p < S; p += kWave) {
+            const uint64_t bit = 1ull << (p & 63);
+            if (!(unk[p >> 6] & bit)) continue;
+            const int64_t v = a.bmem[base + p];
+            const int k = a.bslot[base + p];
+            const int32_t cv = load_i32(&a.col[v]);
+            uint8_t ns = ST_UNKNOWN;
+            if (cv != COL_UNDECIDED) {
+                ns = cv == (int32_t)c ? ST_TAKEN : ST_NOT;
+            } else {
+                bool hit_tak = false, hit_unk = false;
+                const int64_t pw = p >> 6;
+                for (int64_t w = 0; w <= pw; ++w) {
+                    uint64_t r = Rm[p * nw + w];
+                    if (w == pw) r &= bit - 1ull;  // earlier members only
+                    hit_tak |= (r & tak[w]) != 0ull;
+                    hit_unk |= (r & unk[w]) != 0ull;
+                }
+                uint64_t *blk = a.blk + v * a.fw;
+                uint64_t *fre = a.fre + v * a.fw;
+                if (hit_tak) {
+                    ns = ST_NOT;
+                    atomicOr((unsigned long long *)&blk[k >> 6], 1ull << (k & 63));
+                    if (atomicAdd(&a.nblk[v], 1) == a.T - 1) {  // the last slot was blocked
+                        __hip_atomic_store(&a.col[v], COL_FAILED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        atomicAdd(a.progress, 1ull);
+                    } else {
+                        // the blocked prefix may now reach a free slot
+                        const int f = first_open(blk, a.T);
+                        if (f > k && f < a.T) wake(a, a.lists[v * a.T + f], out, out_count);
+                    }
+                } else if (any_below(fre, k)) {
+                    ns = ST_NOT;  // an earlier slot is free: v takes that colour or an earlier one
+                } else if (!hit_unk) {
+                    const uint64_t was = atomicOr((unsigned long long *)&fre[k >> 6], 1ull << (k & 63));
+                    if (all_below(blk, k)) {
+                        __hip_atomic_store(&a.col[v], (int32_t)c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        atomicAdd(a.progress, 1ull);
+                        ns = ST_TAKEN;
+                    }
+                    if (!(was & (1ull << (k & 63))) || ns == ST_TAKEN)
+                        wake_open_slots(a, v, ns == ST_TAKEN ? 0 : k + 1, k, out, out_count);
+                }
+            }
+            if (ns != ST_UNKNOWN) {
+                __hip_atomic_store(&a.st[base + p], ns, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (ns == ST_TAKEN) atomicOr((unsigned long long *)&tak[p >> 6], bit);
+                atomicAnd((unsigned long long *)&unk[p >> 6], ~bit);
+                changed = 1;
+            }
+        }
+        if (changed) *changed_any = 1;
+        __syncthreads();
+        const bool more = *changed_any != 0;
+        __syncthreads();
+        if (!more) break;
+    }
+}
+
+// One round of the worklist: visit the buckets listed by the previous round
+// (wl[cur], count in wl_count[cur]); state changes append the buckets they
+// may unblock to wl[cur ^ 1].  No workgroup waits on another: rounds are
+// separate launches in stream order.
+__global__ void __launch_bounds__(kWave) jp_round_kernel(JpArgs a, int cur)
 {
     extern __shared__ uint64_t sbits[];  // taken[nw_max], unknown[nw_max]
     uint64_t *tak = sbits;
     uint64_t *unk = sbits + a.nw_max;
     __shared__ int changed_any;
-    const int lane = threadIdx.x;
-    for (int64_t c = blockIdx.x; c < a.P; c += gridDim.x) {
-        if (a.done[c]) continue;
-        const int64_t base = a.bstart[c];
-        const int64_t S = a.bstart[c + 1] - base;
-        const int64_t nw = (S + 63) >> 6;
-        const uint64_t *Rm = a.R + a.rb_off[c];
+    __shared__ int go;
+    const int32_t n_in = a.wl_count[cur];
+    int32_t *out = a.wl[cur ^ 1];
+    int32_t *out_count = &a.wl_count[cur ^ 1];
+    for (int64_t i = blockIdx.x; i < n_in; i += gridDim.x) {
+        const int64_t c = a.wl[cur][i];
+        if (threadIdx.x == 0)
+            go = __hip_atomic_exchange(&a.dirty[c], 0u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) != 0u;
         __syncthreads();
-        for (int64_t w = lane; w < nw; w += kWave) tak[w] = unk[w] = 0ull;
+        if (go) resolve_bucket(a, c, tak, unk, &changed_any, out, out_count);
         __syncthreads();
-        for (int64_t p = lane; p < S; p += kWave) {
-            const uint8_t s = a.st[base + p];
-            if (s == ST_UNKNOWN) atomicOr((unsigned long long *)&unk[p >> 6], 1ull << (p & 63));
-            else if (s == ST_TAKEN) atomicOr((unsigned long long *)&tak[p >> 6], 1ull << (p & 63));
-        }
-        __syncthreads();
-        while (true) {
-            if (lane == 0) changed_any = 0;
-            __syncthreads();
-            int changed = 0;
-            for (int64_t p = lane; p < S; p += kWave) {
-                const uint64_t bit = 1ull << (p & 63);
-                if (!(unk[p >> 6] & bit)) continue;
-                const int64_t v = a.bmem[base + p];
-                const int k = a.bslot[base + p];
-                const int32_t cv = load_i32(&a.col[v]);
-                uint8_t ns = ST_UNKNOWN;
-                if (cv != COL_UNDECIDED) {
-                    ns = cv == (int32_t)c ? ST_TAKEN : ST_NOT;
-                } else {
-                    bool hit_tak = false, hit_unk = false;
-                    const int64_t pw = p >> 6;
-                    for (int64_t w = 0; w <= pw; ++w) {
-                        uint64_t r = Rm[p * nw + w];
-                        if (w == pw) r &= bit - 1ull;  // earlier members only
-                        hit_tak |= (r & tak[w]) != 0ull;
-                        hit_unk |= (r & unk[w]) != 0ull;
-                    }
-                    uint64_t *blk = a.blk + v * a.fw;
-                    uint64_t *fre = a.fre + v * a.fw;
-                    if (hit_tak) {
-                        ns = ST_NOT;
-                        atomicOr((unsigned long long *)&blk[k >> 6], 1ull << (k & 63));
-                        if (atomicAdd(&a.nblk[v], 1) == a.T - 1) {  // the last slot was blocked
-                            __hip_atomic_store(&a.col[v], COL_FAILED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            atomicAdd(a.progress, 1ull);
-                        }
-                    } else if (any_below(fre, k)) {
-                        ns = ST_NOT;  // an earlier slot is free: v takes that colour or an earlier one
-                    } else if (!hit_unk) {
-                        atomicOr((unsigned long long *)&fre[k >> 6], 1ull << (k & 63));
-                        if (all_below(blk, k)) {
-                            __hip_atomic_store(&a.col[v], (int32_t)c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            atomicAdd(a.progress, 1ull);
-                            ns = ST_TAKEN;
-                        }
-                    }
-                }
-                if (ns != ST_UNKNOWN) {
-                    a.st[base + p] = ns;
-                    atomicAnd((unsigned long long *)&unk[p >> 6], ~bit);
-                    if (ns == ST_TAKEN) atomicOr((unsigned long long *)&tak[p >> 6], bit);
-                    changed = 1;
-                }
-            }
-            if (changed) changed_any = 1;
-            __syncthreads();
-            if (!changed_any) break;
-            __syncthreads();
-        }
-        int left = 0;
-        for (int64_t w = lane; w < nw; w += kWave) left |= unk[w] != 0ull;
-        if (!__any(left) && lane == 0) a.done[c] = 1;
+    }
+}
+
+// The list a round has consumed is emptied before the next round refills it.
+__global__ void jp_reset_kernel(int32_t *count) { *count = 0; }
+
+// Worklist of every bucket (the first round, and the host's recovery round).
+__global__ void wl_all_kernel(int64_t P, int32_t *wl, uint32_t *dirty, int32_t *wl_count)
+{
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < P; c += (int64_t)gridDim.x * blockDim.x) {
+        wl[c] = (int32_t)c;
+        dirty[c] = 1u;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        wl_count[0] = (int32_t)P;
+        wl_count[1] = 0;
     }
 }
 
@@ -209,11 +286,21 @@ unsigned grid_for(int64_t work, int threads, int64_t cap = 65535 * 16)
 
 }  // namespace
 
-void launch_jp_round(const JpArgs &a, hipStream_t st)
+void launch_jp_all(const JpArgs &a, hipStream_t st)
+{
+    if (a.P <= 0) return;
+    wl_all_kernel<<<grid_for(a.P, 256), 256, 0, st>>>(a.P, a.wl[0], a.dirty, a.wl_count);
+    PCHECK_LAUNCH();
+}
+
+void launch_jp_round(const JpArgs &a, int cur, hipStream_t st)
 {
     if (a.P <= 0) return;
     const size_t lds = (size_t)2 * a.nw_max * sizeof(uint64_t);
-    jp_round_kernel<<<grid_for(a.P, 1, 1 << 20), kWave, lds, st>>>(a);
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(a.P, 16384));
+    jp_round_kernel<<<(unsigned)grid, kWave, lds, st>>>(a, cur);
+    PCHECK_LAUNCH();
+    jp_reset_kernel<<<1, 1, 0, st>>>(&a.wl_count[cur]);
     PCHECK_LAUNCH();
 }
 

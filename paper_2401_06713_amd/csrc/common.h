@@ -117,7 +117,12 @@ struct RelateArgs {
     int32_t W;
     int32_t relation;
     uint64_t *R;              // relation bit matrices
+    const uint64_t *bx, *bz;  // member strings in bucket order (set by launch_relate_prep)
+    const int32_t *tile_bucket;  // owner bucket of each row tile (set by launch_relate_prep)
 };
+// Gathers member strings into bucket order and the row-tile owners.
+void launch_relate_prep(RelateArgs &a, int64_t entries, uint64_t *bx, uint64_t *bz, int32_t *tile_bucket,
+                        hipStream_t st);
 void launch_relate(const RelateArgs &a, hipStream_t st);
 
 struct DupArgs {
@@ -128,6 +133,7 @@ struct DupArgs {
     const int64_t *rb_off;
     const uint32_t *lists;  // m x T, rows sorted
     int32_t T;
+    const uint64_t *R;      // relation matrices (the exact check visits relation pairs only)
     uint64_t *D;            // pairs sharing a smaller colour (zeroed by the caller)
     uint32_t *slow;         // buckets left to the exact per-pair check
     int32_t *n_slow;
@@ -159,17 +165,26 @@ struct JpArgs {
     const uint8_t *bslot;
     const int64_t *rb_off;
     const uint64_t *R;
-    int64_t nw_max;       // words per row of the largest bucket
+    const uint32_t *lists;  // m x T, rows sorted
+    const int64_t *pos_of;  // bucket position of (vertex, slot)
+    int64_t nw_max;         // words per row of the largest bucket
     int32_t T;
-    int32_t fw;           // words per slot mask = ceil(T/64)
-    int32_t *col;         // local palette colour, -1 failed, -2 undecided
-    uint64_t *blk, *fre;  // m x fw: slots known blocked / known free
-    int32_t *nblk;        // blocked-slot count per vertex
-    uint8_t *st;          // per bucket entry: unknown / taken / not taken
-    uint8_t *done;        // per bucket: every member resolved
+    int32_t fw;             // words per slot mask = ceil(T/64)
+    int32_t *col;           // local palette colour, -1 failed, -2 undecided
+    uint64_t *blk, *fre;    // m x fw: slots known blocked / known free
+    int32_t *nblk;          // blocked-slot count per vertex
+    uint8_t *st;            // per bucket entry: unknown / taken / not taken
+    uint32_t *dirty;        // per bucket: waiting on a worklist
+    int32_t *wl[2];         // worklists of buckets (P entries each)
+    int32_t *wl_count;      // [2]
     unsigned long long *progress;  // decided vertices
+    int64_t m;              // vertices to decide
 };
-void launch_jp_round(const JpArgs &a, hipStream_t st);
+// Every bucket onto worklist 0 (marked waiting); worklist 1 empty.
+void launch_jp_all(const JpArgs &a, hipStream_t st);
+// One worklist round reading list `cur` and filling list cur ^ 1; then list
+// `cur` is emptied.
+void launch_jp_round(const JpArgs &a, int cur, hipStream_t st);
 void launch_csr_to_relation(int64_t m, const int64_t *rowptr, const int32_t *adj, const uint32_t *lists, int32_t T,
                             const int64_t *pos_of, const int64_t *bstart, const int64_t *rb_off, uint64_t *R,
                             hipStream_t st);

@@ -27,19 +27,6 @@ namespace {
 
 constexpr int kWave = 64;
 
-// Bucket index owning work item `item`, given offsets off[0..P] (off[P] =
-// total items): the largest c with off[c] <= item.
-__device__ __forceinline__ int64_t find_bucket(const int64_t *__restrict__ off, int64_t P, int64_t item)
-{
-    int64_t lo = 0, hi = P;  // off[lo] <= item < off[hi]
-    while (hi - lo > 1) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (off[mid] <= item) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
-
 template <int W, int REL>
 __device__ __forceinline__ uint32_t pair_bit(const uint32_t (&xi)[2 * W], const uint32_t (&zi)[2 * W],
                                              const uint32_t *xj, const uint32_t *zj)
@@ -83,18 +70,52 @@ __device__ __forceinline__ uint64_t wave_transpose64(uint64_t r)
     return r;
 }
 
-// One wave per (bucket, row tile of 64 members).  Row members stay in
-// registers; each column tile (64 members, zero-padded) is staged in LDS and
-// read by broadcast.  Lane i accumulates the relation bits of row i against
-// the tile's 64 columns; a bit transpose turns the tile into the column
-// members' words, so each tile is tested once and written twice.
-template <int W, int REL>
-__global__ void __launch_bounds__(kWave) relate_kernel(RelateArgs a)
+// LDS written by lanes of this wave becomes readable by its other lanes
+// (a wave's LDS operations complete in order; this keeps the compiler from
+// moving reads above the writes).
+__device__ __forceinline__ void wave_lds_sync()
 {
-    __shared__ uint32_t cx[kWave * 2 * W], cz[kWave * 2 * W];
-    const int lane = threadIdx.x;
-    for (int64_t item = blockIdx.x; item < a.total_row_tiles; item += gridDim.x) {
-        const int64_t c = find_bucket(a.tile_off, a.P, item);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int W>
+__device__ __forceinline__ void load_member(const uint64_t *bx, const uint64_t *bz, int64_t e, bool ok,
+                                            uint32_t (&xo)[2 * W], uint32_t (&zo)[2 * W])
+{
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const uint64_t xv = ok ? bx[e * W + w] : 0ull, zv = ok ? bz[e * W + w] : 0ull;
+        xo[2 * w] = (uint32_t)xv;
+        xo[2 * w + 1] = (uint32_t)(xv >> 32);
+        zo[2 * w] = (uint32_t)zv;
+        zo[2 * w + 1] = (uint32_t)(zv >> 32);
+    }
+}
+
+// Each wave takes (bucket, row tile of 64 members) work items; 4 independent
+// waves per workgroup.  Row members stay in registers; column members are
+// staged in the wave's LDS slice.
+//  - Diagonal tile: lane i tests column (i + s) mod 64 for s = 1..32, which
+//    covers every pair of the tile at least once in 32 steps; the bits,
+//    gathered at position s, are rotated into place and OR-ed with their
+//    transpose.
+//  - Tiles to the right: every lane reads the same column by broadcast;
+//    lane i accumulates its row word, and a bit transpose gives the column
+//    members' words, so each pair is tested once and written twice.
+// Column blocks of 8 past the end of the bucket are skipped.
+constexpr int kRelWaves = 4;
+
+template <int W, int REL>
+__global__ void __launch_bounds__(kWave * kRelWaves) relate_kernel(RelateArgs a)
+{
+    __shared__ uint32_t sx[kRelWaves][kWave * 2 * W], sz[kRelWaves][kWave * 2 * W];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t *cx = sx[wave], *cz = sz[wave];
+    for (int64_t item = (int64_t)blockIdx.x * kRelWaves + wave; item < a.total_row_tiles;
+         item += (int64_t)gridDim.x * kRelWaves) {
+        const int64_t c = a.tile_bucket[item];
         const int64_t rt = item - a.tile_off[c];
         const int64_t base = a.bstart[c];
         const int64_t S = a.bstart[c + 1] - base;
@@ -102,161 +123,236 @@ __global__ void __launch_bounds__(kWave) relate_kernel(RelateArgs a)
         uint64_t *Rm = a.R + a.rb_off[c];
         const int64_t i = rt * kWave + lane;
         uint32_t xi[2 * W], zi[2 * W];
-        if (i < S) {
-            const int64_t g = (int64_t)a.ids[a.bmem[base + i]] * W;
+        load_member<W>(a.bx, a.bz, base + i, i < S, xi, zi);
+        // diagonal tile
+        wave_lds_sync();
 #pragma unroll
-            for (int w = 0; w < W; ++w) {
-                const uint64_t xv = a.x[g + w], zv = a.z[g + w];
-                xi[2 * w] = (uint32_t)xv;
-                xi[2 * w + 1] = (uint32_t)(xv >> 32);
-                zi[2 * w] = (uint32_t)zv;
-                zi[2 * w + 1] = (uint32_t)(zv >> 32);
-            }
-        } else {
-#pragma unroll
-            for (int h = 0; h < 2 * W; ++h) xi[h] = zi[h] = 0u;
+        for (int h = 0; h < 2 * W; ++h) {
+            cx[lane * 2 * W + h] = xi[h];
+            cz[lane * 2 * W + h] = zi[h];
         }
-        for (int64_t ct = rt; ct < nw; ++ct) {
+        wave_lds_sync();
+        uint32_t rl = 0u;
+#pragma unroll 4
+        for (int s = 1; s < 32; ++s) {
+            const int jl = (lane + s) & 63;
+            rl |= pair_bit<W, REL>(xi, zi, &cx[jl * 2 * W], &cz[jl * 2 * W]) << s;
+        }
+        const int j32 = (lane + 32) & 63;
+        const uint64_t r = ((uint64_t)pair_bit<W, REL>(xi, zi, &cx[j32 * 2 * W], &cz[j32 * 2 * W]) << 32) | rl;
+        const int rot = lane;
+        const uint64_t placed = rot ? ((r << rot) | (r >> (64 - rot))) : r;
+        const uint64_t diag = placed | wave_transpose64(placed);
+        if (i < S) Rm[i * nw + rt] = diag;
+        // tiles to the right
+        for (int64_t ct = rt + 1; ct < nw; ++ct) {
             const int64_t j = ct * kWave + lane;
-            __syncthreads();
-            if (j < S) {
-                const int64_t g = (int64_t)a.ids[a.bmem[base + j]] * W;
+            uint32_t xj[2 * W], zj[2 * W];
+            load_member<W>(a.bx, a.bz, base + j, j < S, xj, zj);
+            wave_lds_sync();
 #pragma unroll
-                for (int w = 0; w < W; ++w) {
-                    const uint64_t xv = a.x[g + w], zv = a.z[g + w];
-                    cx[lane * 2 * W + 2 * w] = (uint32_t)xv;
-                    cx[lane * 2 * W + 2 * w + 1] = (uint32_t)(xv >> 32);
-                    cz[lane * 2 * W + 2 * w] = (uint32_t)zv;
-                    cz[lane * 2 * W + 2 * w + 1] = (uint32_t)(zv >> 32);
+            for (int h = 0; h < 2 * W; ++h) {
+                cx[lane * 2 * W + h] = xj[h];
+                cz[lane * 2 * W + h] = zj[h];
+            }
+            wave_lds_sync();
+            const int64_t cols = S - ct * kWave;
+            const int blocks = cols >= kWave ? 8 : (int)((cols + 7) >> 3);
+            uint64_t row = 0;
+            for (int b = 0; b < blocks; ++b) {
+                uint32_t bits8 = 0u;
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const int jj = b * 8 + t;
+                    bits8 |= pair_bit<W, REL>(xi, zi, &cx[jj * 2 * W], &cz[jj * 2 * W]) << t;
                 }
-            } else {
-#pragma unroll
-                for (int h = 0; h < 2 * W; ++h) cx[lane * 2 * W + h] = cz[lane * 2 * W + h] = 0u;
+                row |= (uint64_t)bits8 << (b * 8);
             }
-            __syncthreads();
-            uint32_t lo = 0u, hi = 0u;
-#pragma unroll
-            for (int jj = 0; jj < 32; ++jj) lo |= pair_bit<W, REL>(xi, zi, &cx[jj * 2 * W], &cz[jj * 2 * W]) << jj;
-#pragma unroll
-            for (int jj = 0; jj < 32; ++jj)
-                hi |= pair_bit<W, REL>(xi, zi, &cx[(jj + 32) * 2 * W], &cz[(jj + 32) * 2 * W]) << jj;
-            uint64_t row = ((uint64_t)hi << 32) | lo;
-            if (i >= S) row = 0;
-            if (ct == rt) {
-                // keep the upper triangle (columns after the row), then add
-                // its transpose: the row's bits for earlier members
-                row &= lane == 63 ? 0ull : (~0ull << (lane + 1));
-                const uint64_t col = wave_transpose64(row);
-                if (i < S) Rm[i * nw + rt] = row | col;
-            } else {
-                const uint64_t col = wave_transpose64(row);
-                if (i < S) Rm[i * nw + ct] = row;
-                if (j < S) Rm[j * nw + rt] = col;
-            }
+            const uint64_t col = wave_transpose64(row);
+            if (i < S) Rm[i * nw + ct] = row;
+            if (j < S) Rm[j * nw + rt] = col;
         }
     }
+}
+
+// Strings of the bucket members in bucket order (one contiguous row per
+// bucket entry), so the relation kernel's loads are coalesced.
+__global__ void gather_members_kernel(const uint32_t *__restrict__ bmem, int64_t entries,
+                                      const int32_t *__restrict__ ids, const uint64_t *__restrict__ x,
+                                      const uint64_t *__restrict__ z, int32_t W, uint64_t *__restrict__ bx,
+                                      uint64_t *__restrict__ bz)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < entries;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t g = (int64_t)ids[bmem[e]] * W;
+        for (int w = 0; w < W; ++w) {
+            bx[e * W + w] = x[g + w];
+            bz[e * W + w] = z[g + w];
+        }
+    }
+}
+
+// Owner bucket of every row tile.
+__global__ void tile_bucket_kernel(const int64_t *__restrict__ tile_off, int64_t P, int32_t *__restrict__ owner)
+{
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < P; c += (int64_t)gridDim.x * blockDim.x)
+        for (int64_t t = tile_off[c]; t < tile_off[c + 1]; ++t) owner[t] = (int32_t)c;
 }
 
 // ---- pairs sharing a smaller colour -------------------------------------
 // Member p of bucket c has prefix L(v_p)[0..k_p), the colours below c.  Two
 // members share a smaller colour iff some colour occurs in both prefixes.
-// An LDS hash set finds the colours that occur twice; the (colour, member)
-// entries of those colours yield the pairs, whose bits are set in D.
+// Per window of at most kDupWindow colours (halved while the list below
+// overflows), two LDS bitmaps mark colours seen once and seen again; the (colour, member) entries of colours seen again are
+// listed, sorted by colour, and every two members in a run of one colour get
+// their bit set in D.  Entries are fetched in batches of independent loads
+// (entry e -> member by a search of the prefix-length scan).
 constexpr int kDupThreads = 256;
-constexpr int kDupTable = 8192;  // slots; a bucket fits when its prefixes hold <= kDupTable/2 colours
-constexpr int kDupList = 1024;
-constexpr uint32_t kEmpty = 0xFFFFFFFFu;
-constexpr uint32_t kTwice = 0x80000000u;
-
-__device__ __forceinline__ uint32_t hash_colour(uint32_t c) { return (c * 0x9E3779B1u) >> (32 - 13); }
+constexpr int kDupWindow = 1 << 16;          // colours per pass
+constexpr int kDupWords = kDupWindow / 32;   // bitmap words
+constexpr int kDupMembers = 1024;            // larger buckets take the exact per-pair check
+constexpr int kDupList = 2048;               // listed entries per pass (power of two)
+constexpr int kDupBatch = 8;
+constexpr uint32_t kNone = 0xFFFFFFFFu;
 
 __global__ void __launch_bounds__(kDupThreads) dup_kernel(DupArgs a)
 {
-    __shared__ uint32_t table[kDupTable];
-    __shared__ uint32_t lcol[kDupList];
-    __shared__ uint32_t lmem[kDupList];
+    __shared__ uint32_t seen[kDupWords], again[kDupWords];
+    __shared__ uint32_t mv[kDupMembers];
+    __shared__ int32_t koff[kDupMembers + 1];
+    __shared__ uint64_t list[kDupList];  // colour << 32 | member
+    __shared__ int wsum[kDupThreads / 64];
     __shared__ int lcount;
-    __shared__ int total_prefix;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     for (int64_t c = blockIdx.x; c < a.P; c += gridDim.x) {
         const int64_t base = a.bstart[c];
-        const int64_t S = a.bstart[c + 1] - base;
+        const int S = (int)(a.bstart[c + 1] - base);
         if (S < 2) continue;
-        __syncthreads();
-        if (t == 0) {
-            total_prefix = 0;
-            lcount = 0;
-        }
-        __syncthreads();
-        int mine = 0;
-        for (int64_t p = t; p < S; p += kDupThreads) mine += a.bslot[base + p];
-        atomicAdd(&total_prefix, mine);
-        __syncthreads();
-        const int tp = total_prefix;
-        if (tp == 0) continue;
-        if (2 * tp > kDupTable) {  // too many prefix colours for the table: exact per-pair check later
+        if (S > kDupMembers) {
             if (t == 0) a.slow[atomicAdd(a.n_slow, 1)] = (uint32_t)c;
             continue;
         }
-        for (int s = t; s < kDupTable; s += kDupThreads) table[s] = kEmpty;
+        // members and the exclusive scan of their prefix lengths
         __syncthreads();
-        for (int64_t p = t; p < S; p += kDupThreads) {
-            const int k = a.bslot[base + p];
-            const uint32_t *L = a.lists + (int64_t)a.bmem[base + p] * a.T;
-            for (int s = 0; s < k; ++s) {
-                const uint32_t col = L[s];
-                uint32_t h = hash_colour(col);
-                while (true) {
-                    const uint32_t old = atomicCAS(&table[h], kEmpty, col);
-                    if (old == kEmpty) break;
-                    if ((old & ~kTwice) == col) {
-                        atomicOr(&table[h], kTwice);
-                        break;
-                    }
-                    h = (h + 1) & (kDupTable - 1);
-                }
+        int chunk_base = 0;
+        for (int p0 = 0; p0 < S; p0 += kDupThreads) {
+            const int p = p0 + t;
+            int k = 0;
+            if (p < S) {
+                mv[p] = a.bmem[base + p];
+                k = a.bslot[base + p];
             }
-        }
-        __syncthreads();
-        bool overflow = false;
-        for (int64_t p = t; p < S; p += kDupThreads) {
-            const int k = a.bslot[base + p];
-            const uint32_t *L = a.lists + (int64_t)a.bmem[base + p] * a.T;
-            for (int s = 0; s < k; ++s) {
-                const uint32_t col = L[s];
-                uint32_t h = hash_colour(col);
-                while ((table[h] & ~kTwice) != col) h = (h + 1) & (kDupTable - 1);
-                if (table[h] & kTwice) {
-                    const int e = atomicAdd(&lcount, 1);
-                    if (e < kDupList) {
-                        lcol[e] = col;
-                        lmem[e] = (uint32_t)p;
-                    } else {
-                        overflow = true;
-                    }
-                }
+            int inc = k;
+            for (int d = 1; d < 64; d <<= 1) {
+                const int o = __shfl_up(inc, d, 64);
+                if (lane >= d) inc += o;
             }
+            if (lane == 63) wsum[wave] = inc;
+            __syncthreads();
+            int before = chunk_base;
+            int all = 0;
+            for (int w = 0; w < kDupThreads / 64; ++w) {
+                if (w < wave) before += wsum[w];
+                all += wsum[w];
+            }
+            if (p < S) koff[p] = before + inc - k;
+            chunk_base += all;
+            __syncthreads();
         }
-        __syncthreads();
-        const int n = lcount;
-        if (n > kDupList) {
-            if (t == 0) a.slow[atomicAdd(a.n_slow, 1)] = (uint32_t)c;
-            continue;
-        }
-        (void)overflow;
+        const int total = chunk_base;
+        if (total == 0) continue;
         const int64_t nw = (S + 63) >> 6;
         uint64_t *Dm = a.D + a.rb_off[c];
-        for (int e = t; e < n; e += kDupThreads)
-            for (int f = 0; f < n; ++f)
-                if (f != e && lcol[f] == lcol[e]) {
-                    const uint32_t p = lmem[e], q = lmem[f];
-                    atomicOr((unsigned long long *)&Dm[(int64_t)p * nw + (q >> 6)], 1ull << (q & 63));
+        bool overflow = false;
+        int64_t lo = 0, win = kDupWindow;
+        while (lo < c) {
+            const int64_t hi = lo + win < c ? lo + win : c;
+            const int words = (int)((hi - lo + 31) >> 5);
+            __syncthreads();
+            for (int w = t; w < words; w += kDupThreads) seen[w] = again[w] = 0u;
+            if (t == 0) lcount = 0;
+            __syncthreads();
+            for (int round = 0; round < 2; ++round) {  // 0: mark, 1: list colours seen again
+                for (int e0 = t; e0 < total; e0 += kDupThreads * kDupBatch) {
+                    uint32_t col[kDupBatch];
+                    int mem[kDupBatch];
+#pragma unroll
+                    for (int j = 0; j < kDupBatch; ++j) {
+                        const int e = e0 + j * kDupThreads;
+                        col[j] = kNone;
+                        mem[j] = 0;
+                        if (e < total) {
+                            int l = 0, h = S;  // koff[l] <= e < koff[h]
+                            while (h - l > 1) {
+                                const int mid = (l + h) >> 1;
+                                if (koff[mid] <= e) l = mid;
+                                else h = mid;
+                            }
+                            mem[j] = l;
+                            col[j] = a.lists[(int64_t)mv[l] * a.T + (e - koff[l])];
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < kDupBatch; ++j) {
+                        const uint32_t cc = col[j];
+                        if (cc == kNone || cc < lo || cc >= hi) continue;
+                        const uint32_t b = cc - (uint32_t)lo;
+                        const uint32_t bit = 1u << (b & 31);
+                        if (round == 0) {
+                            if (atomicOr(&seen[b >> 5], bit) & bit) atomicOr(&again[b >> 5], bit);
+                        } else if (again[b >> 5] & bit) {
+                            const int at = atomicAdd(&lcount, 1);
+                            if (at < kDupList) list[at] = ((uint64_t)cc << 32) | (uint32_t)mem[j];
+                        }
+                    }
                 }
+                __syncthreads();
+            }
+            const int n = lcount;
+            if (n > kDupList) {  // too many shared colours for the list: narrower window
+                if (win <= 64) {
+                    overflow = true;  // exact per-pair check
+                    break;
+                }
+                win >>= 1;
+                continue;
+            }
+            lo = hi;
+            if (n < 2) continue;
+            int N = 2;
+            while (N < n) N <<= 1;
+            for (int e = n + t; e < N; e += kDupThreads) list[e] = ~0ull;
+            __syncthreads();
+            for (int k = 2; k <= N; k <<= 1)
+                for (int j = k >> 1; j > 0; j >>= 1) {
+                    for (int e = t; e < N; e += kDupThreads) {
+                        const int f = e ^ j;
+                        if (f > e) {
+                            const uint64_t ve = list[e], vf = list[f];
+                            if ((ve > vf) == ((e & k) == 0)) {
+                                list[e] = vf;
+                                list[f] = ve;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+            // each entry pairs with the later entries of its colour run
+            for (int e = t; e < n; e += kDupThreads) {
+                const uint32_t ce = (uint32_t)(list[e] >> 32), pe = (uint32_t)list[e];
+                for (int f = e + 1; f < n && (uint32_t)(list[f] >> 32) == ce; ++f) {
+                    const uint32_t pf = (uint32_t)list[f];
+                    atomicOr((unsigned long long *)&Dm[(int64_t)pe * nw + (pf >> 6)], 1ull << (pf & 63));
+                    atomicOr((unsigned long long *)&Dm[(int64_t)pf * nw + (pe >> 6)], 1ull << (pe & 63));
+                }
+            }
+        }
+        if (overflow && t == 0) a.slow[atomicAdd(a.n_slow, 1)] = (uint32_t)c;
     }
 }
 
-// Buckets whose prefixes overflow the LDS table: test every pair directly by
-// merging the two prefixes (rare: only very large buckets).
+// Buckets the LDS pass cannot take: every relation pair is checked directly
+// by merging the two prefixes (rare: only very large buckets).
 __global__ void __launch_bounds__(256) dup_slow_kernel(DupArgs a, int64_t n_slow)
 {
     for (int64_t b = blockIdx.x; b < n_slow; b += gridDim.x) {
@@ -264,26 +360,32 @@ __global__ void __launch_bounds__(256) dup_slow_kernel(DupArgs a, int64_t n_slow
         const int64_t base = a.bstart[c];
         const int64_t S = a.bstart[c + 1] - base;
         const int64_t nw = (S + 63) >> 6;
+        const uint64_t *Rm = a.R + a.rb_off[c];
         uint64_t *Dm = a.D + a.rb_off[c];
         for (int64_t p = threadIdx.x; p < S; p += blockDim.x) {
             const int kp = a.bslot[base + p];
             if (kp == 0) continue;
             const uint32_t *Lp = a.lists + (int64_t)a.bmem[base + p] * a.T;
-            for (int64_t q = 0; q < S; ++q) {
-                const int kq = a.bslot[base + q];
-                if (q == p || kq == 0) continue;
-                const uint32_t *Lq = a.lists + (int64_t)a.bmem[base + q] * a.T;
-                int x = 0, y = 0;
-                bool shared = false;
-                while (x < kp && y < kq) {
-                    if (Lp[x] == Lq[y]) {
-                        shared = true;
-                        break;
+            for (int64_t w = 0; w < nw; ++w) {
+                uint64_t bits = Rm[p * nw + w];
+                while (bits) {
+                    const int64_t q = w * 64 + __builtin_ctzll(bits);
+                    bits &= bits - 1;
+                    const int kq = a.bslot[base + q];
+                    if (kq == 0) continue;
+                    const uint32_t *Lq = a.lists + (int64_t)a.bmem[base + q] * a.T;
+                    int x = 0, y = 0;
+                    bool shared = false;
+                    while (x < kp && y < kq) {
+                        if (Lp[x] == Lq[y]) {
+                            shared = true;
+                            break;
+                        }
+                        if (Lp[x] < Lq[y]) ++x;
+                        else ++y;
                     }
-                    if (Lp[x] < Lq[y]) ++x;
-                    else ++y;
+                    if (shared) atomicOr((unsigned long long *)&Dm[p * nw + (q >> 6)], 1ull << (q & 63));
                 }
-                if (shared) atomicOr((unsigned long long *)&Dm[p * nw + (q >> 6)], 1ull << (q & 63));
             }
         }
     }
@@ -307,24 +409,58 @@ __global__ void __launch_bounds__(kWave) count_kernel(CsrArgs a)
     }
 }
 
-// CSR rows: each member's edges in this bucket go to its (vertex, slot)
-// segment, whose start comes from the exclusive scan of the counts.
-__global__ void __launch_bounds__(kWave) fill_kernel(CsrArgs a)
+// CSR rows: one wave per member row.  The 64 lanes test the 64 bits of a
+// row word, and a ballot prefix count (mbcnt) gives each set bit its slot in
+// the member's contiguous (vertex, slot) segment, so every store of the
+// wave lands in one run of the CSR.  When the bucket fits, its rows of
+// R & ~D, member ids and segment offsets are first staged in LDS with
+// independent loads.
+constexpr int kFillWaves = 4;
+constexpr int kFillMembers = 1024;
+constexpr int kFillWords = 4096;
+
+__global__ void __launch_bounds__(kWave * kFillWaves) fill_kernel(CsrArgs a)
 {
+    __shared__ uint64_t rows[kFillWords];
+    __shared__ int64_t seg[kFillMembers];
+    __shared__ uint32_t mv[kFillMembers];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int64_t c = blockIdx.x; c < a.P; c += gridDim.x) {
         const int64_t base = a.bstart[c];
         const int64_t S = a.bstart[c + 1] - base;
+        if (S < 2) continue;
         const int64_t nw = (S + 63) >> 6;
         const uint64_t *Rm = a.R + a.rb_off[c];
         const uint64_t *Dm = a.D + a.rb_off[c];
-        for (int64_t p = threadIdx.x; p < S; p += kWave) {
-            int64_t at = a.slot_off[(int64_t)a.bmem[base + p] * a.T + a.bslot[base + p]];
-            for (int64_t w = 0; w < nw; ++w) {
-                uint64_t bits = Rm[p * nw + w] & ~Dm[p * nw + w];
-                while (bits) {
-                    const int b = __builtin_ctzll(bits);
-                    bits &= bits - 1;
-                    a.adj[at++] = (int32_t)a.bmem[base + w * 64 + b];
+        if (S <= kFillMembers && S * nw <= kFillWords) {
+            __syncthreads();
+            for (int64_t p = threadIdx.x; p < S; p += blockDim.x) {
+                const uint32_t v = a.bmem[base + p];
+                mv[p] = v;
+                seg[p] = a.slot_off[(int64_t)v * a.T + a.bslot[base + p]];
+            }
+            for (int64_t w = threadIdx.x; w < S * nw; w += blockDim.x) rows[w] = Rm[w] & ~Dm[w];
+            __syncthreads();
+            for (int64_t p = wave; p < S; p += kFillWaves) {
+                int64_t at = seg[p];
+                for (int64_t w = 0; w < nw; ++w) {
+                    const uint64_t bits = rows[p * nw + w];
+                    const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bits >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)bits, 0u));
+                    if ((bits >> lane) & 1ull) a.adj[at + rank] = (int32_t)mv[w * 64 + lane];
+                    at += __popcll(bits);
+                }
+            }
+        } else {
+            for (int64_t p = wave; p < S; p += kFillWaves) {
+                const uint32_t vp = a.bmem[base + p];
+                int64_t at = a.slot_off[(int64_t)vp * a.T + a.bslot[base + p]];
+                for (int64_t w = 0; w < nw; ++w) {
+                    const uint64_t bits = Rm[p * nw + w] & ~Dm[p * nw + w];
+                    const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bits >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)bits, 0u));
+                    if ((bits >> lane) & 1ull) a.adj[at + rank] = (int32_t)a.bmem[base + w * 64 + lane];
+                    at += __popcll(bits);
                 }
             }
         }
@@ -345,16 +481,33 @@ unsigned grid_cap(int64_t items, int64_t cap = 1 << 22)
 
 }  // namespace
 
+void launch_relate_prep(RelateArgs &a, int64_t entries, uint64_t *bx, uint64_t *bz, int32_t *tile_bucket,
+                        hipStream_t st)
+{
+    if (entries > 0) {
+        gather_members_kernel<<<grid_cap((entries + 255) / 256, 65535 * 16), 256, 0, st>>>(a.bmem, entries, a.ids,
+                                                                                        a.x, a.z, a.W, bx, bz);
+        PCHECK_LAUNCH();
+    }
+    if (a.P > 0) {
+        tile_bucket_kernel<<<grid_cap((a.P + 255) / 256, 65535 * 16), 256, 0, st>>>(a.tile_off, a.P, tile_bucket);
+        PCHECK_LAUNCH();
+    }
+    a.bx = bx;
+    a.bz = bz;
+    a.tile_bucket = tile_bucket;
+}
+
 void launch_relate(const RelateArgs &a, hipStream_t st)
 {
     if (a.total_row_tiles <= 0) return;
-    const unsigned grid = grid_cap(a.total_row_tiles);
+    const unsigned grid = grid_cap((a.total_row_tiles + kRelWaves - 1) / kRelWaves);
 #define PICASSO_REL_CASE(WW)                                                                       \
     case WW:                                                                                       \
         if (a.relation == PICASSO_REL_ANTICOMMUTE)                                                 \
-            relate_kernel<WW, PICASSO_REL_ANTICOMMUTE><<<grid, kWave, 0, st>>>(a);                 \
+            relate_kernel<WW, PICASSO_REL_ANTICOMMUTE><<<grid, kWave * kRelWaves, 0, st>>>(a);     \
         else                                                                                       \
-            relate_kernel<WW, PICASSO_REL_QWC><<<grid, kWave, 0, st>>>(a);                         \
+            relate_kernel<WW, PICASSO_REL_QWC><<<grid, kWave * kRelWaves, 0, st>>>(a);             \
         break;
     switch (a.W) {
         PICASSO_REL_CASE(1)
@@ -392,7 +545,7 @@ void launch_count(const CsrArgs &a, hipStream_t st)
 void launch_fill(const CsrArgs &a, hipStream_t st)
 {
     if (a.P <= 0) return;
-    fill_kernel<<<grid_cap(a.P, 1 << 20), kWave, 0, st>>>(a);
+    fill_kernel<<<grid_cap(a.P, 1 << 20), kWave * kFillWaves, 0, st>>>(a);
     PCHECK_LAUNCH();
 }
 

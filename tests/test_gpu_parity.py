@@ -69,6 +69,9 @@ def gpu_edges(h, seed, ell, ids, P, T, rel):
     (800, 256, (0.85, 0.05, 0.05, 0.05), 30, 8),             # W = 4
     (1100, 30, (0.6, 0.1, 0.2, 0.1), 2, 1),                 # buckets > 512 members (column chunks)
     (700, 64, (0.5, 0.2, 0.2, 0.1), 9000, 3),               # mostly empty buckets
+    (3000, 40, (0.7, 0.1, 0.1, 0.1), 6, 3),                  # buckets > 1024 members: exact dedup path
+    (1500, 24, (0.6, 0.1, 0.2, 0.1), 100, 64),              # long prefixes: several hash passes
+    (1200, 24, (0.6, 0.1, 0.2, 0.1), 300, 200),             # T near the limit, multi-word slot masks
 ])
 def test_conflict_graph_bit_exact(orc, rel, n, q, probs, P, T):
     say("graph", rel, n, q, P, T)
