@@ -174,6 +174,51 @@ int64_t picasso_conflict_graph(picasso_handle h, uint64_t seed, int32_t ell, int
 int64_t picasso_list_color_csr(picasso_handle h, int64_t m, const uint64_t *prio, const uint32_t *lists, int32_t T,
                                int64_t P, const int64_t *rowptr, const int32_t *adj, int32_t *out_col);
 
+/* ---- Learned parameters (the paper's Sec. VI predictor, as a small MLP) --- */
+
+typedef struct picasso_mlp_ctx *picasso_mlp;
+
+#define PICASSO_MLP_NPARAMS 4674 /* W1[64][5] b1[64] W2[64][64] b2[64] W3[2][64] b3[2] */
+#define PICASSO_FEATURE_PAIRS 4096
+
+/* Features of an iteration's vertex set: out[5] = (ln m, q, mean Pauli
+ * weight, fraction of PICASSO_FEATURE_PAIRS sampled vertex pairs joined by
+ * the relation, ell).  ids host, m ascending original ids.  Sampled pair k
+ * is keyed by (seed; k, ell).  Returns PICASSO_OK or an error. */
+int32_t picasso_features(picasso_handle h, uint64_t seed, int32_t ell, int64_t m, const int32_t *ids,
+                         int32_t relation, double *out);
+
+/* A 5 -> 64 -> 64 -> 2 perceptron (ReLU hidden layers, FP32) on the device
+ * of the calling thread.  params: host, PICASSO_MLP_NPARAMS floats in the
+ * layout above, or NULL for a deterministic initialisation from seed
+ * (scaled normal weights, zero biases).  Returns NULL on error. */
+picasso_mlp picasso_mlp_create(const float *params, uint64_t seed);
+void picasso_mlp_destroy(picasso_mlp mlp);
+int32_t picasso_mlp_get_params(picasso_mlp mlp, float *out);      /* host, NPARAMS floats */
+int32_t picasso_mlp_set_params(picasso_mlp mlp, const float *in);  /* resets the Adam state */
+
+/* Raw outputs o (B x 2, host) for B feature rows (B x 5, host); the
+ * parameters are f = 0.01 + 0.24 sigmoid(o0), alpha = 1 + 3 sigmoid(o1). */
+int32_t picasso_mlp_forward(picasso_mlp mlp, const float *features, int32_t B, float *out);
+
+/* Loss (1/(2B)) sum (o - target)^2 over B rows and its gradient (host,
+ * NPARAMS floats; may be NULL).  Returns PICASSO_OK. */
+int32_t picasso_mlp_gradient(picasso_mlp mlp, const float *features, const float *target, int32_t B, float *grad,
+                             float *loss);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on a batch; writes the
+ * batch loss before the step to *loss.  Returns PICASSO_OK. */
+int32_t picasso_mlp_train_step(picasso_mlp mlp, const float *features, const float *target, int32_t B, float lr,
+                               float *loss);
+
+/* Colour with per-iteration parameters from the network: each iteration
+ * computes its features on the device, runs the network, and uses the FP32
+ * (f, alpha) it returns.  out_schedule (host, 2 * max_sched floats, may be
+ * NULL) receives the (f, alpha) of the first max_sched iterations.  Returns
+ * n_colors or an error. */
+int64_t picasso_color_learned(picasso_handle h, uint64_t seed, picasso_mlp mlp, int32_t relation,
+                              int32_t *out_colors, float *out_schedule, int32_t max_sched);
+
 #ifdef __cplusplus
 }
 #endif

@@ -232,3 +232,102 @@ def color(x: np.ndarray, z: np.ndarray, q: int, seed: int, frac: float, alpha: f
         for s in stats[: min(nit.value, max_stats)]
     ]
     return int(nc), out[:n], st
+
+
+# ---- parameter schedule, features, predictor twin ---------------------------
+MLP_IN, MLP_HIDDEN, MLP_OUT = 5, 64, 2
+FEATURE_PAIRS = 4096
+
+
+def _bind_extra():
+    L = lib()
+    if getattr(L, "_extra_bound", False):
+        return L
+    p = ctypes.c_void_p
+    i32, i64, u32, u64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
+    L.orc_color_schedule.argtypes = [i64, i32, p, p, u64, p, p, i32, i32, p, p, i32, p]
+    L.orc_color_schedule.restype = i64
+    L.orc_features_bits.argtypes = [i64, i32, p, p, i64, p, u64, u32, i32, i32, p]
+    L.orc_features_bits.restype = None
+    L.orc_mlp_nparams.argtypes = []
+    L.orc_mlp_nparams.restype = i32
+    L.orc_mlp_forward.argtypes = [p, p, i32, p]
+    L.orc_mlp_forward.restype = None
+    L.orc_mlp_squash.argtypes = [p, p, p]
+    L.orc_mlp_squash.restype = None
+    L.orc_mlp_loss_grad.argtypes = [p, p, p, i32, p]
+    L.orc_mlp_loss_grad.restype = dbl
+    L.orc_adam_step.argtypes = [p, p, p, p, i32, dbl, dbl, dbl, dbl, i32]
+    L.orc_adam_step.restype = None
+    L._extra_bound = True
+    return L
+
+
+def color_schedule(x, z, q, seed, fracs, alphas, rel, max_stats=4096):
+    """Iteration l uses (fracs[l-1], alphas[l-1]), the last entry after the end."""
+    L = _bind_extra()
+    x = np.ascontiguousarray(x, dtype=np.uint64).reshape(-1, _words(q))
+    z = np.ascontiguousarray(z, dtype=np.uint64).reshape(-1, _words(q))
+    n = x.shape[0]
+    fr = np.ascontiguousarray(fracs, dtype=np.float64)
+    al = np.ascontiguousarray(alphas, dtype=np.float64)
+    out = np.zeros(max(n, 1), dtype=np.int32)
+    stats = (IterStat * max_stats)()
+    nit = ctypes.c_int32()
+    nc = L.orc_color_schedule(n, q, _ptr(x), _ptr(z), seed, _ptr(fr), _ptr(al), len(fr), rel, _ptr(out), stats,
+                              max_stats, ctypes.byref(nit))
+    if nc < 0:
+        raise MemoryError("oracle: allocation failed")
+    st = [dict(m=s.m, P=s.P, T=s.T, pair_tests=s.pair_tests, edges=s.edges, colored=s.colored, offset=s.offset)
+          for s in stats[: min(nit.value, max_stats)]]
+    return int(nc), out[:n], st
+
+
+def features(x, z, q, ids, seed, ell, rel, K=FEATURE_PAIRS):
+    L = _bind_extra()
+    x = np.ascontiguousarray(x, dtype=np.uint64).reshape(-1, _words(q))
+    z = np.ascontiguousarray(z, dtype=np.uint64).reshape(-1, _words(q))
+    ids = np.ascontiguousarray(ids, dtype=np.int32)
+    out = np.zeros(5, dtype=np.float64)
+    L.orc_features_bits(x.shape[0], q, _ptr(x), _ptr(z), ids.shape[0], _ptr(ids), seed, ell, rel, K, _ptr(out))
+    return out
+
+
+def mlp_nparams() -> int:
+    return int(_bind_extra().orc_mlp_nparams())
+
+
+def mlp_forward(params, raw):
+    L = _bind_extra()
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    raw = np.ascontiguousarray(raw, dtype=np.float64).reshape(-1, MLP_IN)
+    out = np.zeros((raw.shape[0], MLP_OUT), dtype=np.float64)
+    L.orc_mlp_forward(_ptr(params), _ptr(raw), raw.shape[0], _ptr(out))
+    return out
+
+
+def mlp_squash(o):
+    L = _bind_extra()
+    o = np.ascontiguousarray(o, dtype=np.float64)
+    f, a = ctypes.c_double(), ctypes.c_double()
+    L.orc_mlp_squash(_ptr(o), ctypes.byref(f), ctypes.byref(a))
+    return f.value, a.value
+
+
+def mlp_loss_grad(params, raw, target):
+    L = _bind_extra()
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    raw = np.ascontiguousarray(raw, dtype=np.float64).reshape(-1, MLP_IN)
+    target = np.ascontiguousarray(target, dtype=np.float64).reshape(-1, MLP_OUT)
+    grad = np.zeros_like(params)
+    loss = L.orc_mlp_loss_grad(_ptr(params), _ptr(raw), _ptr(target), raw.shape[0], _ptr(grad))
+    return loss, grad
+
+
+def adam_step(params, grad, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """In-place Adam update of float64 arrays params, m, v."""
+    L = _bind_extra()
+    for a in (params, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = np.ascontiguousarray(grad, dtype=np.float64)
+    L.orc_adam_step(_ptr(params), _ptr(g), _ptr(m), _ptr(v), step, lr, b1, b2, eps, params.shape[0])

@@ -28,6 +28,12 @@
  *                      T = P, complete and empty relation graphs, chromatic
  *                      lower bound by subset DP for n <= 12.  Exact colour
  *                      values beyond these are parity unpinned by the paper.
+ *   schedule driver -- a constant schedule reproduces the fixed-parameter run.
+ *   features        -- direct counts (weight), density 1 / 0 on complete and
+ *                      empty relation graphs, closed-form density for i.i.d.
+ *   predictor twin  -- gradients against central finite differences, the
+ *                      forward pass against the collapsed affine map, Adam's
+ *                      first step in closed form.
  */
 #include <math.h>
 #include <stdint.h>
@@ -530,4 +536,244 @@ int64_t orc_color(int64_t n, int32_t q, const uint64_t *x, const uint64_t *z, ui
     free(chars);
     free(ids);
     return distinct;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Iterations with a parameter schedule: iteration ell uses (fracs[ell-1],   */
+/* alphas[ell-1]) (the last entry once the schedule is exhausted).  This is */
+/* how a learned predictor's per-iteration outputs are replayed.            */
+/* ------------------------------------------------------------------------ */
+int64_t orc_color_schedule(int64_t n, int32_t q, const uint64_t *x, const uint64_t *z, uint64_t seed,
+                           const double *fracs, const double *alphas, int32_t n_sched, int32_t rel,
+                           int32_t *out_colors, orc_iter_stat *stats, int32_t max_stats, int32_t *n_iters)
+{
+    char *chars = (char *)malloc((size_t)(n * q > 0 ? n * q : 1));
+    int32_t *ids = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    if (!chars || !ids || n_sched < 1) {
+        free(chars); free(ids);
+        return -1;
+    }
+    orc_decode(n, q, x, z, chars);
+    for (int64_t i = 0; i < n; i++) {
+        ids[i] = (int32_t)i;
+        out_colors[i] = -1;
+    }
+    int64_t m = n, offset = 0, distinct = 0;
+    uint32_t ell = 1;
+    int32_t it = 0;
+    while (m > 0) {
+        const int32_t si = (int32_t)ell - 1 < n_sched ? (int32_t)ell - 1 : n_sched - 1;
+        int64_t P;
+        int32_t T;
+        orc_params(m, fracs[si], alphas[si], 0, &P, &T);
+        uint32_t *lists = (uint32_t *)malloc((size_t)(m * T) * sizeof(uint32_t));
+        uint64_t *prio = (uint64_t *)malloc((size_t)m * sizeof(uint64_t));
+        int32_t *col = (int32_t *)malloc((size_t)m * sizeof(int32_t));
+        char *used = (char *)calloc((size_t)P, 1);
+        if (!lists || !prio || !col || !used) {
+            free(lists); free(prio); free(col); free(used); free(chars); free(ids);
+            return -1;
+        }
+        orc_sample_lists(seed, ell, m, ids, P, T, lists);
+        for (int64_t i = 0; i < m; i++) prio[i] = orc_priority(seed, ell, (uint32_t)ids[i]);
+        edge_buf eb = {0, 0, 0};
+        int64_t tests = 0;
+        int64_t ne = conflict_edges_by_colour(q, m, ids, chars, lists, T, P, rel, 0, P, &eb, &tests);
+        if (ne < 0 || orc_greedy_from_edges(m, prio, lists, T, P, eb.uv, ne, col)) {
+            free(eb.uv); free(lists); free(prio); free(col); free(used); free(chars); free(ids);
+            return -1;
+        }
+        free(eb.uv);
+        int64_t next = 0, colored = 0;
+        for (int64_t i = 0; i < m; i++) {
+            if (col[i] >= 0) {
+                out_colors[ids[i]] = (int32_t)(offset + col[i]);
+                if (!used[col[i]]) {
+                    used[col[i]] = 1;
+                    distinct++;
+                }
+                colored++;
+            } else {
+                ids[next++] = ids[i];
+            }
+        }
+        if (stats && it < max_stats) {
+            orc_iter_stat s = {m, P, T, tests, ne, colored, offset};
+            stats[it] = s;
+        }
+        it++;
+        free(lists); free(prio); free(col); free(used);
+        offset += P;
+        m = next;
+        ell++;
+    }
+    if (n_iters) *n_iters = it;
+    free(chars);
+    free(ids);
+    return distinct;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Instance features for the parameter predictor (the paper's Sec. VI       */
+/* predicts (P', alpha) from the graph; here from five numbers per          */
+/* iteration):                                                              */
+/*   f0 = ln m, f1 = q, f2 = mean Pauli weight (non-identity positions per  */
+/*   string), f3 = fraction of K sampled vertex pairs joined by the         */
+/*   relation, f4 = ell.                                                    */
+/* Sampled pair k: a = floor(r1*m/2^64), b' = floor(r2*(m-1)/2^64),         */
+/* b = b' + (b' >= a), with r1, r2 the keyed draws (seed; k, 0|1, ell,      */
+/* tag "FEAT"): a uniform ordered pair of distinct vertices.                */
+/* ------------------------------------------------------------------------ */
+#define ORC_TAG_FEAT 0x46454154u
+
+void orc_features(int32_t q, const char *chars, int64_t m, const int32_t *ids, uint64_t seed, uint32_t ell,
+                  int32_t rel, int32_t K, double out[5])
+{
+    int64_t weight = 0;
+    for (int64_t i = 0; i < m; i++)
+        for (int k = 0; k < q; k++)
+            if (chars[(int64_t)ids[i] * q + k] != 'I') weight++;
+    int64_t hits = 0;
+    if (m >= 2)
+        for (int32_t k = 0; k < K; k++) {
+            uint64_t r1 = orc_hash64(seed, (uint32_t)k, 0, ell, ORC_TAG_FEAT);
+            uint64_t r2 = orc_hash64(seed, (uint32_t)k, 1, ell, ORC_TAG_FEAT);
+            uint64_t a = mul_high64(r1, (uint64_t)m);
+            uint64_t b = mul_high64(r2, (uint64_t)(m - 1));
+            if (b >= a) b++;
+            hits += orc_relation_chars(q, chars + (int64_t)ids[a] * q, chars + (int64_t)ids[b] * q, rel);
+        }
+    out[0] = m > 0 ? log((double)m) : 0.0;
+    out[1] = (double)q;
+    out[2] = m > 0 ? (double)weight / (double)m : 0.0;
+    out[3] = (m >= 2 && K > 0) ? (double)hits / (double)K : 0.0;
+    out[4] = (double)ell;
+}
+
+/* Exported wrapper on bit-plane input. */
+void orc_features_bits(int64_t n, int32_t q, const uint64_t *x, const uint64_t *z, int64_t m, const int32_t *ids,
+                       uint64_t seed, uint32_t ell, int32_t rel, int32_t K, double out[5])
+{
+    char *chars = (char *)malloc((size_t)(n * q > 0 ? n * q : 1));
+    if (!chars) return;
+    orc_decode(n, q, x, z, chars);
+    orc_features(q, chars, m, ids, seed, ell, rel, K, out);
+    free(chars);
+}
+
+/* ------------------------------------------------------------------------ */
+/* The parameter predictor: a 3-layer perceptron 5 -> 64 -> 64 -> 2 with    */
+/* ReLU hidden layers (FP64 twin of the GPU network).                       */
+/* Parameter vector layout (4674 values):                                   */
+/*   W1[64][5], b1[64], W2[64][64], b2[64], W3[2][64], b3[2]                */
+/* Inputs are scaled before the first layer:                                */
+/*   (ln m / 16, q / 128, weight / 128, density, ell / 16).                 */
+/* Outputs o (2 values) map to parameters by                                */
+/*   f = 0.01 + 0.24 sigmoid(o0), alpha = 1 + 3 sigmoid(o1).                */
+/* Training loss over a batch of B rows: (1/(2B)) sum (o - t)^2.            */
+/* ------------------------------------------------------------------------ */
+#define ORC_H 64
+#define ORC_IN 5
+#define ORC_OUT 2
+#define ORC_NPARAM (ORC_H * ORC_IN + ORC_H + ORC_H * ORC_H + ORC_H + ORC_OUT * ORC_H + ORC_OUT)
+
+int32_t orc_mlp_nparams(void) { return ORC_NPARAM; }
+
+static void mlp_scale(const double *raw, double *xin)
+{
+    xin[0] = raw[0] / 16.0;
+    xin[1] = raw[1] / 128.0;
+    xin[2] = raw[2] / 128.0;
+    xin[3] = raw[3];
+    xin[4] = raw[4] / 16.0;
+}
+
+/* Forward pass of one row; keeps the activations for the gradient. */
+static void mlp_row(const double *p, const double *raw, double *xin, double *h1, double *h2, double *o)
+{
+    const double *W1 = p, *b1 = W1 + ORC_H * ORC_IN, *W2 = b1 + ORC_H, *b2 = W2 + ORC_H * ORC_H;
+    const double *W3 = b2 + ORC_H, *b3 = W3 + ORC_OUT * ORC_H;
+    mlp_scale(raw, xin);
+    for (int j = 0; j < ORC_H; j++) {
+        double s = b1[j];
+        for (int i = 0; i < ORC_IN; i++) s += W1[j * ORC_IN + i] * xin[i];
+        h1[j] = s > 0.0 ? s : 0.0;
+    }
+    for (int j = 0; j < ORC_H; j++) {
+        double s = b2[j];
+        for (int i = 0; i < ORC_H; i++) s += W2[j * ORC_H + i] * h1[i];
+        h2[j] = s > 0.0 ? s : 0.0;
+    }
+    for (int k = 0; k < ORC_OUT; k++) {
+        double s = b3[k];
+        for (int i = 0; i < ORC_H; i++) s += W3[k * ORC_H + i] * h2[i];
+        o[k] = s;
+    }
+}
+
+void orc_mlp_forward(const double *p, const double *raw, int32_t B, double *out)
+{
+    double xin[ORC_IN], h1[ORC_H], h2[ORC_H];
+    for (int b = 0; b < B; b++) mlp_row(p, raw + (int64_t)b * ORC_IN, xin, h1, h2, out + (int64_t)b * ORC_OUT);
+}
+
+void orc_mlp_squash(const double *o, double *frac, double *alpha)
+{
+    *frac = 0.01 + 0.24 / (1.0 + exp(-o[0]));
+    *alpha = 1.0 + 3.0 / (1.0 + exp(-o[1]));
+}
+
+/* Loss and its gradient by the chain rule (backpropagation). */
+double orc_mlp_loss_grad(const double *p, const double *raw, const double *t, int32_t B, double *grad)
+{
+    const double *W2 = p + ORC_H * ORC_IN + ORC_H, *W3 = W2 + ORC_H * ORC_H + ORC_H;
+    double *gW1 = grad, *gb1 = gW1 + ORC_H * ORC_IN, *gW2 = gb1 + ORC_H, *gb2 = gW2 + ORC_H * ORC_H;
+    double *gW3 = gb2 + ORC_H, *gb3 = gW3 + ORC_OUT * ORC_H;
+    for (int i = 0; i < ORC_NPARAM; i++) grad[i] = 0.0;
+    double loss = 0.0;
+    double xin[ORC_IN], h1[ORC_H], h2[ORC_H], o[ORC_OUT], d3[ORC_OUT], d2[ORC_H], d1[ORC_H];
+    for (int b = 0; b < B; b++) {
+        mlp_row(p, raw + (int64_t)b * ORC_IN, xin, h1, h2, o);
+        for (int k = 0; k < ORC_OUT; k++) {
+            const double e = o[k] - t[(int64_t)b * ORC_OUT + k];
+            loss += 0.5 * e * e / B;
+            d3[k] = e / B;
+        }
+        for (int i = 0; i < ORC_H; i++) {
+            double s = 0.0;
+            for (int k = 0; k < ORC_OUT; k++) s += W3[k * ORC_H + i] * d3[k];
+            d2[i] = h2[i] > 0.0 ? s : 0.0;
+        }
+        for (int i = 0; i < ORC_H; i++) {
+            double s = 0.0;
+            for (int j = 0; j < ORC_H; j++) s += W2[j * ORC_H + i] * d2[j];
+            d1[i] = h1[i] > 0.0 ? s : 0.0;
+        }
+        for (int k = 0; k < ORC_OUT; k++) {
+            for (int i = 0; i < ORC_H; i++) gW3[k * ORC_H + i] += d3[k] * h2[i];
+            gb3[k] += d3[k];
+        }
+        for (int j = 0; j < ORC_H; j++) {
+            for (int i = 0; i < ORC_H; i++) gW2[j * ORC_H + i] += d2[j] * h1[i];
+            gb2[j] += d2[j];
+        }
+        for (int j = 0; j < ORC_H; j++) {
+            for (int i = 0; i < ORC_IN; i++) gW1[j * ORC_IN + i] += d1[j] * xin[i];
+            gb1[j] += d1[j];
+        }
+    }
+    return loss;
+}
+
+/* Adam (Kingma & Ba, 2015): m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * p -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps). */
+void orc_adam_step(double *p, const double *g, double *m, double *v, int32_t step, double lr, double b1, double b2,
+                   double eps, int32_t nparam)
+{
+    const double c1 = 1.0 - pow(b1, (double)step), c2 = 1.0 - pow(b2, (double)step);
+    for (int i = 0; i < nparam; i++) {
+        m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+        v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+        p[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
+    }
 }

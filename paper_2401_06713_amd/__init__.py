@@ -38,7 +38,18 @@ EXPORTS = (
     "picasso_sample_lists",
     "picasso_conflict_graph",
     "picasso_list_color_csr",
+    "picasso_features",
+    "picasso_mlp_create",
+    "picasso_mlp_destroy",
+    "picasso_mlp_get_params",
+    "picasso_mlp_set_params",
+    "picasso_mlp_forward",
+    "picasso_mlp_gradient",
+    "picasso_mlp_train_step",
+    "picasso_color_learned",
 )
+MLP_NPARAMS = 4674
+FEATURE_PAIRS = 4096
 
 
 class IterStats(ctypes.Structure):
@@ -136,6 +147,25 @@ def lib() -> ctypes.CDLL:
     L.picasso_conflict_graph.argtypes = [p, u64, i32, i64, p, i64, i32, i32, p, p, i64]
     L.picasso_list_color_csr.restype = i64
     L.picasso_list_color_csr.argtypes = [p, i64, p, p, i32, i64, p, p, p]
+    f32 = ctypes.c_float
+    L.picasso_features.restype = i32
+    L.picasso_features.argtypes = [p, u64, i32, i64, p, i32, p]
+    L.picasso_mlp_create.restype = p
+    L.picasso_mlp_create.argtypes = [p, u64]
+    L.picasso_mlp_destroy.restype = None
+    L.picasso_mlp_destroy.argtypes = [p]
+    L.picasso_mlp_get_params.restype = i32
+    L.picasso_mlp_get_params.argtypes = [p, p]
+    L.picasso_mlp_set_params.restype = i32
+    L.picasso_mlp_set_params.argtypes = [p, p]
+    L.picasso_mlp_forward.restype = i32
+    L.picasso_mlp_forward.argtypes = [p, p, i32, p]
+    L.picasso_mlp_gradient.restype = i32
+    L.picasso_mlp_gradient.argtypes = [p, p, p, i32, p, ctypes.POINTER(f32)]
+    L.picasso_mlp_train_step.restype = i32
+    L.picasso_mlp_train_step.argtypes = [p, p, p, i32, f32, ctypes.POINTER(f32)]
+    L.picasso_color_learned.restype = i64
+    L.picasso_color_learned.argtypes = [p, u64, p, i32, p, p, i32]
     _lib = L
     return L
 
@@ -243,6 +273,100 @@ class Picasso:
                                               _ptr(adj), adj.shape[0]))
         assert ne2 == ne
         return rowptr, adj[: 2 * ne]
+
+
+    def features(self, seed: int, ell: int, ids, relation: int) -> np.ndarray:
+        """(ln m, q, mean Pauli weight, sampled relation density, ell)."""
+        ids = np.ascontiguousarray(ids, dtype=np.int32)
+        out = np.zeros(5, dtype=np.float64)
+        _check(lib().picasso_features(self._h, seed, ell, ids.shape[0], _ptr(ids), relation, _ptr(out)))
+        return out
+
+    def color_learned(self, mlp: "Mlp", seed: int = 0, relation: int = REL_ANTICOMMUTE, max_sched: int = 256):
+        """Colours with per-iteration (f, alpha) from the network.
+
+        Returns (n_colors, colors, schedule) with schedule (iterations, 2) float32."""
+        out = np.empty(max(self.n, 1), dtype=np.int32)
+        sched = np.zeros((max_sched, 2), dtype=np.float32)
+        nc = _check(lib().picasso_color_learned(self._h, seed, mlp._m, relation, _ptr(out), _ptr(sched), max_sched))
+        n_it = min(self.stats()["n_iters"], max_sched)
+        return nc, out[: self.n], sched[:n_it].copy()
+
+
+class Mlp:
+    """The 5 -> 64 -> 64 -> 2 parameter predictor on the device (FP32)."""
+
+    def __init__(self, params=None, seed: int = 0):
+        L = lib()
+        if params is not None:
+            params = np.ascontiguousarray(params, dtype=np.float32)
+            assert params.shape == (MLP_NPARAMS,)
+        m = L.picasso_mlp_create(_ptr(params) if params is not None else None, seed)
+        if not m:
+            raise PicassoError(EINVAL, last_error())
+        self._m = ctypes.c_void_p(m)
+
+    def close(self):
+        if getattr(self, "_m", None):
+            lib().picasso_mlp_destroy(self._m)
+            self._m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(MLP_NPARAMS, dtype=np.float32)
+        _check(lib().picasso_mlp_get_params(self._m, _ptr(out)))
+        return out
+
+    def set_params(self, params):
+        params = np.ascontiguousarray(params, dtype=np.float32)
+        _check(lib().picasso_mlp_set_params(self._m, _ptr(params)))
+
+    def forward(self, feats) -> np.ndarray:
+        feats = np.ascontiguousarray(feats, dtype=np.float32).reshape(-1, 5)
+        out = np.zeros((feats.shape[0], 2), dtype=np.float32)
+        _check(lib().picasso_mlp_forward(self._m, _ptr(feats), feats.shape[0], _ptr(out)))
+        return out
+
+    def gradient(self, feats, target):
+        feats = np.ascontiguousarray(feats, dtype=np.float32).reshape(-1, 5)
+        target = np.ascontiguousarray(target, dtype=np.float32).reshape(-1, 2)
+        grad = np.zeros(MLP_NPARAMS, dtype=np.float32)
+        loss = ctypes.c_float()
+        _check(lib().picasso_mlp_gradient(self._m, _ptr(feats), _ptr(target), feats.shape[0], _ptr(grad),
+                                          ctypes.byref(loss)))
+        return loss.value, grad
+
+    def train_step(self, feats, target, lr: float = 1e-3) -> float:
+        feats = np.ascontiguousarray(feats, dtype=np.float32).reshape(-1, 5)
+        target = np.ascontiguousarray(target, dtype=np.float32).reshape(-1, 2)
+        loss = ctypes.c_float()
+        _check(lib().picasso_mlp_train_step(self._m, _ptr(feats), _ptr(target), feats.shape[0], lr,
+                                            ctypes.byref(loss)))
+        return loss.value
+
+
+def squash(o):
+    """Network outputs -> (palette fraction, list multiplier)."""
+    o = np.asarray(o, dtype=np.float64)
+    return 0.01 + 0.24 / (1 + np.exp(-o[..., 0])), 1.0 + 3.0 / (1 + np.exp(-o[..., 1]))
+
+
+def unsquash(frac, alpha):
+    """(palette fraction, list multiplier) -> network targets (inverse of squash)."""
+    u = np.clip((np.asarray(frac, dtype=np.float64) - 0.01) / 0.24, 1e-3, 1 - 1e-3)
+    w = np.clip((np.asarray(alpha, dtype=np.float64) - 1.0) / 3.0, 1e-3, 1 - 1e-3)
+    return np.stack([np.log(u / (1 - u)), np.log(w / (1 - w))], axis=-1)
 
 
 def list_color_csr(prio, lists, P: int, rowptr, adj, handle: Picasso | None = None):

@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <random>
 #include <vector>
 
 #include "common.h"
@@ -79,7 +80,21 @@ struct picasso_ctx {
     picasso_stats stats;
 };
 
+struct picasso_mlp_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    Arena arena;
+    DevBuf params, m1, m2, raw, target, out, keep, row_loss, grad, fa;
+    int32_t step = 0;
+};
+
 namespace {
+
+template <typename T>
+T *mbuf(picasso_mlp_ctx *c, DevBuf &b, size_t count)
+{
+    return static_cast<T *>(c->arena.ensure(b, count * sizeof(T)));
+}
 
 template <typename T>
 T *buf(picasso_ctx *h, DevBuf &b, size_t count)
@@ -205,7 +220,7 @@ BucketInfo build_lists_and_buckets(picasso_ctx *h, uint64_t seed, uint32_t ell, 
 // Relation matrices, duplicate-pair matrices, CSR counts, scan and fill.
 // Returns |E_c|; the CSR is in h->rowptr / h->adj.
 int64_t build_conflict_graph(picasso_ctx *h, int64_t m, int64_t P, int32_t T, int32_t rel, const BucketInfo &bi,
-                             double *ms_relate, double *ms_csr)
+                             double *ms_relate, double *ms_csr, bool *used_mfma = nullptr)
 {
     hipStream_t st = h->stream;
     Timer tm(h);
@@ -227,8 +242,15 @@ int64_t build_conflict_graph(picasso_ctx *h, int64_t m, int64_t P, int32_t T, in
     launch_relate_prep(ra, m * T, buf<uint64_t>(h, h->bx, (size_t)m * T * h->W),
                        buf<uint64_t>(h, h->bz, (size_t)m * T * h->W),
                        buf<int32_t>(h, h->tile_bucket, (size_t)std::max<int64_t>(bi.row_tiles, 1)), st);
+    const bool mfma = h->pair_path == PICASSO_PATH_MFMA ||
+                      (h->pair_path == PICASSO_PATH_AUTO && mfma_supported(h->q, rel));
+    if (mfma && !mfma_supported(h->q, rel))
+        throw Error(PICASSO_EINVAL, "the MFMA pair path does not support this q and relation");
+    ra.mfma_max_members = mfma ? mfma_member_cap(h->q, rel) : -1;
+    if (used_mfma) *used_mfma = mfma;
     tm.mark();
-    launch_relate(ra, st);
+    if (mfma) launch_relate_mfma(ra, h->q, st);
+    if (!mfma || bi.max_size > ra.mfma_max_members) launch_relate(ra, st);
     tm.mark();
     // pairs sharing a smaller colour
     launch_fill_u64(D, bi.words, 0ull, st);
@@ -369,7 +391,42 @@ void download(picasso_ctx *h, void *dst, const void *src, size_t bytes)
 
 void init_ids(picasso_ctx *h, int64_t m);
 
-int64_t color_all(picasso_ctx *h, uint64_t seed, double frac, double alpha, int32_t rel, int32_t *d_out)
+// Features of the current vertex set (ids on the device): exact integer
+// counts from the device, the five values formed on the host in double.
+void device_features(picasso_ctx *h, uint64_t seed, uint32_t ell, int64_t m, const int32_t *d_ids, int32_t rel,
+                     double out[5])
+{
+    unsigned long long *sc = buf<unsigned long long>(h, h->scalars, 8);
+    launch_fill_u64(reinterpret_cast<uint64_t *>(sc + 4), 2, 0ull, h->stream);
+    launch_features(m, d_ids, static_cast<const uint64_t *>(h->x.p), static_cast<const uint64_t *>(h->z.p), h->W,
+                    seed, ell, rel, kFeaturePairs, sc + 4, sc + 5, h->stream);
+    unsigned long long hv[2];
+    PCHECK_HIP(hipMemcpyAsync(hv, sc + 4, sizeof(hv), hipMemcpyDeviceToHost, h->stream));
+    PCHECK_HIP(hipStreamSynchronize(h->stream));
+    out[0] = m > 0 ? std::log((double)m) : 0.0;
+    out[1] = (double)h->q;
+    out[2] = m > 0 ? (double)hv[0] / (double)m : 0.0;
+    out[3] = m >= 2 ? (double)hv[1] / (double)kFeaturePairs : 0.0;
+    out[4] = (double)ell;
+}
+
+// The predictor's (f, alpha) for one feature row, computed on the device.
+void mlp_params_for(picasso_mlp_ctx *mc, hipStream_t st, const double feat[5], float fa_out[2])
+{
+    float raw[5];
+    for (int i = 0; i < 5; ++i) raw[i] = (float)feat[i];
+    float *d_raw = mbuf<float>(mc, mc->raw, 8);
+    float *d_out = mbuf<float>(mc, mc->out, 8);
+    float *d_fa = mbuf<float>(mc, mc->fa, 8);
+    PCHECK_HIP(hipMemcpyAsync(d_raw, raw, sizeof(raw), hipMemcpyHostToDevice, st));
+    launch_mlp_rows(static_cast<const float *>(mc->params.p), d_raw, 1, d_out, nullptr, nullptr, nullptr, st);
+    launch_squash(d_out, 1, d_fa, st);
+    PCHECK_HIP(hipMemcpyAsync(fa_out, d_fa, 2 * sizeof(float), hipMemcpyDeviceToHost, st));
+    PCHECK_HIP(hipStreamSynchronize(st));
+}
+
+int64_t color_all(picasso_ctx *h, uint64_t seed, double frac, double alpha, int32_t rel, int32_t *d_out,
+                  picasso_mlp_ctx *mlp = nullptr, float *sched = nullptr, int32_t max_sched = 0)
 {
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = h->stream;
@@ -384,6 +441,18 @@ int64_t color_all(picasso_ctx *h, uint64_t seed, double frac, double alpha, int3
     while (m > 0) {
         int64_t P;
         int32_t T;
+        if (mlp) {
+            double feat[5];
+            device_features(h, seed, ell, m, static_cast<const int32_t *>(h->ids.p), rel, feat);
+            float fa[2];
+            mlp_params_for(mlp, h->stream, feat, fa);
+            frac = (double)fa[0];
+            alpha = (double)fa[1];
+            if (sched && (int32_t)ell <= max_sched) {
+                sched[2 * (ell - 1)] = fa[0];
+                sched[2 * (ell - 1) + 1] = fa[1];
+            }
+        }
         params(m, frac, alpha, h->fixed_T, P, T);
         if (T > PICASSO_MAX_T) throw Error(PICASSO_EINVAL, "list size " + std::to_string(T) + " exceeds PICASSO_MAX_T");
         if (P > INT32_MAX) throw Error(PICASSO_EINVAL, "palette too large");
@@ -392,14 +461,15 @@ int64_t color_all(picasso_ctx *h, uint64_t seed, double frac, double alpha, int3
         it.P = P;
         it.T = T;
         it.offset = offset;
-        it.pair_path = PICASSO_PATH_VALU;
         Timer tm(h);
         tm.mark();
         const int32_t *d_ids = static_cast<const int32_t *>(h->ids.p);
         const BucketInfo bi = build_lists_and_buckets(h, seed, ell, m, d_ids, P, T);
         it.pair_tests = bi.pair_tests;
         tm.mark();
-        it.edges = build_conflict_graph(h, m, P, T, rel, bi, &it.ms_count, &it.ms_fill);
+        bool used_mfma = false;
+        it.edges = build_conflict_graph(h, m, P, T, rel, bi, &it.ms_count, &it.ms_fill, &used_mfma);
+        it.pair_path = used_mfma ? PICASSO_PATH_MFMA : PICASSO_PATH_VALU;
         tm.mark();
         it.jp_rounds = color_buckets(h, m, P, T, bi);
         tm.mark();
@@ -757,6 +827,204 @@ int64_t picasso_list_color_csr(picasso_handle h, int64_t m, const uint64_t *prio
             int64_t colored = 0;
             for (int64_t i = 0; i < m; ++i) colored += out_col[i] >= 0;
             return colored;
+        },
+        PICASSO_EINTERNAL);
+}
+
+int32_t picasso_features(picasso_handle h, uint64_t seed, int32_t ell, int64_t m, const int32_t *ids,
+                         int32_t relation, double *out)
+{
+    return guarded(
+        [&]() -> int32_t {
+            check_handle(h);
+            check_rel(relation);
+            if (!out) throw Error(PICASSO_EINVAL, "null output");
+            check_subset(h, m, ids, 1, 1);
+            int32_t *d_ids = buf<int32_t>(h, h->ids, (size_t)std::max<int64_t>(m, 1));
+            upload(h, d_ids, ids, (size_t)m * sizeof(int32_t));
+            device_features(h, seed, (uint32_t)ell, m, d_ids, relation, out);
+            return PICASSO_OK;
+        },
+        PICASSO_EINTERNAL);
+}
+
+picasso_mlp picasso_mlp_create(const float *params, uint64_t seed)
+{
+    auto *c = new picasso_mlp_ctx();
+    try {
+        PCHECK_HIP(hipGetDevice(&c->device));
+        PCHECK_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        std::vector<float> init(kMlpParams, 0.0f);
+        if (params) {
+            std::memcpy(init.data(), params, sizeof(float) * kMlpParams);
+        } else {
+            // He-scaled normal weights, zero biases, from a seeded std generator
+            std::mt19937_64 gen(seed);
+            std::normal_distribution<double> nd(0.0, 1.0);
+            const int layers[3][3] = {{0, kMlpHidden * kMlpIn, kMlpIn},
+                                      {kMlpHidden * kMlpIn + kMlpHidden, kMlpHidden * kMlpHidden, kMlpHidden},
+                                      {kMlpHidden * kMlpIn + 2 * kMlpHidden + kMlpHidden * kMlpHidden,
+                                       kMlpOut * kMlpHidden, kMlpHidden}};
+            for (const auto &L : layers) {
+                const double sd = std::sqrt(2.0 / L[2]);
+                for (int i = 0; i < L[1]; ++i) init[L[0] + i] = (float)(nd(gen) * sd);
+            }
+        }
+        float *dp = mbuf<float>(c, c->params, kMlpParams);
+        PCHECK_HIP(hipMemcpyAsync(dp, init.data(), sizeof(float) * kMlpParams, hipMemcpyHostToDevice, c->stream));
+        float *m1 = mbuf<float>(c, c->m1, kMlpParams);
+        float *m2 = mbuf<float>(c, c->m2, kMlpParams);
+        PCHECK_HIP(hipMemsetAsync(m1, 0, sizeof(float) * kMlpParams, c->stream));
+        PCHECK_HIP(hipMemsetAsync(m2, 0, sizeof(float) * kMlpParams, c->stream));
+        PCHECK_HIP(hipStreamSynchronize(c->stream));
+    } catch (const std::exception &e) {
+        set_last_error(e.what());
+        picasso_mlp_destroy(c);
+        return nullptr;
+    }
+    return c;
+}
+
+void picasso_mlp_destroy(picasso_mlp c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    DevBuf *all[] = {&c->params, &c->m1, &c->m2, &c->raw, &c->target, &c->out, &c->keep, &c->row_loss, &c->grad, &c->fa};
+    for (DevBuf *b : all) c->arena.release(*b);
+    if (c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+static void check_mlp(picasso_mlp c)
+{
+    if (!c) throw Error(PICASSO_EINVAL, "null network");
+    PCHECK_HIP(hipSetDevice(c->device));
+}
+
+int32_t picasso_mlp_get_params(picasso_mlp c, float *out)
+{
+    return guarded(
+        [&]() -> int32_t {
+            check_mlp(c);
+            if (!out) throw Error(PICASSO_EINVAL, "null output");
+            PCHECK_HIP(hipMemcpyAsync(out, c->params.p, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost, c->stream));
+            PCHECK_HIP(hipStreamSynchronize(c->stream));
+            return PICASSO_OK;
+        },
+        PICASSO_EINTERNAL);
+}
+
+int32_t picasso_mlp_set_params(picasso_mlp c, const float *in)
+{
+    return guarded(
+        [&]() -> int32_t {
+            check_mlp(c);
+            if (!in) throw Error(PICASSO_EINVAL, "null input");
+            PCHECK_HIP(hipMemcpyAsync(c->params.p, in, sizeof(float) * kMlpParams, hipMemcpyHostToDevice, c->stream));
+            PCHECK_HIP(hipMemsetAsync(c->m1.p, 0, sizeof(float) * kMlpParams, c->stream));
+            PCHECK_HIP(hipMemsetAsync(c->m2.p, 0, sizeof(float) * kMlpParams, c->stream));
+            PCHECK_HIP(hipStreamSynchronize(c->stream));
+            c->step = 0;
+            return PICASSO_OK;
+        },
+        PICASSO_EINTERNAL);
+}
+
+int32_t picasso_mlp_forward(picasso_mlp c, const float *features, int32_t B, float *out)
+{
+    return guarded(
+        [&]() -> int32_t {
+            check_mlp(c);
+            if (B < 0 || (B > 0 && (!features || !out))) throw Error(PICASSO_EINVAL, "bad batch");
+            if (B == 0) return PICASSO_OK;
+            float *d_raw = mbuf<float>(c, c->raw, (size_t)B * kMlpIn);
+            float *d_out = mbuf<float>(c, c->out, (size_t)B * kMlpOut);
+            PCHECK_HIP(hipMemcpyAsync(d_raw, features, sizeof(float) * B * kMlpIn, hipMemcpyHostToDevice, c->stream));
+            launch_mlp_rows(static_cast<const float *>(c->params.p), d_raw, B, d_out, nullptr, nullptr, nullptr,
+                            c->stream);
+            PCHECK_HIP(hipMemcpyAsync(out, d_out, sizeof(float) * B * kMlpOut, hipMemcpyDeviceToHost, c->stream));
+            PCHECK_HIP(hipStreamSynchronize(c->stream));
+            return PICASSO_OK;
+        },
+        PICASSO_EINTERNAL);
+}
+
+// Forward with training state, then the gradient; returns the batch loss.
+static float mlp_gradient_impl(picasso_mlp c, const float *features, const float *target, int32_t B)
+{
+    if (B <= 0 || !features || !target) throw Error(PICASSO_EINVAL, "bad batch");
+    float *d_raw = mbuf<float>(c, c->raw, (size_t)B * kMlpIn);
+    float *d_t = mbuf<float>(c, c->target, (size_t)B * kMlpOut);
+    float *d_keep = mbuf<float>(c, c->keep, (size_t)B * kMlpKeep);
+    float *d_loss = mbuf<float>(c, c->row_loss, (size_t)B);
+    float *d_grad = mbuf<float>(c, c->grad, kMlpParams);
+    PCHECK_HIP(hipMemcpyAsync(d_raw, features, sizeof(float) * B * kMlpIn, hipMemcpyHostToDevice, c->stream));
+    PCHECK_HIP(hipMemcpyAsync(d_t, target, sizeof(float) * B * kMlpOut, hipMemcpyHostToDevice, c->stream));
+    launch_mlp_rows(static_cast<const float *>(c->params.p), d_raw, B, nullptr, d_t, d_keep, d_loss, c->stream);
+    launch_mlp_grad(d_keep, B, d_grad, c->stream);
+    std::vector<float> rl(B);
+    PCHECK_HIP(hipMemcpyAsync(rl.data(), d_loss, sizeof(float) * B, hipMemcpyDeviceToHost, c->stream));
+    PCHECK_HIP(hipStreamSynchronize(c->stream));
+    double loss = 0.0;
+    for (float v : rl) loss += v;
+    return (float)loss;
+}
+
+int32_t picasso_mlp_gradient(picasso_mlp c, const float *features, const float *target, int32_t B, float *grad,
+                             float *loss)
+{
+    return guarded(
+        [&]() -> int32_t {
+            check_mlp(c);
+            const float l = mlp_gradient_impl(c, features, target, B);
+            if (loss) *loss = l;
+            if (grad) {
+                PCHECK_HIP(hipMemcpyAsync(grad, c->grad.p, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost, c->stream));
+                PCHECK_HIP(hipStreamSynchronize(c->stream));
+            }
+            return PICASSO_OK;
+        },
+        PICASSO_EINTERNAL);
+}
+
+int32_t picasso_mlp_train_step(picasso_mlp c, const float *features, const float *target, int32_t B, float lr,
+                               float *loss)
+{
+    return guarded(
+        [&]() -> int32_t {
+            check_mlp(c);
+            if (!(lr > 0.0f)) throw Error(PICASSO_EINVAL, "learning rate must be > 0");
+            const float l = mlp_gradient_impl(c, features, target, B);
+            ++c->step;
+            launch_adam(static_cast<float *>(c->params.p), static_cast<const float *>(c->grad.p),
+                        static_cast<float *>(c->m1.p), static_cast<float *>(c->m2.p), lr, 0.9f, 0.999f, 1e-8f,
+                        c->step, c->stream);
+            PCHECK_HIP(hipStreamSynchronize(c->stream));
+            if (loss) *loss = l;
+            return PICASSO_OK;
+        },
+        PICASSO_EINTERNAL);
+}
+
+int64_t picasso_color_learned(picasso_handle h, uint64_t seed, picasso_mlp mlp, int32_t relation,
+                              int32_t *out_colors, float *out_schedule, int32_t max_sched)
+{
+    return guarded(
+        [&]() -> int64_t {
+            check_handle(h);
+            check_rel(relation);
+            if (!mlp) throw Error(PICASSO_EINVAL, "null network");
+            if (h->n > 0 && !out_colors) throw Error(PICASSO_EINVAL, "null output");
+            if (mlp->device != h->device) throw Error(PICASSO_EINVAL, "network and handle on different devices");
+            if (h->n == 0) {
+                std::memset(&h->stats, 0, sizeof(h->stats));
+                return 0;
+            }
+            int32_t *d_out = buf<int32_t>(h, h->out_colors, (size_t)h->n);
+            const int64_t nc = color_all(h, seed, 0.125, 2.0, relation, d_out, mlp, out_schedule, max_sched);
+            download(h, out_colors, d_out, (size_t)h->n * sizeof(int32_t));
+            return nc;
         },
         PICASSO_EINTERNAL);
 }

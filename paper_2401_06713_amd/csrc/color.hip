@@ -63,25 +63,16 @@ __device__ __forceinline__ bool any_below(const uint64_t *m, int k)
     return false;
 }
 
-__device__ __forceinline__ uint8_t load_st(const uint8_t *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Put bucket c2 on the next round's worklist unless it is already waiting.
+// The wave first waits for its own outstanding memory operations, so the
+// state change that causes the wake is complete (state is written with
+// coherent stores and atomics) before the bucket can be taken off a list.
+// No cache flush or invalidate is needed: readers use coherent loads.
 __device__ __forceinline__ void wake(const JpArgs &a, int64_t c2, int32_t *out, int32_t *out_count)
 {
-    if (__hip_atomic_exchange(&a.dirty[c2], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+    __builtin_amdgcn_s_waitcnt(0);
+    if (__hip_atomic_exchange(&a.dirty[c2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
         out[atomicAdd(out_count, 1)] = (int32_t)c2;
-}
-
-// Wake the buckets of v's still-unresolved slots in [from, T) other than skip.
-__device__ void wake_open_slots(const JpArgs &a, int64_t v, int from, int skip, int32_t *out, int32_t *out_count)
-{
-    for (int k2 = from; k2 < a.T; ++k2) {
-        if (k2 == skip) continue;
-        if (load_st(&a.st[a.pos_of[v * a.T + k2]]) == ST_UNKNOWN) wake(a, a.lists[v * a.T + k2], out, out_count);
-    }
 }
 
 // First slot of v not known blocked (T if all are).
@@ -97,21 +88,33 @@ __device__ __forceinline__ int first_open(const uint64_t *blk, int T)
     return T;
 }
 
-// Resolve what can be resolved in bucket c (passes until nothing changes);
-// state changes that may unblock other buckets wake them.
-__device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t *tak, uint64_t *unk, int *changed_any,
-                               int32_t *out, int32_t *out_count)
+constexpr int kJpStage = 1024;  // members whose (vertex, slot) are staged in LDS
+
+// Resolve what can be resolved in bucket c (passes until nothing changes).
+// Cross-bucket effects wake the buckets they may unblock:
+//  - a slot of v found free for the first time: v will not take any later
+//    slot, so the buckets of v's later slots are woken;
+//  - a blocked slot that completes v's blocked prefix up to slot f: the
+//    bucket of f is woken (v may now take it).
+// Taking a colour needs no wake of its own: the slot was found free first.
+__device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t *tak, uint64_t *unk, uint32_t *mv,
+                               uint8_t *mk, int *changed_any, int32_t *out, int32_t *out_count)
 {
     const int lane = threadIdx.x;
     const int64_t base = a.bstart[c];
     const int64_t S = a.bstart[c + 1] - base;
     const int64_t nw = (S + 63) >> 6;
     const uint64_t *Rm = a.R + a.rb_off[c];
+    const bool staged = S <= kJpStage;
     __syncthreads();
     for (int64_t w = lane; w < nw; w += kWave) tak[w] = unk[w] = 0ull;
     __syncthreads();
     for (int64_t p = lane; p < S; p += kWave) {
         const uint8_t s = a.st[base + p];
+        if (staged) {
+            mv[p] = a.bmem[base + p];
+            mk[p] = a.bslot[base + p];
+        }
         if (s == ST_UNKNOWN) atomicOr((unsigned long long *)&unk[p >> 6], 1ull << (p & 63));
         else if (s == ST_TAKEN) atomicOr((unsigned long long *)&tak[p >> 6], 1ull << (p & 63));
     }
@@ -122,8 +125,10 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t *tak, uint64
         for (int64_t p = lane; p < S; p += kWave) {
             const uint64_t bit = 1ull << (p & 63);
             if (!(unk[p >> 6] & bit)) continue;
-            const int64_t v = a.bmem[base + p];
-            const int k = a.bslot[base + p];
+            const int64_t v = staged ? mv[p] : a.bmem[base + p];
+            const int k = staged ? mk[p] : a.bslot[base + p];
+            uint64_t *blk = a.blk + v * a.fw;
+            uint64_t *fre = a.fre + v * a.fw;
             const int32_t cv = load_i32(&a.col[v]);
             uint8_t ns = ST_UNKNOWN;
             if (cv != COL_UNDECIDED) {
@@ -137,30 +142,37 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t *tak, uint64
                     hit_tak |= (r & tak[w]) != 0ull;
                     hit_unk |= (r & unk[w]) != 0ull;
                 }
-                uint64_t *blk = a.blk + v * a.fw;
-                uint64_t *fre = a.fre + v * a.fw;
                 if (hit_tak) {
                     ns = ST_NOT;
-                    atomicOr((unsigned long long *)&blk[k >> 6], 1ull << (k & 63));
+                    const uint64_t kb = 1ull << (k & 63);
+                    const uint64_t old = atomicOr((unsigned long long *)&blk[k >> 6], kb);
                     if (atomicAdd(&a.nblk[v], 1) == a.T - 1) {  // the last slot was blocked
                         __hip_atomic_store(&a.col[v], COL_FAILED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         atomicAdd(a.progress, 1ull);
                     } else {
-                        // the blocked prefix may now reach a free slot
-                        const int f = first_open(blk, a.T);
+                        int f;
+                        if (a.fw == 1) {
+                            const uint64_t nb = ~(old | kb);
+                            f = nb ? __builtin_ctzll(nb) : 64;
+                        } else {
+                            f = first_open(blk, a.T);
+                        }
                         if (f > k && f < a.T) wake(a, a.lists[v * a.T + f], out, out_count);
                     }
                 } else if (any_below(fre, k)) {
                     ns = ST_NOT;  // an earlier slot is free: v takes that colour or an earlier one
                 } else if (!hit_unk) {
-                    const uint64_t was = atomicOr((unsigned long long *)&fre[k >> 6], 1ull << (k & 63));
+                    const uint64_t kb = 1ull << (k & 63);
+                    const uint64_t was = atomicOr((unsigned long long *)&fre[k >> 6], kb);
                     if (all_below(blk, k)) {
                         __hip_atomic_store(&a.col[v], (int32_t)c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         atomicAdd(a.progress, 1ull);
                         ns = ST_TAKEN;
                     }
-                    if (!(was & (1ull << (k & 63))) || ns == ST_TAKEN)
-                        wake_open_slots(a, v, ns == ST_TAKEN ? 0 : k + 1, k, out, out_count);
+                    if (!(was & kb)) {
+                        const uint32_t *Lv = a.lists + v * a.T;
+                        for (int k2 = k + 1; k2 < a.T; ++k2) wake(a, Lv[k2], out, out_count);
+                    }
                 }
             }
             if (ns != ST_UNKNOWN) {
@@ -187,6 +199,8 @@ __global__ void __launch_bounds__(kWave) jp_round_kernel(JpArgs a, int cur)
     extern __shared__ uint64_t sbits[];  // taken[nw_max], unknown[nw_max]
     uint64_t *tak = sbits;
     uint64_t *unk = sbits + a.nw_max;
+    __shared__ uint32_t mv[kJpStage];
+    __shared__ uint8_t mk[kJpStage];
     __shared__ int changed_any;
     __shared__ int go;
     const int32_t n_in = a.wl_count[cur];
@@ -195,9 +209,9 @@ __global__ void __launch_bounds__(kWave) jp_round_kernel(JpArgs a, int cur)
     for (int64_t i = blockIdx.x; i < n_in; i += gridDim.x) {
         const int64_t c = a.wl[cur][i];
         if (threadIdx.x == 0)
-            go = __hip_atomic_exchange(&a.dirty[c], 0u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+            go = __hip_atomic_exchange(&a.dirty[c], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
         __syncthreads();
-        if (go) resolve_bucket(a, c, tak, unk, &changed_any, out, out_count);
+        if (go) resolve_bucket(a, c, tak, unk, mv, mk, &changed_any, out, out_count);
         __syncthreads();
     }
 }

@@ -119,11 +119,18 @@ struct RelateArgs {
     uint64_t *R;              // relation bit matrices
     const uint64_t *bx, *bz;  // member strings in bucket order (set by launch_relate_prep)
     const int32_t *tile_bucket;  // owner bucket of each row tile (set by launch_relate_prep)
+    int64_t mfma_max_members;    // buckets up to this size go to the MFMA kernel (-1: none)
 };
 // Gathers member strings into bucket order and the row-tile owners.
 void launch_relate_prep(RelateArgs &a, int64_t entries, uint64_t *bx, uint64_t *bz, int32_t *tile_bucket,
                         hipStream_t st);
 void launch_relate(const RelateArgs &a, hipStream_t st);
+// int8 MFMA relation path: whether q and the relation fit it, the largest
+// bucket it takes, and the launch (buckets above the cap stay on the VALU
+// kernel, which skips the buckets at or below it).
+bool mfma_supported(int32_t q, int32_t relation);
+int64_t mfma_member_cap(int32_t q, int32_t relation);
+void launch_relate_mfma(const RelateArgs &a, int32_t q, hipStream_t st);
 
 struct DupArgs {
     const int64_t *bstart;
@@ -192,5 +199,23 @@ void launch_finish_iteration(int64_t m, const int32_t *col, const int32_t *ids, 
                              uint32_t *used_bits, unsigned long long *n_used, int32_t *uncol_flag, hipStream_t st);
 void launch_compact_ids(int64_t m, const int32_t *ids, const int32_t *flag, const int64_t *pos, int32_t *next_ids,
                         hipStream_t st);
+
+// learned.hip: features of the current vertex set and the predictor network.
+constexpr int kMlpIn = 5, kMlpHidden = 64, kMlpOut = 2;
+constexpr int kMlpParams = kMlpHidden * kMlpIn + kMlpHidden + kMlpHidden * kMlpHidden + kMlpHidden +
+                           kMlpOut * kMlpHidden + kMlpOut;
+constexpr int kMlpKeep = kMlpIn + 2 * kMlpHidden + kMlpOut + 2 * kMlpHidden;  // per-row training state
+constexpr int kFeaturePairs = 4096;
+void launch_features(int64_t m, const int32_t *ids, const uint64_t *x, const uint64_t *z, int32_t W, uint64_t seed,
+                     uint32_t ell, int32_t rel, int32_t K, unsigned long long *weight, unsigned long long *hits,
+                     hipStream_t st);
+// Forward pass over B rows (out: B x 2 raw outputs, may be null); with
+// target/keep/row_loss non-null it also stores the training state.
+void launch_mlp_rows(const float *p, const float *raw, int32_t B, float *out, const float *target, float *keep,
+                     float *row_loss, hipStream_t st);
+void launch_mlp_grad(const float *keep, int32_t B, float *grad, hipStream_t st);
+void launch_adam(float *p, const float *g, float *m1, float *m2, float lr, float b1, float b2, float eps, int32_t step,
+                 hipStream_t st);
+void launch_squash(const float *o, int32_t B, float *fa, hipStream_t st);
 
 }  // namespace picasso

@@ -119,6 +119,7 @@ __global__ void __launch_bounds__(kWave * kRelWaves) relate_kernel(RelateArgs a)
         const int64_t rt = item - a.tile_off[c];
         const int64_t base = a.bstart[c];
         const int64_t S = a.bstart[c + 1] - base;
+        if (S <= a.mfma_max_members) continue;  // done by the MFMA kernel
         const int64_t nw = (S + 63) >> 6;
         uint64_t *Rm = a.R + a.rb_off[c];
         const int64_t i = rt * kWave + lane;
@@ -172,6 +173,110 @@ __global__ void __launch_bounds__(kWave * kRelWaves) relate_kernel(RelateArgs a)
             if (i < S) Rm[i * nw + ct] = row;
             if (j < S) Rm[j * nw + rt] = col;
         }
+    }
+}
+
+// ---- int8 MFMA relation path ------------------------------------------------
+// The relation as an integer matrix product.  Per qubit k, with 0/1 bytes:
+//  ANTICOMMUTE: A_i = [x_i | z_i], B_j = [z_j | x_j];
+//    (A B^T)[i][j] = sum_k x_ik z_jk + z_ik x_jk, whose parity is the
+//    parity of the anticommuting positions (Eq. 5 and the parity rule).
+//  QWC: A_i = [n_i | X_i | Y_i | Z_i] (n = non-identity, X/Y/Z one-hot),
+//    B_j = [n_j | -X_j | -Y_j | -Z_j]; (A B^T)[i][j] = #(both non-identity)
+//    - #(equal non-identity) > 0 exactly when some position holds two
+//    different non-identity Paulis.
+// One workgroup per bucket (buckets up to kMfmaMembers): the members are
+// unpacked once into LDS rows of K bytes (each plane padded to a multiple of
+// 16 qubits, so the swapped/negated B halves are contiguous 16-byte reads),
+// then the four waves compute every 32 x 32 tile with
+// v_mfma_i32_32x32x32_i8.  Lane l holds column j = l % 32 of a tile, i.e. by
+// symmetry 16 bits of row j; two half-waves combine them into the row's
+// 32-bit chunk for the tile's rows.  A and B fragments place bytes at the same
+// (lane half, byte) positions, so the K order the hardware uses cancels out.
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+constexpr int kMfmaThreads = 256;
+constexpr int kMfmaLds = 64 * 1024;   // bytes of unpacked member rows per bucket
+constexpr int kMfmaMembers = 512;
+
+// 4 bits of w starting at bit b -> 4 bytes of 0/1.
+__device__ __forceinline__ uint32_t spread4(uint64_t w, int b)
+{
+    const uint32_t t = (uint32_t)(w >> b) & 0xFu;
+    return (t * 0x00204081u) & 0x01010101u;
+}
+
+template <int REL>
+__global__ void __launch_bounds__(kMfmaThreads) relate_mfma_kernel(RelateArgs a, int32_t qpad, int32_t kbytes)
+{
+    extern __shared__ uint32_t rows32[];  // S rows of kbytes
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int kd = kbytes >> 2;           // dwords per row
+    for (int64_t c = blockIdx.x; c < a.P; c += gridDim.x) {
+        const int64_t base = a.bstart[c];
+        const int64_t S = a.bstart[c + 1] - base;
+        if (S < 2 || S > a.mfma_max_members) continue;
+        const int nt = (int)((S + 31) >> 5);
+        const int Sp = nt * 32;           // padded rows (zero strings)
+        __syncthreads();
+        // unpack: dword d of row r holds qubits 4d..4d+3 of one block
+        for (int e = t; e < Sp * kd; e += kMfmaThreads) {
+            const int r = e / kd, d = e - r * kd;
+            uint32_t val = 0u;
+            if (r < S) {
+                const int blk = (4 * d) / qpad;          // which block of qpad bytes
+                const int q0 = 4 * d - blk * qpad;       // first qubit of the dword
+                const int w = q0 >> 6, b = q0 & 63;      // q0 % 4 == 0, so 4 bits stay in one word
+                if (w < a.W) {
+                    const uint64_t xv = a.bx[(base + r) * a.W + w], zv = a.bz[(base + r) * a.W + w];
+                    if (REL == PICASSO_REL_ANTICOMMUTE) {
+                        val = spread4(blk == 0 ? xv : zv, b);
+                    } else {
+                        const uint64_t pick = blk == 0 ? (xv | zv) : blk == 1 ? (xv & ~zv) : blk == 2 ? (xv & zv) : (zv & ~xv);
+                        val = spread4(pick, b);
+                    }
+                }
+            }
+            rows32[e] = val;
+        }
+        __syncthreads();
+        const char *rows = reinterpret_cast<const char *>(rows32);
+        const int half = lane >> 5, l32 = lane & 31;
+        uint32_t *R32 = reinterpret_cast<uint32_t *>(a.R + a.rb_off[c]);
+        const int64_t cpr = 2 * ((S + 63) >> 6);  // 32-bit chunks per row
+        for (int tile = wave; tile < nt * nt; tile += kMfmaThreads / 64) {
+            const int rt = tile / nt, ct = tile - rt * nt;
+            const char *ra = rows + (int64_t)(rt * 32 + l32) * kbytes;
+            const char *rb = rows + (int64_t)(ct * 32 + l32) * kbytes;
+            v16i acc = {0};
+            for (int kk = 0; kk < kbytes; kk += 32) {
+                const int off = kk + 16 * half;
+                const v4i av = *reinterpret_cast<const v4i *>(ra + off);
+                v4i bv;
+                if (REL == PICASSO_REL_ANTICOMMUTE) {
+                    const int boff = off < qpad ? off + qpad : off - qpad;  // [z | x]
+                    bv = *reinterpret_cast<const v4i *>(rb + boff);
+                } else {
+                    bv = *reinterpret_cast<const v4i *>(rb + off);
+                    if (off >= qpad) bv = bv * 255;  // 0/1 bytes -> 0/-1 bytes
+                }
+                acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(av, bv, acc, 0, 0, 0);
+            }
+            // lane holds D[i][j] for column j = ct*32 + l32 and rows
+            // i = rt*32 + 8*(r/4) + 4*half + r%4
+            uint32_t m = 0u;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const uint32_t bitv = REL == PICASSO_REL_ANTICOMMUTE ? ((uint32_t)acc[r] & 1u) : (acc[r] > 0 ? 1u : 0u);
+                m |= bitv << (8 * (r >> 2) + 4 * half + (r & 3));
+            }
+            m |= (uint32_t)__shfl_xor((int)m, 32, 64);
+            const int64_t j = (int64_t)ct * 32 + l32;
+            if (half == 0 && j < S) R32[j * cpr + rt] = m;
+        }
+        // the last chunk of a row past the padded tiles (odd tile count)
+        if (nt & 1)
+            for (int64_t j = t; j < S; j += kMfmaThreads) R32[j * cpr + nt] = 0u;
     }
 }
 
@@ -518,6 +623,36 @@ void launch_relate(const RelateArgs &a, hipStream_t st)
             throw Error(PICASSO_EINTERNAL, "relate kernel: unsupported word count");
     }
 #undef PICASSO_REL_CASE
+    PCHECK_LAUNCH();
+}
+
+bool mfma_supported(int32_t q, int32_t relation)
+{
+    const int32_t qpad = (q + 15) / 16 * 16;
+    const int32_t kbytes = relation == PICASSO_REL_ANTICOMMUTE ? 2 * qpad : 4 * qpad;
+    return kbytes % 32 == 0 && (int64_t)32 * kbytes <= kMfmaLds;
+}
+
+int64_t mfma_member_cap(int32_t q, int32_t relation)
+{
+    const int32_t qpad = (q + 15) / 16 * 16;
+    const int32_t kbytes = relation == PICASSO_REL_ANTICOMMUTE ? 2 * qpad : 4 * qpad;
+    const int64_t fit = (int64_t)kMfmaLds / kbytes / 32 * 32;
+    return fit < kMfmaMembers ? fit : kMfmaMembers;
+}
+
+void launch_relate_mfma(const RelateArgs &a, int32_t q, hipStream_t st)
+{
+    if (a.P <= 0) return;
+    const int32_t qpad = (q + 15) / 16 * 16;
+    const int32_t kbytes = a.relation == PICASSO_REL_ANTICOMMUTE ? 2 * qpad : 4 * qpad;
+    const int64_t cap = mfma_member_cap(q, a.relation);
+    const size_t lds = (size_t)((cap + 31) / 32 * 32) * kbytes;
+    const unsigned grid = grid_cap(a.P, 1 << 20);
+    if (a.relation == PICASSO_REL_ANTICOMMUTE)
+        relate_mfma_kernel<PICASSO_REL_ANTICOMMUTE><<<grid, kMfmaThreads, lds, st>>>(a, qpad, kbytes);
+    else
+        relate_mfma_kernel<PICASSO_REL_QWC><<<grid, kMfmaThreads, lds, st>>>(a, qpad, kbytes);
     PCHECK_LAUNCH();
 }
 

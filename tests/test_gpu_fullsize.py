@@ -64,16 +64,18 @@ def check_valid(x, z, col, rel):
     assert not relation_np(x, z, a, b, rel).any()
 
 
-@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
-def test_c2_matches_oracle(seed):
-    path = os.path.join(GOLDEN, f"c2_seed{seed}.json")
-    if not os.path.exists(path):
+@pytest.mark.parametrize("seed,path", [(0, pk.PATH_AUTO), (1, pk.PATH_AUTO), (2, pk.PATH_AUTO), (3, pk.PATH_AUTO),
+                                       (4, pk.PATH_AUTO), (0, pk.PATH_VALU), (1, pk.PATH_MFMA)])
+def test_c2_matches_oracle(seed, path):
+    gpath = os.path.join(GOLDEN, f"c2_seed{seed}.json")
+    if not os.path.exists(gpath):
         pytest.skip(f"no stored oracle result for seed {seed}")
-    g = json.load(open(path))
+    g = json.load(open(gpath))
     cfg = wl.C2
-    say("C2 seed", seed)
+    say("C2 seed", seed, "path", path)
     x, z = wl.make(cfg)
     with pk.Picasso(x, z, cfg.q) as h:
+        h.set_option(pk.OPT_PAIR_PATH, path)
         nc, col = h.color(seed, cfg.frac, cfg.alpha, cfg.relation)
         st = h.stats()
     assert nc == g["n_colors"]
@@ -83,4 +85,6 @@ def test_c2_matches_oracle(seed):
     for a, b in zip(st["iters"], g["iters"]):
         for k in ("m", "P", "T", "pair_tests", "edges", "colored", "offset"):
             assert a[k] == b[k], (k, a[k], b[k])
+        if path != pk.PATH_AUTO:
+            assert a["pair_path"] == path
     check_valid(x, z, col, cfg.relation)

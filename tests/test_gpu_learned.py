@@ -1,0 +1,122 @@
+"""Learned parameters on the HIP path vs the oracle's FP64 twin.
+
+Features are integer counts: bit-exact.  The FP32 network is checked against
+the FP64 oracle network with the same weights: outputs within 1e-4 relative
+(the bar set for the predictor), gradients within 1e-3 relative (a reading:
+the FP32 sums over a batch).  A learned colouring is bit-exact against the
+oracle fed the same FP32 (f, alpha) schedule.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2401_06713_amd as pk
+from paper_2401_06713_amd import learn
+from paper_2401_06713_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("rel", [0, 1])
+@pytest.mark.parametrize("n,q,probs", [(3000, 40, (0.7, 0.1, 0.1, 0.1)), (1500, 130, (0.8, 0.2 / 3, 0.2 / 3, 0.2 / 3)),
+                                       (1, 10, (0.5, 0.2, 0.2, 0.1))])
+def test_features_bit_exact(orc, rel, n, q, probs):
+    say("features", rel, n, q)
+    x, z = wl.pauli_strings(n, q, probs, seed=n)
+    with pk.Picasso(x, z, q) as h:
+        for ell, ids in ((1, np.arange(n, dtype=np.int32)),
+                         (4, np.sort(np.random.default_rng(1).choice(n, max(1, n // 3), replace=False)).astype(np.int32))):
+            got = h.features(77, ell, ids, rel)
+            ref = orc.features(x, z, q, ids, 77, ell, rel)
+            assert np.array_equal(got, ref), (got, ref)
+
+
+def random_rows(rng, B):
+    return (rng.random((B, 5)) * np.array([15, 128, 64, 1, 12])).astype(np.float32)
+
+
+def test_forward_within_1e4_of_fp64(orc):
+    rng = np.random.default_rng(0)
+    for seed in range(3):
+        with pk.Mlp(seed=seed) as m:
+            p = m.get_params()
+            rows = random_rows(rng, 333)
+            o = m.forward(rows)
+        ref = orc.mlp_forward(p.astype(np.float64), rows.astype(np.float64))
+        assert np.all(np.abs(o - ref) <= 1e-4 * np.maximum(1.0, np.abs(ref)))
+        f, a = pk.squash(o)
+        fr, ar = pk.squash(ref)
+        assert np.all(np.abs(f - fr) <= 1e-4 * fr) and np.all(np.abs(a - ar) <= 1e-4 * ar)
+
+
+def test_gradient_within_1e3_of_fp64(orc):
+    rng = np.random.default_rng(1)
+    with pk.Mlp(seed=5) as m:
+        p = m.get_params()
+        rows = random_rows(rng, 200)
+        t = rng.normal(0, 1, (200, 2)).astype(np.float32)
+        loss, g = m.gradient(rows, t)
+    rloss, rg = orc.mlp_loss_grad(p.astype(np.float64), rows.astype(np.float64), t.astype(np.float64))
+    assert abs(loss - rloss) <= 1e-4 * max(1.0, rloss)
+    assert np.linalg.norm(g - rg) <= 1e-3 * np.linalg.norm(rg)
+    assert np.all(np.abs(g - rg) <= 1e-3 * np.maximum(np.abs(rg), 1e-3 * np.abs(rg).max()))
+
+
+def test_adam_step_matches_fp64(orc):
+    rng = np.random.default_rng(2)
+    with pk.Mlp(seed=9) as m:
+        p0 = m.get_params()
+        rows = random_rows(rng, 64)
+        t = rng.normal(0, 1, (64, 2)).astype(np.float32)
+        m.train_step(rows, t, 1e-2)
+        p1 = m.get_params()
+    p = p0.astype(np.float64)
+    _, g = orc.mlp_loss_grad(p, rows.astype(np.float64), t.astype(np.float64))
+    mm, vv = np.zeros_like(p), np.zeros_like(p)
+    orc.adam_step(p, g, mm, vv, 1, lr=1e-2)
+    # first Adam step moves every parameter by ~lr * sign(g); tiny gradients are
+    # sign-sensitive in FP32, so compare where the step is well determined
+    sure = np.abs(g) > 1e-4 * np.abs(g).max()
+    assert np.allclose(p1[sure], p[sure], atol=1e-5)
+
+
+@pytest.mark.parametrize("rel", [0, 1])
+def test_learned_colouring_bit_exact(orc, rel):
+    n, q = 4000, 48
+    x, z = wl.pauli_strings(n, q, (0.7, 0.1, 0.1, 0.1), seed=11 + rel)
+    with pk.Mlp(seed=3) as m, pk.Picasso(x, z, q) as h:
+        nc, col, sched = h.color_learned(m, 5, rel)
+        st = h.stats()
+        p = m.get_params().astype(np.float64)
+    assert sched.shape[0] == st["n_iters"]
+    rnc, rcol, rst = orc.color_schedule(x, z, q, 5, sched[:, 0].astype(np.float64), sched[:, 1].astype(np.float64),
+                                        rel)
+    assert nc == rnc and np.array_equal(col, rcol)
+    # the schedule is the FP64 twin's output on the oracle's features, to 1e-4
+    for k, it in enumerate(rst):
+        ids = np.nonzero(rcol >= it["offset"])[0].astype(np.int32)
+        feat = orc.features(x, z, q, ids, 5, k + 1, rel)
+        f, a = orc.mlp_squash(orc.mlp_forward(p, feat[None, :])[0])
+        assert abs(sched[k, 0] - f) <= 1e-4 * f and abs(sched[k, 1] - a) <= 1e-4 * a
+
+
+def test_trained_predictor_gains_over_fixed():
+    """Sweeps over small training instances, training on the device, and a
+    held-out evaluation: the learned parameters must beat the fixed ones on the
+    sweep objective (colours and largest conflict graph, equal weight)."""
+    train_cfgs = learn.training_instances(24, seed=2000, n_lo=1000, n_hi=8000)
+    X, Y, recs = learn.sweep(train_cfgs, 0.5, grid_f=(0.04, 0.08, 0.125, 0.2), grid_a=(1.0, 2.0, 3.0), log=say)
+    mlp, loss = learn.train(X, Y, steps=1500, batch=128, lr=3e-3, log=say)
+    held = learn.training_instances(6, seed=9000, n_lo=3000, n_hi=8000)
+    res = learn.evaluate(mlp, held)
+    J = [r["J_learned"] for r in res]
+    say("held-out J (fixed = 1):", np.round(J, 3))
+    assert np.mean(J) < 1.0
+    assert np.mean([r["learned"]["colors"] / r["fixed"]["colors"] for r in res]) <= 1.05
+    mlp.close()

@@ -60,6 +60,10 @@ def gpu_edges(h, seed, ell, ids, P, T, rel):
     return e
 
 
+_ORACLE_EDGES = {}
+
+
+@pytest.mark.parametrize("path", [pk.PATH_VALU, pk.PATH_MFMA])
 @pytest.mark.parametrize("rel", [0, 1])
 @pytest.mark.parametrize("n,q,probs,P,T", [
     (2000, 16, (0.25, 0.25, 0.25, 0.25), 250, 16),    # C1 iteration 1
@@ -73,15 +77,19 @@ def gpu_edges(h, seed, ell, ids, P, T, rel):
     (1500, 24, (0.6, 0.1, 0.2, 0.1), 100, 64),              # long prefixes: several hash passes
     (1200, 24, (0.6, 0.1, 0.2, 0.1), 300, 200),             # T near the limit, multi-word slot masks
 ])
-def test_conflict_graph_bit_exact(orc, rel, n, q, probs, P, T):
-    say("graph", rel, n, q, P, T)
+def test_conflict_graph_bit_exact(orc, path, rel, n, q, probs, P, T):
+    say("graph", path, rel, n, q, P, T)
     x, z = strings(n, q, probs, seed=q)
     ids = np.sort(np.random.default_rng(q).choice(n, n - n // 5, replace=False)).astype(np.int32)
     with pk.Picasso(x, z, q) as h:
+        h.set_option(pk.OPT_PAIR_PATH, path)
         got = gpu_edges(h, 99, 2, ids, P, T, rel)
-    ch = orc.decode(x, z, q)
-    lists = orc.sample_lists(99, 2, ids, P, T)
-    ref, cnt, _ = orc.conflict_edges_bucketed(ch, ids, lists, P, rel)
+    key = (rel, n, q, P, T)
+    if key not in _ORACLE_EDGES:
+        ch = orc.decode(x, z, q)
+        lists = orc.sample_lists(99, 2, ids, P, T)
+        _ORACLE_EDGES[key] = orc.conflict_edges_bucketed(ch, ids, lists, P, rel)[:2]
+    ref, cnt = _ORACLE_EDGES[key]
     assert cnt == len(got)
     assert np.array_equal(got, ref)
 
@@ -113,8 +121,9 @@ def test_jp_equals_sequential_greedy(orc, seed):
 
 
 # ---------------------------------------------------------------- whole method
-def run_both(orc, x, z, q, seed, frac, alpha, rel, fixed_T=0):
+def run_both(orc, x, z, q, seed, frac, alpha, rel, fixed_T=0, path=pk.PATH_AUTO):
     with pk.Picasso(x, z, q) as h:
+        h.set_option(pk.OPT_PAIR_PATH, path)
         if fixed_T:
             h.set_option(pk.OPT_FIXED_T, fixed_T)
         nc, col = h.color(seed, frac, alpha, rel)
@@ -148,7 +157,8 @@ def test_c1_bit_exact(orc):
 def test_color_bit_exact(orc, rel, n, q, probs, frac, alpha):
     say("color", rel, n, q, frac, alpha)
     x, z = strings(n, q, probs, seed=n + rel)
-    run_both(orc, x, z, q, 5, frac, alpha, rel)
+    for path in (pk.PATH_VALU, pk.PATH_MFMA):
+        run_both(orc, x, z, q, 5, frac, alpha, rel, path=path)
 
 
 def test_edge_cases(orc):
