@@ -64,7 +64,12 @@ enum {
     PICASSO_OPT_STREAM = 4,     /* hipStream_t (cast to int64) to run on; 0 = the
                                    handle's own stream.  The caller keeps the
                                    stream alive while the handle uses it.        */
-    PICASSO_OPT_TIMING = 5      /* 1: record per-phase times (adds event syncs)  */
+    PICASSO_OPT_TIMING = 5,     /* 1: record per-phase times (adds event syncs)  */
+    PICASSO_OPT_JP_BATCH = 6,   /* colouring rounds launched between two host
+                                   checks of progress, at most (1..1024; 16)    */
+    PICASSO_OPT_GRAPH = 7       /* 1 (default): a full batch of colouring rounds
+                                   is captured once per iteration into a HIP
+                                   graph and replayed; 0: plain launches        */
 };
 
 #define PICASSO_PATH_AUTO 0
@@ -82,7 +87,8 @@ typedef struct {
     int64_t pair_tests; /* sum over colours c of C(|B_c|, 2)                   */
     int64_t edges;      /* |E_c|, undirected conflict edges                    */
     int64_t colored;    /* vertices coloured in this iteration                 */
-    int64_t offset;     /* first global colour id of this iteration's palette  */
+    int64_t offset;     /* first global colour id of this iteration's palette
+                           (single-instance handles; 0 for batches)           */
     int32_t pair_path;  /* PICASSO_PATH_VALU or PICASSO_PATH_MFMA              */
     int32_t jp_rounds;  /* colouring rounds                                    */
     double ms_lists, ms_buckets, ms_count, ms_fill, ms_color, ms_compact;
@@ -103,6 +109,18 @@ typedef struct {
     picasso_iter_stats iters[PICASSO_MAX_ITER_STATS];
 } picasso_stats;
 
+/* Per-instance summary of the last colouring call (for batches, one per
+ * instance in creation order; a single-instance handle has one). */
+typedef struct {
+    int64_t n;             /* strings of the instance                          */
+    int64_t n_colors;      /* distinct colours used                            */
+    int64_t palette_total; /* sum of its palette sizes                         */
+    int64_t edges;         /* conflict edges over all its iterations           */
+    int64_t max_edges;     /* largest single-iteration |E_c| of the instance   */
+    int32_t n_iters;       /* iterations the instance took                     */
+    int32_t reserved;
+} picasso_instance_stats;
+
 /* Most recent error message of this host thread ("" if none). */
 const char *picasso_last_error(void);
 
@@ -116,6 +134,15 @@ picasso_handle picasso_create(int64_t n, int32_t q, const uint64_t *x_words, con
 /* As picasso_create, but x_words/z_words are device pointers (copied
  * device-to-device; padding bits are checked on the device). */
 picasso_handle picasso_create_device(int64_t n, int32_t q, const uint64_t *x_words, const uint64_t *z_words);
+
+/* Create one handle holding `count` independent instances (a batch),
+ * coloured together by picasso_color_batch.  Instance i has ns[i] strings on
+ * qs[i] qubits (W_i = ceil(qs[i]/64) words); x_words/z_words (host) hold the
+ * instances back to back: instance i's n_i x W_i rows follow instance
+ * i-1's.  Same limits as picasso_create for every instance, and the total
+ * number of strings is below 2^31.  Returns NULL on error. */
+picasso_handle picasso_create_batch(int32_t count, const int64_t *ns, const int32_t *qs, const uint64_t *x_words,
+                                    const uint64_t *z_words);
 
 /* Release the handle and all device memory it owns.  NULL is ignored. */
 void picasso_destroy(picasso_handle h);
@@ -139,8 +166,32 @@ int64_t picasso_color(picasso_handle h, uint64_t seed, double palette_frac, doub
 int64_t picasso_color_device(picasso_handle h, uint64_t seed, double palette_frac, double list_size,
                              int32_t relation, int32_t *out_colors);
 
-/* Copy the last colouring call's statistics.  Returns PICASSO_OK. */
+/* Colour every instance of a batch handle, each exactly as picasso_color
+ * would colour it alone with its own arguments (Alg. 1 per instance; the
+ * instances advance through their iterations side by side, each kernel
+ * launch covering all instances still holding uncoloured strings).
+ * seeds, palette_fracs, list_sizes, relations: host arrays of one entry per
+ * instance, meanings as in picasso_color.  out_colors: host int32, the
+ * total number of strings, instance i's colours (its own ids from 0) at its
+ * strings' positions in the concatenation.  out_n_colors: host int64 per
+ * instance.  Returns the sum of the instances' colour counts or an error.
+ * The single-instance calls below (picasso_color, picasso_color_device,
+ * picasso_sample_lists, picasso_conflict_graph, picasso_list_color_csr,
+ * picasso_features, picasso_color_learned) reject batch handles of more
+ * than one instance with PICASSO_EINVAL. */
+int64_t picasso_color_batch(picasso_handle h, const uint64_t *seeds, const double *palette_fracs,
+                            const double *list_sizes, const int32_t *relations, int32_t *out_colors,
+                            int64_t *out_n_colors);
+
+/* Copy the last colouring call's statistics (for a batch: iterations
+ * aggregated over the instances: m, P, pair_tests, edges, colored summed,
+ * T the largest list size).  Returns PICASSO_OK. */
 int32_t picasso_get_stats(picasso_handle h, picasso_stats *out);
+
+/* Copy the first `count` per-instance summaries of the last colouring call
+ * into out (host).  count = 0 with out = NULL only queries.  Returns the
+ * handle's number of instances or an error. */
+int32_t picasso_get_instance_stats(picasso_handle h, int32_t count, picasso_instance_stats *out);
 
 /* ---- Single steps of one iteration, for tests and tools ---------------- */
 

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libpicasso.so")
 REL_ANTICOMMUTE = 0
 REL_QWC = 1
 PATH_AUTO, PATH_VALU, PATH_MFMA = 0, 1, 2
-OPT_MEM_BUDGET, OPT_PAIR_PATH, OPT_FIXED_T, OPT_STREAM, OPT_TIMING = 1, 2, 3, 4, 5
+OPT_MEM_BUDGET, OPT_PAIR_PATH, OPT_FIXED_T, OPT_STREAM, OPT_TIMING, OPT_JP_BATCH, OPT_GRAPH = 1, 2, 3, 4, 5, 6, 7
 MAX_T = 256
 MAX_ITER_STATS = 256
 
@@ -30,11 +30,14 @@ EXPORTS = (
     "picasso_last_error",
     "picasso_create",
     "picasso_create_device",
+    "picasso_create_batch",
     "picasso_destroy",
     "picasso_set_option",
     "picasso_color",
     "picasso_color_device",
+    "picasso_color_batch",
     "picasso_get_stats",
+    "picasso_get_instance_stats",
     "picasso_sample_lists",
     "picasso_conflict_graph",
     "picasso_list_color_csr",
@@ -96,6 +99,18 @@ class Stats(ctypes.Structure):
         return d
 
 
+class InstanceStats(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64),
+        ("n_colors", ctypes.c_int64),
+        ("palette_total", ctypes.c_int64),
+        ("edges", ctypes.c_int64),
+        ("max_edges", ctypes.c_int64),
+        ("n_iters", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
 class PicassoError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"picasso error {code}: {msg}")
@@ -131,6 +146,12 @@ def lib() -> ctypes.CDLL:
     L.picasso_create.argtypes = [i64, i32, p, p]
     L.picasso_create_device.restype = p
     L.picasso_create_device.argtypes = [i64, i32, p, p]
+    L.picasso_create_batch.restype = p
+    L.picasso_create_batch.argtypes = [i32, p, p, p, p]
+    L.picasso_color_batch.restype = i64
+    L.picasso_color_batch.argtypes = [p, p, p, p, p, p, p]
+    L.picasso_get_instance_stats.restype = i32
+    L.picasso_get_instance_stats.argtypes = [p, i32, p]
     L.picasso_destroy.restype = None
     L.picasso_destroy.argtypes = [p]
     L.picasso_set_option.restype = i32
@@ -253,6 +274,12 @@ class Picasso:
         _check(lib().picasso_get_stats(self._h, ctypes.byref(s)))
         return s.to_dict()
 
+    def instance_stats(self) -> list[dict]:
+        nb = _check(lib().picasso_get_instance_stats(self._h, 0, None))
+        arr = (InstanceStats * nb)()
+        _check(lib().picasso_get_instance_stats(self._h, nb, arr))
+        return [{k: getattr(r, k) for k, _ in InstanceStats._fields_ if k != "reserved"} for r in arr]
+
     def sample_lists(self, seed: int, ell: int, ids, P: int, T: int):
         ids = np.ascontiguousarray(ids, dtype=np.int32)
         m = ids.shape[0]
@@ -291,6 +318,58 @@ class Picasso:
         nc = _check(lib().picasso_color_learned(self._h, seed, mlp._m, relation, _ptr(out), _ptr(sched), max_sched))
         n_it = min(self.stats()["n_iters"], max_sched)
         return nc, out[: self.n], sched[:n_it].copy()
+
+
+class PicassoBatch(Picasso):
+    """Many independent instances in one handle, coloured together.
+
+    instances: sequence of (x, z, q) with x, z (n_i, ceil(q_i/64)) uint64
+    host arrays.  Only color_batch, stats and instance_stats apply (the
+    single-instance calls reject a handle of more than one instance).
+    """
+
+    def __init__(self, instances):
+        L = lib()
+        xs, zs, ns, qs = [], [], [], []
+        for x, z, q in instances:
+            x = np.ascontiguousarray(x, dtype=np.uint64)
+            z = np.ascontiguousarray(z, dtype=np.uint64)
+            W = (int(q) + 63) // 64
+            if x.shape != z.shape or x.size != x.shape[0] * W:
+                raise PicassoError(EINVAL, f"x/z must both be (n, {W}) uint64")
+            xs.append(x.reshape(-1))
+            zs.append(z.reshape(-1))
+            ns.append(x.shape[0])
+            qs.append(int(q))
+        self.count = len(ns)
+        self.ns = np.asarray(ns, dtype=np.int64)
+        self.qs = np.asarray(qs, dtype=np.int32)
+        self.offsets = np.concatenate([[0], np.cumsum(self.ns)]).astype(np.int64)
+        self.n = int(self.offsets[-1])
+        self.q = int(self.qs.max()) if self.count else 0
+        self.W = (self.q + 63) // 64
+        xc = np.concatenate(xs) if xs else np.zeros(0, np.uint64)
+        zc = np.concatenate(zs) if zs else np.zeros(0, np.uint64)
+        xc = np.ascontiguousarray(xc if xc.size else np.zeros(1, np.uint64))
+        zc = np.ascontiguousarray(zc if zc.size else np.zeros(1, np.uint64))
+        h = L.picasso_create_batch(self.count, _ptr(self.ns) if self.count else None,
+                                   _ptr(self.qs) if self.count else None, _ptr(xc), _ptr(zc))
+        if not h:
+            raise PicassoError(EINVAL, last_error())
+        self._h = ctypes.c_void_p(h)
+
+    def color_batch(self, seeds, palette_fracs, list_sizes, relations):
+        """Returns (n_colors int64[count], [colors int32[n_i] per instance])."""
+        k = self.count
+        seeds = np.ascontiguousarray(np.broadcast_to(np.asarray(seeds, dtype=np.uint64), (k,)))
+        fr = np.ascontiguousarray(np.broadcast_to(np.asarray(palette_fracs, dtype=np.float64), (k,)))
+        al = np.ascontiguousarray(np.broadcast_to(np.asarray(list_sizes, dtype=np.float64), (k,)))
+        rel = np.ascontiguousarray(np.broadcast_to(np.asarray(relations, dtype=np.int32), (k,)))
+        out = np.empty(max(self.n, 1), dtype=np.int32)
+        nc = np.zeros(max(k, 1), dtype=np.int64)
+        _check(lib().picasso_color_batch(self._h, _ptr(seeds), _ptr(fr), _ptr(al), _ptr(rel), _ptr(out), _ptr(nc)))
+        cols = [out[self.offsets[i]:self.offsets[i + 1]].copy() for i in range(k)]
+        return nc[:k], cols
 
 
 class Mlp:

@@ -62,8 +62,11 @@ void Arena::release(DevBuf &b)
 using namespace picasso;
 
 struct picasso_ctx {
-    int64_t n = 0;
-    int32_t q = 0, W = 0;
+    int64_t n = 0;           // strings over all instances
+    int32_t q = 0, W = 0;    // largest q of the instances; words per packed string
+    int32_t nb = 1;          // instances
+    std::vector<int64_t> inst_n, inst_base;  // strings of each instance, first packed string
+    std::vector<int32_t> inst_q;
     int device = 0;
     hipStream_t own_stream = nullptr;
     hipStream_t stream = nullptr;
@@ -71,13 +74,17 @@ struct picasso_ctx {
     int32_t pair_path = PICASSO_PATH_AUTO;
     int32_t fixed_T = 0;
     int32_t timing = 0;
+    int32_t jp_batch = 16;   // colouring rounds per host check, at most
+    int32_t use_graph = 1;   // replay colouring rounds from a captured graph
     Arena arena;
     DevBuf x, z;
     // iteration buffers
     DevBuf ids, next_ids, lists, prio, bcnt, bstart, bmem, bslot, pos_of, tmp_mem, tmp_slot, tiles, words, tile_off,
-        rb_off, R, D, bx, bz, tile_bucket, nslow, slow, slot_cnt, slot_off, rowptr, adj, col, blk, fre, nblk, st, dirty, wl, flags, pos,
-        used, scan_tmp, scalars, out_colors;
+        rb_off, R, D, bx, bz, tile_bucket, nslow, slow, slot_cnt, slot_off, rowptr, adj, col, blk, fre, nblk, st,
+        dirty, wl, flags, pos, used, scan_tmp, scalars, out_colors, inst, vinst, loff, binst, inst_out;
+    std::vector<InstRec> h_inst;  // table of the active instances (kept until the copy has completed)
     picasso_stats stats;
+    std::vector<picasso_instance_stats> istats;
 };
 
 struct picasso_mlp_ctx {
@@ -150,6 +157,53 @@ T read_scalar(picasso_ctx *h, const T *dptr)
     return v;
 }
 
+void upload(picasso_ctx *h, void *dst, const void *src, size_t bytes)
+{
+    if (bytes) PCHECK_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream));
+}
+
+void download(picasso_ctx *h, void *dst, const void *src, size_t bytes)
+{
+    if (bytes) PCHECK_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, h->stream));
+    PCHECK_HIP(hipStreamSynchronize(h->stream));
+}
+
+// Uploads h->h_inst (the active instances, vstart/loff/pal ascending) and
+// derives the per-vertex table for the m active vertices.
+Batch upload_batch(picasso_ctx *h, int64_t m)
+{
+    const size_t nb = h->h_inst.size();
+    InstRec *d = buf<InstRec>(h, h->inst, nb);
+    upload(h, d, h->h_inst.data(), nb * sizeof(InstRec));
+    Batch b{};
+    b.inst = d;
+    b.nb = (int32_t)nb;
+    int32_t *vinst = buf<int32_t>(h, h->vinst, (size_t)std::max<int64_t>(m, 1));
+    int64_t *loff = buf<int64_t>(h, h->loff, (size_t)m + 1);
+    launch_vertex_table(b, m, vinst, loff, h->stream);
+    b.vinst = vinst;
+    b.loff = loff;
+    return b;
+}
+
+// A table of one instance over the m given vertices (ids in h->ids).
+Batch single_instance(picasso_ctx *h, uint64_t seed, int64_t m, int64_t P, int32_t T, int32_t rel)
+{
+    InstRec r{};
+    r.vstart = 0;
+    r.m = m;
+    r.loff = 0;
+    r.pal = 0;
+    r.P = P;
+    r.sbase = 0;
+    r.cbase = 0;
+    r.seed = seed;
+    r.T = T;
+    r.rel = rel;
+    h->h_inst.assign(1, r);
+    return upload_batch(h, m);
+}
+
 struct BucketInfo {
     int64_t pair_tests = 0;  // sum over colours of C(|B_c|, 2)
     int64_t max_size = 0;    // largest bucket
@@ -157,9 +211,11 @@ struct BucketInfo {
     int64_t words = 0;       // sum of |B_c| * ceil(|B_c|/64)
 };
 
-// Buckets of the lists already in h->lists: count, scan, scatter, sort by
-// priority (h->prio), and the shapes of the per-bucket bit matrices.
-BucketInfo buckets_from_lists(picasso_ctx *h, int64_t m, int64_t P, int32_t T)
+// Buckets of the lists already in h->lists (E entries over the m vertices
+// of batch b, P colours): count, scan, scatter, sort by priority (h->prio),
+// the shapes of the per-bucket bit matrices and the bucket -> instance
+// table (b.binst is set).
+BucketInfo buckets_from_lists(picasso_ctx *h, Batch &b, int64_t m, int64_t E, int64_t P)
 {
     hipStream_t st = h->stream;
     const uint32_t *lists = static_cast<const uint32_t *>(h->lists.p);
@@ -169,14 +225,17 @@ BucketInfo buckets_from_lists(picasso_ctx *h, int64_t m, int64_t P, int32_t T)
     unsigned long long *sc = buf<unsigned long long>(h, h->scalars, 8);
     launch_fill_u32(bcnt, P, 0u, st);
     launch_fill_u64(reinterpret_cast<uint64_t *>(sc), 8, 0ull, st);
-    launch_bucket_count(lists, m * T, bcnt, st);
+    launch_bucket_count(lists, E, bcnt, st);
     launch_bucket_pairs(bcnt, P, sc, st);
-    void *tmp = h->arena.ensure(h->scan_tmp, scan_tmp_bytes(std::max<int64_t>(P, m * T) + 1));
+    void *tmp = h->arena.ensure(h->scan_tmp, scan_tmp_bytes(std::max<int64_t>(P, E) + 1));
     exclusive_scan_u32_to_i64(bcnt, bstart, P, true, tmp, st);
     launch_fill_u32(bcnt, P, 0u, st);
-    uint32_t *bmem = buf<uint32_t>(h, h->bmem, (size_t)m * T);
-    uint8_t *bslot = buf<uint8_t>(h, h->bslot, (size_t)m * T);
-    launch_bucket_scatter(lists, m, T, bstart, bcnt, bmem, bslot, st);
+    uint32_t *bmem = buf<uint32_t>(h, h->bmem, (size_t)std::max<int64_t>(E, 1));
+    uint8_t *bslot = buf<uint8_t>(h, h->bslot, (size_t)std::max<int64_t>(E, 1));
+    launch_bucket_scatter(lists, m, b.loff, bstart, bcnt, bmem, bslot, st);
+    int32_t *binst = buf<int32_t>(h, h->binst, (size_t)P);
+    launch_bucket_table(b, P, binst, st);
+    b.binst = binst;
     unsigned long long hs[2];
     PCHECK_HIP(hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, st));
     PCHECK_HIP(hipStreamSynchronize(st));
@@ -187,10 +246,10 @@ BucketInfo buckets_from_lists(picasso_ctx *h, int64_t m, int64_t P, int32_t T)
         throw Error(PICASSO_EINVAL, "a colour bucket holds " + std::to_string(bi.max_size) +
                                         " vertices (limit 131072): palette too small for this many vertices");
     const bool large = bi.max_size > 2048;
-    uint32_t *tmem = large ? buf<uint32_t>(h, h->tmp_mem, (size_t)m * T) : nullptr;
-    uint8_t *tslot = large ? buf<uint8_t>(h, h->tmp_slot, (size_t)m * T) : nullptr;
-    int64_t *pos_of = buf<int64_t>(h, h->pos_of, (size_t)m * T);
-    launch_bucket_sort(bstart, P, bmem, bslot, prio, pos_of, T, large, tmem, tslot, st);
+    uint32_t *tmem = large ? buf<uint32_t>(h, h->tmp_mem, (size_t)E) : nullptr;
+    uint8_t *tslot = large ? buf<uint8_t>(h, h->tmp_slot, (size_t)E) : nullptr;
+    int64_t *pos_of = buf<int64_t>(h, h->pos_of, (size_t)std::max<int64_t>(E, 1));
+    launch_bucket_sort(bstart, P, bmem, bslot, prio, pos_of, b.loff, large, tmem, tslot, st);
     int64_t *tiles = buf<int64_t>(h, h->tiles, (size_t)P);
     int64_t *words = buf<int64_t>(h, h->words, (size_t)P);
     int64_t *tile_off = buf<int64_t>(h, h->tile_off, (size_t)P + 1);
@@ -208,19 +267,22 @@ BucketInfo buckets_from_lists(picasso_ctx *h, int64_t m, int64_t P, int32_t T)
 }
 
 // Lists, priorities and buckets of one iteration.
-BucketInfo build_lists_and_buckets(picasso_ctx *h, uint64_t seed, uint32_t ell, int64_t m, const int32_t *d_ids,
-                                   int64_t P, int32_t T)
+BucketInfo build_lists_and_buckets(picasso_ctx *h, Batch &b, uint32_t ell, int64_t m, const int32_t *d_ids, int64_t E,
+                                   int64_t P, int32_t T_max)
 {
-    uint32_t *lists = buf<uint32_t>(h, h->lists, (size_t)m * T);
-    uint64_t *prio = buf<uint64_t>(h, h->prio, (size_t)m);
-    launch_sample_lists(seed, ell, m, d_ids, P, T, lists, prio, h->stream);
-    return buckets_from_lists(h, m, P, T);
+    uint32_t *lists = buf<uint32_t>(h, h->lists, (size_t)std::max<int64_t>(E, 1));
+    uint64_t *prio = buf<uint64_t>(h, h->prio, (size_t)std::max<int64_t>(m, 1));
+    launch_sample_lists(b, ell, m, d_ids, T_max, lists, prio, h->stream);
+    return buckets_from_lists(h, b, m, E, P);
 }
 
 // Relation matrices, duplicate-pair matrices, CSR counts, scan and fill.
-// Returns |E_c|; the CSR is in h->rowptr / h->adj.
-int64_t build_conflict_graph(picasso_ctx *h, int64_t m, int64_t P, int32_t T, int32_t rel, const BucketInfo &bi,
-                             double *ms_relate, double *ms_csr, bool *used_mfma = nullptr)
+// rel_mask bit r: some instance of the batch uses relation r.  Returns
+// |E_c|; the CSR is in h->rowptr / h->adj, the per-entry offsets in
+// h->slot_off.
+int64_t build_conflict_graph(picasso_ctx *h, const Batch &b, int64_t m, int64_t E, int64_t P, int32_t T_max,
+                             int32_t rel_mask, const BucketInfo &bi, double *ms_relate, double *ms_csr,
+                             bool *used_mfma = nullptr)
 {
     hipStream_t st = h->stream;
     Timer tm(h);
@@ -237,20 +299,27 @@ int64_t build_conflict_graph(picasso_ctx *h, int64_t m, int64_t P, int32_t T, in
     ra.x = static_cast<const uint64_t *>(h->x.p);
     ra.z = static_cast<const uint64_t *>(h->z.p);
     ra.W = h->W;
-    ra.relation = rel;
+    ra.binst = b.binst;
+    ra.inst = b.inst;
     ra.R = R;
-    launch_relate_prep(ra, m * T, buf<uint64_t>(h, h->bx, (size_t)m * T * h->W),
-                       buf<uint64_t>(h, h->bz, (size_t)m * T * h->W),
+    launch_relate_prep(ra, E, buf<uint64_t>(h, h->bx, (size_t)std::max<int64_t>(E, 1) * h->W),
+                       buf<uint64_t>(h, h->bz, (size_t)std::max<int64_t>(E, 1) * h->W),
                        buf<int32_t>(h, h->tile_bucket, (size_t)std::max<int64_t>(bi.row_tiles, 1)), st);
-    const bool mfma = h->pair_path == PICASSO_PATH_MFMA ||
-                      (h->pair_path == PICASSO_PATH_AUTO && mfma_supported(h->q, rel));
-    if (mfma && !mfma_supported(h->q, rel))
-        throw Error(PICASSO_EINVAL, "the MFMA pair path does not support this q and relation");
-    ra.mfma_max_members = mfma ? mfma_member_cap(h->q, rel) : -1;
-    if (used_mfma) *used_mfma = mfma;
+    bool any_mfma = false;
     tm.mark();
-    if (mfma) launch_relate_mfma(ra, h->q, st);
-    if (!mfma || bi.max_size > ra.mfma_max_members) launch_relate(ra, st);
+    for (int32_t rel = 0; rel < 2; ++rel) {
+        if (!(rel_mask >> rel & 1)) continue;
+        const bool mfma = h->pair_path == PICASSO_PATH_MFMA ||
+                          (h->pair_path == PICASSO_PATH_AUTO && mfma_supported(h->q, rel));
+        if (mfma && !mfma_supported(h->q, rel))
+            throw Error(PICASSO_EINVAL, "the MFMA pair path does not support this q and relation");
+        ra.relation = rel;
+        ra.mfma_max_members = mfma ? mfma_member_cap(h->q, rel) : -1;
+        any_mfma |= mfma;
+        if (mfma) launch_relate_mfma(ra, h->q, st);
+        if (!mfma || bi.max_size > ra.mfma_max_members) launch_relate(ra, st);
+    }
+    if (used_mfma) *used_mfma = any_mfma;
     tm.mark();
     // pairs sharing a smaller colour
     launch_fill_u64(D, bi.words, 0ull, st);
@@ -263,12 +332,14 @@ int64_t build_conflict_graph(picasso_ctx *h, int64_t m, int64_t P, int32_t T, in
     da.P = P;
     da.rb_off = ra.rb_off;
     da.lists = static_cast<const uint32_t *>(h->lists.p);
-    da.T = T;
+    da.loff = b.loff;
+    da.binst = b.binst;
+    da.inst = b.inst;
     da.R = R;
     da.D = D;
     da.slow = buf<uint32_t>(h, h->slow, (size_t)P);
     da.n_slow = nslow;
-    if (T > 1) {
+    if (T_max > 1) {
         launch_dup(da, st);
         const int32_t n_slow = read_scalar(h, nslow);
         launch_dup_slow(da, n_slow, st);
@@ -282,15 +353,15 @@ int64_t build_conflict_graph(picasso_ctx *h, int64_t m, int64_t P, int32_t T, in
     ca.rb_off = ra.rb_off;
     ca.R = R;
     ca.D = D;
-    ca.T = T;
-    ca.slot_cnt = buf<int32_t>(h, h->slot_cnt, (size_t)m * T);
+    ca.loff = b.loff;
+    ca.slot_cnt = buf<int32_t>(h, h->slot_cnt, (size_t)std::max<int64_t>(E, 1));
     launch_count(ca, st);
-    int64_t *slot_off = buf<int64_t>(h, h->slot_off, (size_t)m * T + 1);
-    void *tmp = h->arena.ensure(h->scan_tmp, scan_tmp_bytes(std::max<int64_t>(P, m * T) + 1));
-    exclusive_scan_i32_to_i64(ca.slot_cnt, slot_off, m * T, true, tmp, st);
+    int64_t *slot_off = buf<int64_t>(h, h->slot_off, (size_t)E + 1);
+    void *tmp = h->arena.ensure(h->scan_tmp, scan_tmp_bytes(std::max<int64_t>(P, E) + 1));
+    exclusive_scan_i32_to_i64(ca.slot_cnt, slot_off, E, true, tmp, st);
     int64_t *rowptr = buf<int64_t>(h, h->rowptr, (size_t)m + 1);
-    launch_rowptr(slot_off, m, T, rowptr, st);
-    const int64_t total = read_scalar(h, slot_off + m * T);
+    launch_rowptr(slot_off, m, b.loff, rowptr, st);
+    const int64_t total = read_scalar(h, slot_off + E);
     if (total % 2) throw Error(PICASSO_EINTERNAL, "odd CSR size");
     const int64_t bytes = total * (int64_t)sizeof(int32_t);
     if (h->mem_budget > 0 && bytes > h->mem_budget)
@@ -306,8 +377,46 @@ int64_t build_conflict_graph(picasso_ctx *h, int64_t m, int64_t P, int32_t T, in
     return total / 2;
 }
 
+// Colouring rounds: `count` rounds starting from worklist `cur`, either
+// launched one by one or replayed from a graph captured once per
+// iteration (the rounds' arguments do not change within an iteration).
+struct RoundGraph {
+    hipGraphExec_t exec[2] = {nullptr, nullptr};  // starting from list 0 / list 1
+    int32_t rounds = 0;
+    ~RoundGraph()
+    {
+        for (auto &e : exec)
+            if (e) (void)hipGraphExecDestroy(e);
+    }
+};
+
+void capture_rounds(picasso_ctx *h, const JpArgs &j, RoundGraph &g, int32_t rounds)
+{
+    for (int start = 0; start < 2; ++start) {
+        hipGraph_t graph = nullptr;
+        PCHECK_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        int cur = start;
+        try {
+            for (int r = 0; r < rounds; ++r) {
+                launch_jp_round(j, cur, h->stream);
+                cur ^= 1;
+            }
+        } catch (...) {
+            (void)hipStreamEndCapture(h->stream, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            throw;
+        }
+        PCHECK_HIP(hipStreamEndCapture(h->stream, &graph));
+        const hipError_t e = hipGraphInstantiate(&g.exec[start], graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        PCHECK_HIP(e);
+    }
+    g.rounds = rounds;
+}
+
 // List colouring until every vertex is decided.  Result in h->col.
-int32_t color_buckets(picasso_ctx *h, int64_t m, int64_t P, int32_t T, const BucketInfo &bi)
+int32_t color_buckets(picasso_ctx *h, const Batch &b, int64_t m, int64_t E, int64_t P, int32_t T_max,
+                      const BucketInfo &bi)
 {
     hipStream_t st = h->stream;
     JpArgs j{};
@@ -318,15 +427,15 @@ int32_t color_buckets(picasso_ctx *h, int64_t m, int64_t P, int32_t T, const Buc
     j.rb_off = static_cast<const int64_t *>(h->rb_off.p);
     j.R = static_cast<const uint64_t *>(h->R.p);
     j.lists = static_cast<const uint32_t *>(h->lists.p);
+    j.loff = b.loff;
     j.pos_of = static_cast<const int64_t *>(h->pos_of.p);
     j.nw_max = std::max<int64_t>((bi.max_size + 63) / 64, 1);
-    j.T = T;
-    j.fw = (T + 63) / 64;
-    j.col = buf<int32_t>(h, h->col, (size_t)m);
+    j.fw = (T_max + 63) / 64;
+    j.col = buf<int32_t>(h, h->col, (size_t)std::max<int64_t>(m, 1));
     j.blk = buf<uint64_t>(h, h->blk, (size_t)m * j.fw);
     j.fre = buf<uint64_t>(h, h->fre, (size_t)m * j.fw);
-    j.nblk = buf<int32_t>(h, h->nblk, (size_t)m);
-    j.st = buf<uint8_t>(h, h->st, (size_t)m * T);
+    j.nblk = buf<int32_t>(h, h->nblk, (size_t)std::max<int64_t>(m, 1));
+    j.st = buf<uint8_t>(h, h->st, (size_t)std::max<int64_t>(E, 1));
     j.dirty = buf<uint32_t>(h, h->dirty, (size_t)P);
     int32_t *wl = buf<int32_t>(h, h->wl, (size_t)2 * P + 2);
     j.wl[0] = wl;
@@ -339,62 +448,57 @@ int32_t color_buckets(picasso_ctx *h, int64_t m, int64_t P, int32_t T, const Buc
     launch_fill_u64(j.blk, m * j.fw, 0ull, st);
     launch_fill_u64(j.fre, m * j.fw, 0ull, st);
     launch_fill_i32(j.nblk, m, 0, st);
-    launch_fill_u8(j.st, m * T, 0, st);
+    launch_fill_u8(j.st, E, 0, st);
     launch_fill_u64(reinterpret_cast<uint64_t *>(j.progress), 1, 0ull, st);
     launch_jp_all(j, st);
+    RoundGraph graph;
+    const int32_t max_batch = std::max<int32_t>(h->jp_batch, 1);
     int32_t rounds = 0;
-    int cur = 0, batch = 2;
+    int cur = 0, batch = std::min<int32_t>(2, max_batch);
     unsigned long long at_restart = 0;
     bool fresh = true;  // the lists hold every bucket
     while (true) {
-        for (int r = 0; r < batch; ++r) {
-            launch_jp_round(j, cur, st);
-            cur ^= 1;
+        if (h->use_graph && batch == max_batch && max_batch > 1) {
+            if (!graph.rounds) capture_rounds(h, j, graph, batch);
+            PCHECK_HIP(hipGraphLaunch(graph.exec[cur], st));
+            if (batch & 1) cur ^= 1;
+        } else {
+            for (int r = 0; r < batch; ++r) {
+                launch_jp_round(j, cur, st);
+                cur ^= 1;
+            }
         }
         rounds += batch;
-        struct {
-            unsigned long long done;
-        } hs;
+        unsigned long long done = 0;
         int32_t pending = 0;
-        PCHECK_HIP(hipMemcpyAsync(&hs.done, j.progress, sizeof(hs.done), hipMemcpyDeviceToHost, st));
+        PCHECK_HIP(hipMemcpyAsync(&done, j.progress, sizeof(done), hipMemcpyDeviceToHost, st));
         PCHECK_HIP(hipMemcpyAsync(&pending, &j.wl_count[cur], sizeof(pending), hipMemcpyDeviceToHost, st));
         PCHECK_HIP(hipStreamSynchronize(st));
-        if ((int64_t)hs.done >= m) break;
+        if ((int64_t)done >= m) break;
         if (pending == 0) {
             // Nothing left on the worklist but vertices remain: start again
             // from every bucket.  Rounds that start from every bucket decide
             // at least the first undecided vertex of the order.
-            if (fresh && hs.done == at_restart) throw Error(PICASSO_EINTERNAL, "list colouring made no progress");
-            at_restart = hs.done;
+            if (fresh && done == at_restart) throw Error(PICASSO_EINTERNAL, "list colouring made no progress");
+            at_restart = done;
             launch_jp_all(j, st);
             cur = 0;
             fresh = true;
         } else {
             fresh = false;
         }
-        if (batch < 16) batch *= 2;
+        batch = std::min<int32_t>(batch * 2, max_batch);
     }
-    const int32_t launches = rounds;
-    return launches;
-}
-
-void upload(picasso_ctx *h, void *dst, const void *src, size_t bytes)
-{
-    if (bytes) PCHECK_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream));
-}
-
-void download(picasso_ctx *h, void *dst, const void *src, size_t bytes)
-{
-    if (bytes) PCHECK_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, h->stream));
-    PCHECK_HIP(hipStreamSynchronize(h->stream));
+    return rounds;
 }
 
 void init_ids(picasso_ctx *h, int64_t m);
 
-// Features of the current vertex set (ids on the device): exact integer
-// counts from the device, the five values formed on the host in double.
-void device_features(picasso_ctx *h, uint64_t seed, uint32_t ell, int64_t m, const int32_t *d_ids, int32_t rel,
-                     double out[5])
+// Features of the m vertices at d_ids (one instance with q qubits): exact
+// integer counts from the device, the five values formed on the host in
+// double.
+void device_features(picasso_ctx *h, uint64_t seed, uint32_t ell, int64_t m, const int32_t *d_ids, int32_t q,
+                     int32_t rel, double out[5])
 {
     unsigned long long *sc = buf<unsigned long long>(h, h->scalars, 8);
     launch_fill_u64(reinterpret_cast<uint64_t *>(sc + 4), 2, 0ull, h->stream);
@@ -404,7 +508,7 @@ void device_features(picasso_ctx *h, uint64_t seed, uint32_t ell, int64_t m, con
     PCHECK_HIP(hipMemcpyAsync(hv, sc + 4, sizeof(hv), hipMemcpyDeviceToHost, h->stream));
     PCHECK_HIP(hipStreamSynchronize(h->stream));
     out[0] = m > 0 ? std::log((double)m) : 0.0;
-    out[1] = (double)h->q;
+    out[1] = (double)q;
     out[2] = m > 0 ? (double)hv[0] / (double)m : 0.0;
     out[3] = m >= 2 ? (double)hv[1] / (double)kFeaturePairs : 0.0;
     out[4] = (double)ell;
@@ -425,92 +529,164 @@ void mlp_params_for(picasso_mlp_ctx *mc, hipStream_t st, const double feat[5], f
     PCHECK_HIP(hipStreamSynchronize(st));
 }
 
-int64_t color_all(picasso_ctx *h, uint64_t seed, double frac, double alpha, int32_t rel, int32_t *d_out,
-                  picasso_mlp_ctx *mlp = nullptr, float *sched = nullptr, int32_t max_sched = 0)
+// Per-instance run arguments of one colouring call.
+struct RunArgs {
+    const uint64_t *seeds;
+    const double *fracs, *alphas;
+    const int32_t *rels;
+    picasso_mlp_ctx *mlp = nullptr;  // learned parameters (single-instance calls)
+    float *sched = nullptr;          // the learned (f, alpha) of each iteration
+    int32_t max_sched = 0;
+};
+
+// Colours every instance of the handle (Alg. 1 loop, all instances side by
+// side: iteration l advances every instance that still has uncoloured
+// vertices).  Colours land in d_out at each string's packed index;
+// n_colors[i] receives instance i's colour count.  Returns their sum.
+int64_t color_all(picasso_ctx *h, const RunArgs &ra, int32_t *d_out, int64_t *n_colors)
 {
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = h->stream;
     picasso_stats &S = h->stats;
     std::memset(&S, 0, sizeof(S));
     S.n = h->n;
+    h->istats.assign((size_t)h->nb, picasso_instance_stats{});
     h->arena.peak = h->arena.live;
     launch_fill_i32(d_out, h->n, -1, st);
     init_ids(h, h->n);
-    int64_t m = h->n, offset = 0, n_colors = 0;
+    std::vector<int64_t> mi(h->inst_n), off((size_t)h->nb, 0);
+    for (int32_t i = 0; i < h->nb; ++i) {
+        n_colors[i] = 0;
+        h->istats[i].n = h->inst_n[i];
+    }
+    std::vector<int32_t> act;
+    std::vector<int64_t> hv;
+    int64_t m = h->n;
     uint32_t ell = 1;
     while (m > 0) {
-        int64_t P;
-        int32_t T;
-        if (mlp) {
-            double feat[5];
-            device_features(h, seed, ell, m, static_cast<const int32_t *>(h->ids.p), rel, feat);
-            float fa[2];
-            mlp_params_for(mlp, h->stream, feat, fa);
-            frac = (double)fa[0];
-            alpha = (double)fa[1];
-            if (sched && (int32_t)ell <= max_sched) {
-                sched[2 * (ell - 1)] = fa[0];
-                sched[2 * (ell - 1) + 1] = fa[1];
+        // the active instances' table
+        h->h_inst.clear();
+        act.clear();
+        int64_t vs = 0, E = 0, Ptot = 0;
+        int32_t T_max = 0, rel_mask = 0;
+        for (int32_t i = 0; i < h->nb; ++i) {
+            if (mi[i] == 0) continue;
+            double frac = ra.fracs[i], alpha = ra.alphas[i];
+            if (ra.mlp) {
+                double feat[5];
+                device_features(h, ra.seeds[i], ell, mi[i], static_cast<const int32_t *>(h->ids.p) + vs,
+                                h->inst_q[i], ra.rels[i], feat);
+                float fa[2];
+                mlp_params_for(ra.mlp, h->stream, feat, fa);
+                frac = (double)fa[0];
+                alpha = (double)fa[1];
+                if (ra.sched && (int32_t)ell <= ra.max_sched) {
+                    ra.sched[2 * (ell - 1)] = fa[0];
+                    ra.sched[2 * (ell - 1) + 1] = fa[1];
+                }
             }
+            int64_t P;
+            int32_t T;
+            params(mi[i], frac, alpha, h->fixed_T, P, T);
+            if (T > PICASSO_MAX_T)
+                throw Error(PICASSO_EINVAL, "list size " + std::to_string(T) + " exceeds PICASSO_MAX_T");
+            InstRec r{};
+            r.vstart = vs;
+            r.m = mi[i];
+            r.loff = E;
+            r.pal = Ptot;
+            r.P = P;
+            r.sbase = h->inst_base[i];
+            r.cbase = off[i];
+            r.seed = ra.seeds[i];
+            r.T = T;
+            r.rel = ra.rels[i];
+            h->h_inst.push_back(r);
+            act.push_back(i);
+            vs += mi[i];
+            E += mi[i] * T;
+            Ptot += P;
+            T_max = std::max(T_max, T);
+            rel_mask |= 1 << ra.rels[i];
         }
-        params(m, frac, alpha, h->fixed_T, P, T);
-        if (T > PICASSO_MAX_T) throw Error(PICASSO_EINVAL, "list size " + std::to_string(T) + " exceeds PICASSO_MAX_T");
-        if (P > INT32_MAX) throw Error(PICASSO_EINVAL, "palette too large");
+        if (Ptot > INT32_MAX) throw Error(PICASSO_EINVAL, "palette too large");
         picasso_iter_stats it{};
         it.m = m;
-        it.P = P;
-        it.T = T;
-        it.offset = offset;
+        it.P = Ptot;
+        it.T = T_max;
+        it.offset = h->nb == 1 ? off[0] : 0;
         Timer tm(h);
         tm.mark();
+        Batch b = upload_batch(h, m);
         const int32_t *d_ids = static_cast<const int32_t *>(h->ids.p);
-        const BucketInfo bi = build_lists_and_buckets(h, seed, ell, m, d_ids, P, T);
+        const BucketInfo bi = build_lists_and_buckets(h, b, ell, m, d_ids, E, Ptot, T_max);
         it.pair_tests = bi.pair_tests;
         tm.mark();
         bool used_mfma = false;
-        it.edges = build_conflict_graph(h, m, P, T, rel, bi, &it.ms_count, &it.ms_fill, &used_mfma);
+        it.edges = build_conflict_graph(h, b, m, E, Ptot, T_max, rel_mask, bi, &it.ms_count, &it.ms_fill,
+                                        &used_mfma);
         it.pair_path = used_mfma ? PICASSO_PATH_MFMA : PICASSO_PATH_VALU;
         tm.mark();
-        it.jp_rounds = color_buckets(h, m, P, T, bi);
+        it.jp_rounds = color_buckets(h, b, m, E, Ptot, T_max, bi);
         tm.mark();
-        // global colours, used-colour count, next vertex set
-        uint32_t *used = buf<uint32_t>(h, h->used, (size_t)(P + 31) / 32);
-        launch_fill_u32(used, (P + 31) / 32, 0u, st);
-        unsigned long long *sc = buf<unsigned long long>(h, h->scalars, 8);
-        launch_fill_u64(reinterpret_cast<uint64_t *>(sc + 3), 1, 0ull, st);
+        // output colours, used-colour counts, next vertex set
+        const int32_t na = b.nb;
+        uint32_t *used = buf<uint32_t>(h, h->used, (size_t)(Ptot + 31) / 32);
+        launch_fill_u32(used, (Ptot + 31) / 32, 0u, st);
+        int64_t *iout = buf<int64_t>(h, h->inst_out, (size_t)3 * na);  // used, m_next, edges
+        launch_fill_u64(reinterpret_cast<uint64_t *>(iout), na, 0ull, st);
         int32_t *flags = buf<int32_t>(h, h->flags, (size_t)m);
-        launch_finish_iteration(m, static_cast<const int32_t *>(h->col.p), d_ids, offset, d_out, used, sc + 3, flags,
-                                st);
+        launch_finish_iteration(b, m, static_cast<const int32_t *>(h->col.p), d_ids, d_out, used,
+                                reinterpret_cast<unsigned long long *>(iout), flags, st);
         int64_t *pos = buf<int64_t>(h, h->pos, (size_t)m + 1);
-        void *tmp = h->arena.ensure(h->scan_tmp, scan_tmp_bytes(std::max<int64_t>(P, m)));
+        void *tmp = h->arena.ensure(h->scan_tmp, scan_tmp_bytes(std::max<int64_t>(Ptot, m)));
         exclusive_scan_i32_to_i64(flags, pos, m, true, tmp, st);
         int32_t *next = buf<int32_t>(h, h->next_ids, (size_t)m);
         launch_compact_ids(m, d_ids, flags, pos, next, st);
+        launch_instance_totals(b, pos, static_cast<const int64_t *>(h->slot_off.p), iout + na, iout + 2 * na, st);
         tm.mark();
-        const int64_t m_next = read_scalar(h, pos + m);
-        const int64_t used_now = (int64_t)read_scalar(h, sc + 3);
+        hv.resize((size_t)3 * na);
+        download(h, hv.data(), iout, hv.size() * sizeof(int64_t));
+        int64_t m_next = 0, used_now = 0;
+        for (int32_t a = 0; a < na; ++a) {
+            const int32_t i = act[a];
+            const InstRec &r = h->h_inst[a];
+            picasso_instance_stats &is = h->istats[i];
+            n_colors[i] += hv[a];
+            used_now += hv[a];
+            mi[i] = hv[na + a];
+            m_next += mi[i];
+            off[i] += r.P;
+            is.n_iters++;
+            is.palette_total += r.P;
+            is.edges += hv[2 * na + a];
+            is.max_edges = std::max<int64_t>(is.max_edges, hv[2 * na + a]);
+            if (r.m - mi[i] <= 0) throw Error(PICASSO_EINTERNAL, "iteration coloured no vertex of an instance");
+        }
         it.colored = m - m_next;
         it.ms_buckets = tm.ms(0, 1);
         it.ms_color = tm.ms(2, 3);
         it.ms_compact = tm.ms(3, 4);
-        if (it.colored <= 0) throw Error(PICASSO_EINTERNAL, "iteration coloured no vertex");
         std::swap(h->ids, h->next_ids);
-        n_colors += used_now;
         if (S.n_iters < PICASSO_MAX_ITER_STATS) S.iters[S.n_iters] = it;
         S.n_iters++;
-        S.palette_total += P;
+        S.palette_total += Ptot;
         S.pair_tests += it.pair_tests;
         S.edges += it.edges;
         if (it.edges > S.max_edges) S.max_edges = it.edges;
-        offset += P;
         m = m_next;
         ++ell;
     }
     PCHECK_HIP(hipStreamSynchronize(st));
-    S.n_colors = n_colors;
+    int64_t total = 0;
+    for (int32_t i = 0; i < h->nb; ++i) {
+        h->istats[i].n_colors = n_colors[i];
+        total += n_colors[i];
+    }
+    S.n_colors = total;
     S.peak_device_bytes = (int64_t)h->arena.peak;
     S.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    return n_colors;
+    return total;
 }
 
 __global__ void iota_kernel(int32_t *p, int64_t n)
@@ -558,6 +734,11 @@ void check_rel(int32_t rel)
     if (rel != PICASSO_REL_ANTICOMMUTE && rel != PICASSO_REL_QWC) throw Error(PICASSO_EINVAL, "unknown relation");
 }
 
+void check_single(picasso_ctx *h)
+{
+    if (h->nb != 1) throw Error(PICASSO_EINVAL, "this call takes a single-instance handle (use picasso_color_batch)");
+}
+
 void check_color_args(double frac, double alpha, int32_t rel)
 {
     if (!(frac > 0.0 && frac <= 1.0)) throw Error(PICASSO_EINVAL, "palette_frac must be in (0, 1]");
@@ -584,6 +765,10 @@ picasso_handle create_impl(int64_t n, int32_t q, const uint64_t *x, const uint64
         h->n = n;
         h->q = q;
         h->W = W;
+        h->nb = 1;
+        h->inst_n.assign(1, n);
+        h->inst_base.assign(1, 0);
+        h->inst_q.assign(1, q);
         const size_t bytes = (size_t)std::max<int64_t>(n, 1) * W * sizeof(uint64_t);
         uint64_t *dx = static_cast<uint64_t *>(h->arena.ensure(h->x, bytes));
         uint64_t *dz = static_cast<uint64_t *>(h->arena.ensure(h->z, bytes));
@@ -604,6 +789,48 @@ picasso_handle create_impl(int64_t n, int32_t q, const uint64_t *x, const uint64
         picasso_destroy(h);
         throw;
     }
+    return h;
+}
+
+// Instances packed back to back, each row widened to the words of the
+// largest q (zero words above an instance's own q change neither relation).
+picasso_handle create_batch_impl(int32_t count, const int64_t *ns, const int32_t *qs, const uint64_t *x,
+                                 const uint64_t *z)
+{
+    if (count < 1) throw Error(PICASSO_EINVAL, "count must be >= 1");
+    if (!ns || !qs) throw Error(PICASSO_EINVAL, "null sizes");
+    int64_t total = 0;
+    int32_t qmax = 1;
+    for (int32_t i = 0; i < count; ++i) {
+        if (ns[i] < 0 || ns[i] >= ((int64_t)1 << 31)) throw Error(PICASSO_EINVAL, "n must be in [0, 2^31)");
+        if (qs[i] < 1 || qs[i] > 256) throw Error(PICASSO_EINVAL, "q must be in [1, 256]");
+        total += ns[i];
+        qmax = std::max(qmax, qs[i]);
+    }
+    if (total >= ((int64_t)1 << 31)) throw Error(PICASSO_EINVAL, "total strings must be < 2^31");
+    if (total > 0 && (!x || !z)) throw Error(PICASSO_EINVAL, "null string pointer");
+    const int W = (qmax + 63) / 64;
+    std::vector<uint64_t> px((size_t)total * W, 0ull), pz((size_t)total * W, 0ull);
+    std::vector<int64_t> base((size_t)count);
+    int64_t row = 0, word = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        const int Wi = (qs[i] + 63) / 64;
+        const uint64_t mask = qs[i] % 64 ? ~((1ull << (qs[i] % 64)) - 1ull) : 0ull;
+        base[i] = row;
+        for (int64_t r = 0; r < ns[i]; ++r, ++row, word += Wi) {
+            if ((x[word + Wi - 1] | z[word + Wi - 1]) & mask)
+                throw Error(PICASSO_EINVAL, "padding bits set in instance " + std::to_string(i));
+            for (int w = 0; w < Wi; ++w) {
+                px[(size_t)row * W + w] = x[word + w];
+                pz[(size_t)row * W + w] = z[word + w];
+            }
+        }
+    }
+    picasso_handle h = create_impl(total, qmax, px.data(), pz.data(), false);
+    h->nb = count;
+    h->inst_n.assign(ns, ns + count);
+    h->inst_base = base;
+    h->inst_q.assign(qs, qs + count);
     return h;
 }
 
@@ -633,6 +860,17 @@ picasso_handle picasso_create_device(int64_t n, int32_t q, const uint64_t *x_wor
     }
 }
 
+picasso_handle picasso_create_batch(int32_t count, const int64_t *ns, const int32_t *qs, const uint64_t *x_words,
+                                    const uint64_t *z_words)
+{
+    try {
+        return create_batch_impl(count, ns, qs, x_words, z_words);
+    } catch (const std::exception &e) {
+        set_last_error(e.what());
+        return nullptr;
+    }
+}
+
 void picasso_destroy(picasso_handle h)
 {
     if (!h) return;
@@ -644,7 +882,7 @@ void picasso_destroy(picasso_handle h)
                      &h->slot_cnt, &h->slot_off, &h->rowptr, &h->adj,      &h->col,     &h->blk,      &h->fre,
                      &h->nblk,    &h->st,       &h->dirty,   &h->wl,       &h->flags,   &h->pos,      &h->used,
                      &h->scan_tmp, &h->bx,      &h->bz,      &h->tile_bucket,
-                     &h->scalars, &h->out_colors};
+                     &h->scalars, &h->out_colors, &h->inst,    &h->vinst,    &h->loff,    &h->binst,    &h->inst_out};
     for (DevBuf *b : all) h->arena.release(*b);
     if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
     delete h;
@@ -674,6 +912,13 @@ int32_t picasso_set_option(picasso_handle h, int32_t key, int64_t value)
                 case PICASSO_OPT_TIMING:
                     h->timing = value != 0;
                     break;
+                case PICASSO_OPT_JP_BATCH:
+                    if (value < 1 || value > 1024) throw Error(PICASSO_EINVAL, "rounds per check must be in [1, 1024]");
+                    h->jp_batch = (int32_t)value;
+                    break;
+                case PICASSO_OPT_GRAPH:
+                    h->use_graph = value != 0;
+                    break;
                 default:
                     throw Error(PICASSO_EINVAL, "unknown option");
             }
@@ -688,13 +933,16 @@ int64_t picasso_color_device(picasso_handle h, uint64_t seed, double palette_fra
     return guarded(
         [&]() -> int64_t {
             check_handle(h);
+            check_single(h);
             check_color_args(palette_frac, list_size, relation);
             if (h->n > 0 && !out_colors) throw Error(PICASSO_EINVAL, "null output");
             if (h->n == 0) {
                 std::memset(&h->stats, 0, sizeof(h->stats));
                 return 0;
             }
-            return color_all(h, seed, palette_frac, list_size, relation, out_colors);
+            RunArgs ra{&seed, &palette_frac, &list_size, &relation};
+            int64_t nc = 0;
+            return color_all(h, ra, out_colors, &nc);
         },
         PICASSO_EINTERNAL);
 }
@@ -705,6 +953,7 @@ int64_t picasso_color(picasso_handle h, uint64_t seed, double palette_frac, doub
     return guarded(
         [&]() -> int64_t {
             check_handle(h);
+            check_single(h);
             check_color_args(palette_frac, list_size, relation);
             if (h->n > 0 && !out_colors) throw Error(PICASSO_EINVAL, "null output");
             if (h->n == 0) {
@@ -712,12 +961,53 @@ int64_t picasso_color(picasso_handle h, uint64_t seed, double palette_frac, doub
                 return 0;
             }
             int32_t *d_out = buf<int32_t>(h, h->out_colors, (size_t)h->n);
-            const int64_t nc = color_all(h, seed, palette_frac, list_size, relation, d_out);
+            RunArgs ra{&seed, &palette_frac, &list_size, &relation};
+            int64_t n_colors = 0;
+            const int64_t nc = color_all(h, ra, d_out, &n_colors);
             const auto t0 = std::chrono::steady_clock::now();
             download(h, out_colors, d_out, (size_t)h->n * sizeof(int32_t));
             h->stats.ms_total +=
                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
             return nc;
+        },
+        PICASSO_EINTERNAL);
+}
+
+int64_t picasso_color_batch(picasso_handle h, const uint64_t *seeds, const double *palette_fracs,
+                            const double *list_sizes, const int32_t *relations, int32_t *out_colors,
+                            int64_t *out_n_colors)
+{
+    return guarded(
+        [&]() -> int64_t {
+            check_handle(h);
+            if (!seeds || !palette_fracs || !list_sizes || !relations || !out_n_colors)
+                throw Error(PICASSO_EINVAL, "null argument");
+            for (int32_t i = 0; i < h->nb; ++i) check_color_args(palette_fracs[i], list_sizes[i], relations[i]);
+            if (h->n > 0 && !out_colors) throw Error(PICASSO_EINVAL, "null output");
+            if (h->n == 0) {
+                std::memset(&h->stats, 0, sizeof(h->stats));
+                h->istats.assign((size_t)h->nb, picasso_instance_stats{});
+                for (int32_t i = 0; i < h->nb; ++i) out_n_colors[i] = 0;
+                return 0;
+            }
+            int32_t *d_out = buf<int32_t>(h, h->out_colors, (size_t)h->n);
+            RunArgs ra{seeds, palette_fracs, list_sizes, relations};
+            const int64_t nc = color_all(h, ra, d_out, out_n_colors);
+            download(h, out_colors, d_out, (size_t)h->n * sizeof(int32_t));
+            return nc;
+        },
+        PICASSO_EINTERNAL);
+}
+
+int32_t picasso_get_instance_stats(picasso_handle h, int32_t count, picasso_instance_stats *out)
+{
+    return guarded(
+        [&]() -> int32_t {
+            if (!h) throw Error(PICASSO_EINVAL, "null handle");
+            if (count < 0 || count > h->nb || (count > 0 && !out)) throw Error(PICASSO_EINVAL, "bad count or output");
+            for (int32_t i = 0; i < count; ++i)
+                out[i] = i < (int32_t)h->istats.size() ? h->istats[i] : picasso_instance_stats{};
+            return h->nb;
         },
         PICASSO_EINTERNAL);
 }
@@ -751,6 +1041,7 @@ int32_t picasso_sample_lists(picasso_handle h, uint64_t seed, int32_t ell, int64
     return guarded(
         [&]() -> int32_t {
             check_handle(h);
+            check_single(h);
             check_subset(h, m, ids, P, T);
             if (m > 0 && !out_lists) throw Error(PICASSO_EINVAL, "null output");
             if (m == 0) return PICASSO_OK;
@@ -758,7 +1049,8 @@ int32_t picasso_sample_lists(picasso_handle h, uint64_t seed, int32_t ell, int64
             upload(h, d_ids, ids, (size_t)m * sizeof(int32_t));
             uint32_t *lists = buf<uint32_t>(h, h->lists, (size_t)m * T);
             uint64_t *prio = buf<uint64_t>(h, h->prio, (size_t)m);
-            launch_sample_lists(seed, (uint32_t)ell, m, d_ids, P, T, lists, prio, h->stream);
+            const Batch b = single_instance(h, seed, m, P, T, PICASSO_REL_ANTICOMMUTE);
+            launch_sample_lists(b, (uint32_t)ell, m, d_ids, T, lists, prio, h->stream);
             download(h, out_lists, lists, (size_t)m * T * sizeof(uint32_t));
             if (out_prio) download(h, out_prio, prio, (size_t)m * sizeof(uint64_t));
             return PICASSO_OK;
@@ -772,6 +1064,7 @@ int64_t picasso_conflict_graph(picasso_handle h, uint64_t seed, int32_t ell, int
     return guarded(
         [&]() -> int64_t {
             check_handle(h);
+            check_single(h);
             check_subset(h, m, ids, P, T);
             check_rel(relation);
             if (m == 0) {
@@ -780,8 +1073,9 @@ int64_t picasso_conflict_graph(picasso_handle h, uint64_t seed, int32_t ell, int
             }
             int32_t *d_ids = buf<int32_t>(h, h->ids, (size_t)m);
             upload(h, d_ids, ids, (size_t)m * sizeof(int32_t));
-            const BucketInfo bi = build_lists_and_buckets(h, seed, (uint32_t)ell, m, d_ids, P, T);
-            const int64_t edges = build_conflict_graph(h, m, P, T, relation, bi, nullptr, nullptr);
+            Batch b = single_instance(h, seed, m, P, T, relation);
+            const BucketInfo bi = build_lists_and_buckets(h, b, (uint32_t)ell, m, d_ids, m * T, P, T);
+            const int64_t edges = build_conflict_graph(h, b, m, m * T, P, T, 1 << relation, bi, nullptr, nullptr);
             if (out_rowptr) download(h, out_rowptr, h->rowptr.p, (size_t)(m + 1) * sizeof(int64_t));
             if (out_adj && 2 * edges <= adj_cap) download(h, out_adj, h->adj.p, (size_t)(2 * edges) * sizeof(int32_t));
             return edges;
@@ -795,6 +1089,7 @@ int64_t picasso_list_color_csr(picasso_handle h, int64_t m, const uint64_t *prio
     return guarded(
         [&]() -> int64_t {
             check_handle(h);
+            check_single(h);
             if (m < 0 || m >= ((int64_t)1 << 31)) throw Error(PICASSO_EINVAL, "m out of range");
             if (T < 1 || T > PICASSO_MAX_T || P < 1 || T > P) throw Error(PICASSO_EINVAL, "bad T or P");
             if (m == 0) return 0;
@@ -816,13 +1111,14 @@ int64_t picasso_list_color_csr(picasso_handle h, int64_t m, const uint64_t *prio
             int32_t *d_adj = buf<int32_t>(h, h->adj, (size_t)std::max<int64_t>(total, 1));
             upload(h, d_rowptr, rowptr, (size_t)(m + 1) * sizeof(int64_t));
             upload(h, d_adj, adj, (size_t)total * sizeof(int32_t));
-            const BucketInfo bi = buckets_from_lists(h, m, P, T);
+            Batch b = single_instance(h, 0, m, P, T, PICASSO_REL_ANTICOMMUTE);
+            const BucketInfo bi = buckets_from_lists(h, b, m, m * T, P);
             uint64_t *R = buf<uint64_t>(h, h->R, (size_t)std::max<int64_t>(bi.words, 1));
             launch_fill_u64(R, bi.words, 0ull, h->stream);
-            launch_csr_to_relation(m, d_rowptr, d_adj, static_cast<const uint32_t *>(h->lists.p), T,
+            launch_csr_to_relation(m, d_rowptr, d_adj, static_cast<const uint32_t *>(h->lists.p), b.loff,
                                    static_cast<const int64_t *>(h->pos_of.p), static_cast<const int64_t *>(h->bstart.p),
                                    static_cast<const int64_t *>(h->rb_off.p), R, h->stream);
-            color_buckets(h, m, P, T, bi);
+            color_buckets(h, b, m, m * T, P, T, bi);
             download(h, out_col, h->col.p, (size_t)m * sizeof(int32_t));
             int64_t colored = 0;
             for (int64_t i = 0; i < m; ++i) colored += out_col[i] >= 0;
@@ -837,12 +1133,13 @@ int32_t picasso_features(picasso_handle h, uint64_t seed, int32_t ell, int64_t m
     return guarded(
         [&]() -> int32_t {
             check_handle(h);
+            check_single(h);
             check_rel(relation);
             if (!out) throw Error(PICASSO_EINVAL, "null output");
             check_subset(h, m, ids, 1, 1);
             int32_t *d_ids = buf<int32_t>(h, h->ids, (size_t)std::max<int64_t>(m, 1));
             upload(h, d_ids, ids, (size_t)m * sizeof(int32_t));
-            device_features(h, seed, (uint32_t)ell, m, d_ids, relation, out);
+            device_features(h, seed, (uint32_t)ell, m, d_ids, h->q, relation, out);
             return PICASSO_OK;
         },
         PICASSO_EINTERNAL);
@@ -1013,6 +1310,7 @@ int64_t picasso_color_learned(picasso_handle h, uint64_t seed, picasso_mlp mlp, 
     return guarded(
         [&]() -> int64_t {
             check_handle(h);
+            check_single(h);
             check_rel(relation);
             if (!mlp) throw Error(PICASSO_EINVAL, "null network");
             if (h->n > 0 && !out_colors) throw Error(PICASSO_EINVAL, "null output");
@@ -1022,7 +1320,10 @@ int64_t picasso_color_learned(picasso_handle h, uint64_t seed, picasso_mlp mlp, 
                 return 0;
             }
             int32_t *d_out = buf<int32_t>(h, h->out_colors, (size_t)h->n);
-            const int64_t nc = color_all(h, seed, 0.125, 2.0, relation, d_out, mlp, out_schedule, max_sched);
+            const double f0 = 0.125, a0 = 2.0;
+            RunArgs ra{&seed, &f0, &a0, &relation, mlp, out_schedule, max_sched};
+            int64_t n_colors = 0;
+            const int64_t nc = color_all(h, ra, d_out, &n_colors);
             download(h, out_colors, d_out, (size_t)h->n * sizeof(int32_t));
             return nc;
         },

@@ -129,6 +129,8 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t *tak, uint64
             const int k = staged ? mk[p] : a.bslot[base + p];
             uint64_t *blk = a.blk + v * a.fw;
             uint64_t *fre = a.fre + v * a.fw;
+            const int64_t l0 = a.loff[v];
+            const int T = (int)(a.loff[v + 1] - l0);
             const int32_t cv = load_i32(&a.col[v]);
             uint8_t ns = ST_UNKNOWN;
             if (cv != COL_UNDECIDED) {
@@ -146,7 +148,7 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t *tak, uint64
                     ns = ST_NOT;
                     const uint64_t kb = 1ull << (k & 63);
                     const uint64_t old = atomicOr((unsigned long long *)&blk[k >> 6], kb);
-                    if (atomicAdd(&a.nblk[v], 1) == a.T - 1) {  // the last slot was blocked
+                    if (atomicAdd(&a.nblk[v], 1) == T - 1) {  // the last slot was blocked
                         __hip_atomic_store(&a.col[v], COL_FAILED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         atomicAdd(a.progress, 1ull);
                     } else {
@@ -155,9 +157,9 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t *tak, uint64
                             const uint64_t nb = ~(old | kb);
                             f = nb ? __builtin_ctzll(nb) : 64;
                         } else {
-                            f = first_open(blk, a.T);
+                            f = first_open(blk, T);
                         }
-                        if (f > k && f < a.T) wake(a, a.lists[v * a.T + f], out, out_count);
+                        if (f > k && f < T) wake(a, a.lists[l0 + f], out, out_count);
                     }
                 } else if (any_below(fre, k)) {
                     ns = ST_NOT;  // an earlier slot is free: v takes that colour or an earlier one
@@ -170,8 +172,8 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t *tak, uint64
                         ns = ST_TAKEN;
                     }
                     if (!(was & kb)) {
-                        const uint32_t *Lv = a.lists + v * a.T;
-                        for (int k2 = k + 1; k2 < a.T; ++k2) wake(a, Lv[k2], out, out_count);
+                        const uint32_t *Lv = a.lists + l0;
+                        for (int k2 = k + 1; k2 < T; ++k2) wake(a, Lv[k2], out, out_count);
                     }
                 }
             }
@@ -236,23 +238,27 @@ __global__ void wl_all_kernel(int64_t P, int32_t *wl, uint32_t *dirty, int32_t *
 // {u, v} and every colour c in L(u) and L(v), set the pair's bits in bucket
 // c (members located through pos_of[(vertex, slot)]).
 __global__ void csr_to_relation_kernel(int64_t m, const int64_t *rowptr, const int32_t *adj, const uint32_t *lists,
-                                       int32_t T, const int64_t *pos_of, const int64_t *bstart, const int64_t *rb_off,
-                                       uint64_t *R)
+                                       const int64_t *loff, const int64_t *pos_of, const int64_t *bstart,
+                                       const int64_t *rb_off, uint64_t *R)
 {
     for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < m; u += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t *Lu = lists + u * T;
+        const int64_t lu = loff[u];
+        const int64_t Tu = loff[u + 1] - lu;
+        const uint32_t *Lu = lists + lu;
         for (int64_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
             const int64_t v = adj[e];
             if (v == u) continue;
-            const uint32_t *Lv = lists + v * T;
-            int x = 0, y = 0;
-            while (x < T && y < T) {
+            const int64_t lv = loff[v];
+            const int64_t Tv = loff[v + 1] - lv;
+            const uint32_t *Lv = lists + lv;
+            int64_t x = 0, y = 0;
+            while (x < Tu && y < Tv) {
                 if (Lu[x] == Lv[y]) {
                     const uint32_t c = Lu[x];
                     const int64_t S = bstart[c + 1] - bstart[c];
                     const int64_t nw = (S + 63) >> 6;
-                    const int64_t pu = pos_of[u * T + x] - bstart[c];
-                    const int64_t pv = pos_of[v * T + y] - bstart[c];
+                    const int64_t pu = pos_of[lu + x] - bstart[c];
+                    const int64_t pv = pos_of[lv + y] - bstart[c];
                     atomicOr((unsigned long long *)&R[rb_off[c] + pu * nw + (pv >> 6)], 1ull << (pv & 63));
                     ++x;
                     ++y;
@@ -266,16 +272,17 @@ __global__ void csr_to_relation_kernel(int64_t m, const int64_t *rowptr, const i
     }
 }
 
-__global__ void finish_kernel(int64_t m, const int32_t *col, const int32_t *ids, int64_t offset,
-                              int32_t *out_colors, uint32_t *used_bits, unsigned long long *n_used,
-                              int32_t *uncol_flag)
+__global__ void finish_kernel(Batch b, int64_t m, const int32_t *col, const int32_t *ids, int32_t *out_colors,
+                              uint32_t *used_bits, unsigned long long *n_used, int32_t *uncol_flag)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t c = col[i];
         if (c >= 0) {
-            if (out_colors) out_colors[ids[i]] = (int32_t)(offset + c);
+            const int32_t ii = b.vinst[i];
+            const InstRec &r = b.inst[ii];
+            if (out_colors) out_colors[ids[i]] = (int32_t)(r.cbase + (c - r.pal));
             const uint32_t bit = 1u << (c & 31);
-            if (!(atomicOr(&used_bits[c >> 5], bit) & bit)) atomicAdd(n_used, 1ull);
+            if (!(atomicOr(&used_bits[c >> 5], bit) & bit)) atomicAdd(&n_used[ii], 1ull);
             uncol_flag[i] = 0;
         } else {
             uncol_flag[i] = 1;
@@ -288,6 +295,16 @@ __global__ void compact_kernel(int64_t m, const int32_t *ids, const int32_t *fla
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
         if (flag[i]) next_ids[pos[i]] = ids[i];
+}
+
+__global__ void instance_totals_kernel(Batch b, const int64_t *pos, const int64_t *slot_off, int64_t *m_next,
+                                       int64_t *edges)
+{
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < b.nb; i += gridDim.x * blockDim.x) {
+        const InstRec &r = b.inst[i];
+        if (m_next) m_next[i] = pos[r.vstart + r.m] - pos[r.vstart];
+        if (edges) edges[i] = (slot_off[r.loff + r.m * r.T] - slot_off[r.loff]) / 2;
+    }
 }
 
 unsigned grid_for(int64_t work, int threads, int64_t cap = 65535 * 16)
@@ -318,20 +335,28 @@ void launch_jp_round(const JpArgs &a, int cur, hipStream_t st)
     PCHECK_LAUNCH();
 }
 
-void launch_csr_to_relation(int64_t m, const int64_t *rowptr, const int32_t *adj, const uint32_t *lists, int32_t T,
-                            const int64_t *pos_of, const int64_t *bstart, const int64_t *rb_off, uint64_t *R,
-                            hipStream_t st)
+void launch_csr_to_relation(int64_t m, const int64_t *rowptr, const int32_t *adj, const uint32_t *lists,
+                            const int64_t *loff, const int64_t *pos_of, const int64_t *bstart, const int64_t *rb_off,
+                            uint64_t *R, hipStream_t st)
 {
     if (m <= 0) return;
-    csr_to_relation_kernel<<<grid_for(m, 256), 256, 0, st>>>(m, rowptr, adj, lists, T, pos_of, bstart, rb_off, R);
+    csr_to_relation_kernel<<<grid_for(m, 256), 256, 0, st>>>(m, rowptr, adj, lists, loff, pos_of, bstart, rb_off, R);
     PCHECK_LAUNCH();
 }
 
-void launch_finish_iteration(int64_t m, const int32_t *col, const int32_t *ids, int64_t offset, int32_t *out_colors,
+void launch_finish_iteration(const Batch &b, int64_t m, const int32_t *col, const int32_t *ids, int32_t *out_colors,
                              uint32_t *used_bits, unsigned long long *n_used, int32_t *uncol_flag, hipStream_t st)
 {
     if (m <= 0) return;
-    finish_kernel<<<grid_for(m, 256), 256, 0, st>>>(m, col, ids, offset, out_colors, used_bits, n_used, uncol_flag);
+    finish_kernel<<<grid_for(m, 256), 256, 0, st>>>(b, m, col, ids, out_colors, used_bits, n_used, uncol_flag);
+    PCHECK_LAUNCH();
+}
+
+void launch_instance_totals(const Batch &b, const int64_t *pos, const int64_t *slot_off, int64_t *m_next,
+                            int64_t *edges, hipStream_t st)
+{
+    if (b.nb <= 0) return;
+    instance_totals_kernel<<<grid_for(b.nb, 256), 256, 0, st>>>(b, pos, slot_off, m_next, edges);
     PCHECK_LAUNCH();
 }
 

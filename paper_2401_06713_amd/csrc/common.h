@@ -69,6 +69,35 @@ struct Arena {
     void release(DevBuf &b);
 };
 
+// ---- a batch of instances during one iteration -----------------------------
+// Every kernel works on the concatenation of the active instances of a
+// batch; a single instance is a batch of one.  Active vertices of one
+// instance are contiguous (compaction keeps their order), each instance's
+// palette is a range of one batch-wide colour space, and each bucket holds
+// members of a single instance.  The kernels read per-instance values from
+// this record and reach it through vinst (per active vertex) or binst (per
+// bucket).
+struct InstRec {
+    int64_t vstart;  // first active vertex of the instance (index into ids)
+    int64_t m;       // active vertices
+    int64_t loff;    // first list entry of the instance
+    int64_t pal;     // first batch-wide colour of the instance's palette
+    int64_t P;       // palette size
+    int64_t sbase;   // first string of the instance in the packed arrays
+    int64_t cbase;   // instance-local id of the palette's first colour (colours of earlier iterations)
+    uint64_t seed;
+    int32_t T;       // list size
+    int32_t rel;     // PICASSO_REL_*
+};
+
+struct Batch {
+    const InstRec *inst;  // [nb]
+    int32_t nb;
+    const int32_t *vinst; // [m] instance of each active vertex
+    const int64_t *loff;  // [m+1] first list entry of each active vertex; T_v = loff[v+1] - loff[v]
+    const int32_t *binst; // [P] instance of each bucket
+};
+
 // ---- launch wrappers (each defined in the TU that holds its kernels) ------
 
 // scan.hip: exclusive prefix sums on the device.  `tmp` is scratch of at
@@ -81,18 +110,23 @@ void exclusive_scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, bool 
                                hipStream_t st);
 
 // lists.hip
-void launch_sample_lists(uint64_t seed, uint32_t ell, int64_t m, const int32_t *ids, int64_t P, int32_t T,
+// Instance and list offset of every active vertex; instance of every bucket.
+void launch_vertex_table(const Batch &b, int64_t m, int32_t *vinst, int64_t *loff, hipStream_t st);
+void launch_bucket_table(const Batch &b, int64_t P, int32_t *binst, hipStream_t st);
+// Lists of every active vertex (batch-wide colours, rows sorted) and the
+// priorities; T_max is the largest list size of the batch.
+void launch_sample_lists(const Batch &b, uint32_t ell, int64_t m, const int32_t *ids, int32_t T_max,
                          uint32_t *lists, uint64_t *prio, hipStream_t st);
 void launch_bucket_count(const uint32_t *lists, int64_t entries, uint32_t *bcnt, hipStream_t st);
-void launch_bucket_scatter(const uint32_t *lists, int64_t m, int32_t T, const int64_t *bstart, uint32_t *bfill,
-                           uint32_t *bmem, uint8_t *bslot, hipStream_t st);
+void launch_bucket_scatter(const uint32_t *lists, int64_t m, const int64_t *loff, const int64_t *bstart,
+                           uint32_t *bfill, uint32_t *bmem, uint8_t *bslot, hipStream_t st);
 void launch_check_padding(const uint64_t *x, const uint64_t *z, int64_t n, int32_t q, int32_t *bad,
                           hipStream_t st);
 
 // lists.hip: bucket order.  Sorts each bucket's members by (priority,
-// local index); pos_of[v*T + k] receives the bucket position of (v, k).
+// local index); pos_of[loff[v] + k] receives the bucket position of (v, k).
 void launch_bucket_sort(const int64_t *bstart, int64_t P, uint32_t *bmem, uint8_t *bslot, const uint64_t *prio,
-                        int64_t *pos_of, int32_t T, bool has_large, uint32_t *tmp_mem, uint8_t *tmp_slot,
+                        int64_t *pos_of, const int64_t *loff, bool has_large, uint32_t *tmp_mem, uint8_t *tmp_slot,
                         hipStream_t st);
 // Sum of C(|B_c|, 2) into pairs[0], largest |B_c| into pairs[1].
 void launch_bucket_pairs(const uint32_t *bcnt, int64_t P, unsigned long long *pairs, hipStream_t st);
@@ -115,7 +149,9 @@ struct RelateArgs {
     const int32_t *ids;       // local -> original id
     const uint64_t *x, *z;    // all n strings, n x W
     int32_t W;
-    int32_t relation;
+    int32_t relation;         // the relation this launch evaluates
+    const int32_t *binst;     // instance of each bucket
+    const InstRec *inst;      // buckets whose instance has another relation are skipped
     uint64_t *R;              // relation bit matrices
     const uint64_t *bx, *bz;  // member strings in bucket order (set by launch_relate_prep)
     const int32_t *tile_bucket;  // owner bucket of each row tile (set by launch_relate_prep)
@@ -138,8 +174,10 @@ struct DupArgs {
     const uint8_t *bslot;
     int64_t P;
     const int64_t *rb_off;
-    const uint32_t *lists;  // m x T, rows sorted
-    int32_t T;
+    const uint32_t *lists;  // rows sorted, row v at loff[v]
+    const int64_t *loff;
+    const int32_t *binst;   // instance of each bucket (its palette start bounds the colours below it)
+    const InstRec *inst;
     const uint64_t *R;      // relation matrices (the exact check visits relation pairs only)
     uint64_t *D;            // pairs sharing a smaller colour (zeroed by the caller)
     uint32_t *slow;         // buckets left to the exact per-pair check
@@ -155,14 +193,14 @@ struct CsrArgs {
     int64_t P;
     const int64_t *rb_off;
     const uint64_t *R, *D;
-    int32_t T;
-    int32_t *slot_cnt;       // count pass: m*T edge counts per (vertex, slot)
+    const int64_t *loff;     // list entry of (v, 0)
+    int32_t *slot_cnt;       // count pass: edge count per list entry (vertex, slot)
     const int64_t *slot_off; // fill pass: exclusive scan of slot_cnt
     int32_t *adj;            // fill pass: CSR column indices
 };
 void launch_count(const CsrArgs &a, hipStream_t st);
 void launch_fill(const CsrArgs &a, hipStream_t st);
-void launch_rowptr(const int64_t *slot_off, int64_t m, int32_t T, int64_t *rowptr, hipStream_t st);
+void launch_rowptr(const int64_t *slot_off, int64_t m, const int64_t *loff, int64_t *rowptr, hipStream_t st);
 
 // color.hip
 struct JpArgs {
@@ -172,12 +210,12 @@ struct JpArgs {
     const uint8_t *bslot;
     const int64_t *rb_off;
     const uint64_t *R;
-    const uint32_t *lists;  // m x T, rows sorted
+    const uint32_t *lists;  // rows sorted, row v at loff[v]
+    const int64_t *loff;    // [m+1]; T_v = loff[v+1] - loff[v]
     const int64_t *pos_of;  // bucket position of (vertex, slot)
     int64_t nw_max;         // words per row of the largest bucket
-    int32_t T;
-    int32_t fw;             // words per slot mask = ceil(T/64)
-    int32_t *col;           // local palette colour, -1 failed, -2 undecided
+    int32_t fw;             // words per slot mask = ceil(T_max/64)
+    int32_t *col;           // batch-wide colour, -1 failed, -2 undecided
     uint64_t *blk, *fre;    // m x fw: slots known blocked / known free
     int32_t *nblk;          // blocked-slot count per vertex
     uint8_t *st;            // per bucket entry: unknown / taken / not taken
@@ -192,11 +230,18 @@ void launch_jp_all(const JpArgs &a, hipStream_t st);
 // One worklist round reading list `cur` and filling list cur ^ 1; then list
 // `cur` is emptied.
 void launch_jp_round(const JpArgs &a, int cur, hipStream_t st);
-void launch_csr_to_relation(int64_t m, const int64_t *rowptr, const int32_t *adj, const uint32_t *lists, int32_t T,
-                            const int64_t *pos_of, const int64_t *bstart, const int64_t *rb_off, uint64_t *R,
-                            hipStream_t st);
-void launch_finish_iteration(int64_t m, const int32_t *col, const int32_t *ids, int64_t offset, int32_t *out_colors,
+void launch_csr_to_relation(int64_t m, const int64_t *rowptr, const int32_t *adj, const uint32_t *lists,
+                            const int64_t *loff, const int64_t *pos_of, const int64_t *bstart, const int64_t *rb_off,
+                            uint64_t *R, hipStream_t st);
+// Output colours (instance-local ids: cbase + colour - pal, written at the
+// vertex's packed string index), used-colour counts per instance and the
+// uncoloured flags.
+void launch_finish_iteration(const Batch &b, int64_t m, const int32_t *col, const int32_t *ids, int32_t *out_colors,
                              uint32_t *used_bits, unsigned long long *n_used, int32_t *uncol_flag, hipStream_t st);
+// Per instance: vertices left (from the compaction positions) and conflict
+// edges (from the CSR slot offsets, halved).
+void launch_instance_totals(const Batch &b, const int64_t *pos, const int64_t *slot_off, int64_t *m_next,
+                            int64_t *edges, hipStream_t st);
 void launch_compact_ids(int64_t m, const int32_t *ids, const int32_t *flag, const int64_t *pos, int32_t *next_ids,
                         hipStream_t st);
 

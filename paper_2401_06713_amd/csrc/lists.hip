@@ -16,22 +16,73 @@
 namespace picasso {
 namespace {
 
-// One thread per vertex.  s[T][blockDim] holds each thread's sorted set
-// (slot-major, so consecutive threads hit consecutive LDS banks).
-__global__ void sample_lists_kernel(uint64_t seed, uint32_t ell, int64_t m, const int32_t *__restrict__ ids,
-                                    int64_t P, int32_t T, uint32_t *__restrict__ lists, uint64_t *__restrict__ prio)
+// Instance of active vertex v: the last record with vstart <= v.
+__device__ __forceinline__ int32_t find_instance_of_vertex(const Batch &b, int64_t v)
+{
+    int32_t lo = 0, hi = b.nb;  // inst[lo].vstart <= v < inst[hi].vstart
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (b.inst[mid].vstart <= v) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void vertex_table_kernel(Batch b, int64_t m, int32_t *__restrict__ vinst, int64_t *__restrict__ loff)
+{
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v <= m; v += (int64_t)gridDim.x * blockDim.x) {
+        if (v == m) {
+            const InstRec &r = b.inst[b.nb - 1];
+            loff[m] = r.loff + r.m * r.T;
+        } else {
+            const int32_t i = find_instance_of_vertex(b, v);
+            const InstRec &r = b.inst[i];
+            vinst[v] = i;
+            loff[v] = r.loff + (v - r.vstart) * r.T;
+        }
+    }
+}
+
+__global__ void bucket_table_kernel(Batch b, int64_t P, int32_t *__restrict__ binst)
+{
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < P; c += (int64_t)gridDim.x * blockDim.x) {
+        int32_t lo = 0, hi = b.nb;  // inst[lo].pal <= c < inst[hi].pal
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (b.inst[mid].pal <= c) lo = mid;
+            else hi = mid;
+        }
+        binst[c] = lo;
+    }
+}
+
+// One thread per vertex.  s[T_max][blockDim] holds each thread's sorted set
+// (slot-major, so consecutive threads hit consecutive LDS banks).  The draws
+// use the instance's seed and palette and the vertex's id within its
+// instance; the stored colour is shifted by the instance's palette start.
+__global__ void sample_lists_kernel(Batch b, uint32_t ell, int64_t m, const int32_t *__restrict__ ids,
+                                    uint32_t *__restrict__ lists, uint64_t *__restrict__ prio)
 {
     extern __shared__ uint32_t s[];
+    __shared__ int uniform;
     const int B = blockDim.x, t = threadIdx.x;
     const int64_t r0 = (int64_t)blockIdx.x * B;
     const int64_t i = r0 + t;
+    const int64_t rows = (m - r0) < B ? (m - r0) : B;
+    if (t == 0) uniform = b.vinst[r0] == b.vinst[r0 + rows - 1];
+    int32_t T = 0;
+    uint32_t pal = 0;
     if (i < m) {
-        const uint32_t v = (uint32_t)ids[i];
+        const InstRec &r = b.inst[b.vinst[i]];
+        T = r.T;
+        pal = (uint32_t)r.pal;
+        const int64_t P = r.P;
+        const uint32_t v = (uint32_t)(ids[i] - r.sbase);
         int cnt = 0;
         for (int step = 0; step < T; ++step) {
             const uint64_t j = (uint64_t)(P - T + step);
-            const uint64_t r = philox_draw(seed, v, (uint32_t)step, ell, TAG_LIST);
-            const uint32_t cand = (uint32_t)__umul64hi(r, j + 1);  // in [0, j]
+            const uint64_t rnd = philox_draw(r.seed, v, (uint32_t)step, ell, TAG_LIST);
+            const uint32_t cand = (uint32_t)__umul64hi(rnd, j + 1);  // in [0, j]
             // binary search for cand among s[0..cnt)
             int lo = 0, hi = cnt;
             while (lo < hi) {
@@ -48,15 +99,23 @@ __global__ void sample_lists_kernel(uint64_t seed, uint32_t ell, int64_t m, cons
             }
             ++cnt;
         }
-        if (prio) prio[i] = philox_draw(seed, v, 0, ell, TAG_PRIO);
+        if (prio) prio[i] = philox_draw(r.seed, v, 0, ell, TAG_PRIO);
     }
     __syncthreads();
-    const int64_t rows = (m - r0) < B ? (m - r0) : B;
-    const int64_t words = rows * T;
-    uint32_t *dst = lists + r0 * T;
-    for (int64_t e = t; e < words; e += B) {
-        const int64_t row = e / T, slot = e - row * T;
-        dst[e] = s[slot * B + row];
+    if (uniform) {
+        // one instance: the block's rows are one run of lists, written coalesced
+        const InstRec &r = b.inst[b.vinst[r0]];
+        const int32_t Tu = r.T;
+        const uint32_t pu = (uint32_t)r.pal;
+        const int64_t words = rows * Tu;
+        uint32_t *dst = lists + b.loff[r0];
+        for (int64_t e = t; e < words; e += B) {
+            const int64_t row = e / Tu, slot = e - row * Tu;
+            dst[e] = pu + s[slot * B + row];
+        }
+    } else if (i < m) {
+        uint32_t *dst = lists + b.loff[i];
+        for (int k = 0; k < T; ++k) dst[k] = pal + s[k * B + t];
     }
 }
 
@@ -66,18 +125,18 @@ __global__ void bucket_count_kernel(const uint32_t *__restrict__ lists, int64_t 
         atomicAdd(&bcnt[lists[e]], 1u);
 }
 
-__global__ void bucket_scatter_kernel(const uint32_t *__restrict__ lists, int64_t m, int32_t T,
+__global__ void bucket_scatter_kernel(const uint32_t *__restrict__ lists, int64_t m, const int64_t *__restrict__ loff,
                                       const int64_t *__restrict__ bstart, uint32_t *__restrict__ bfill,
                                       uint32_t *__restrict__ bmem, uint8_t *__restrict__ bslot)
 {
-    const int64_t entries = m * T;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < entries;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t c = lists[e];
-        const int64_t at = bstart[c] + atomicAdd(&bfill[c], 1u);
-        const int64_t row = e / T;
-        bmem[at] = (uint32_t)row;
-        bslot[at] = (uint8_t)(e - row * T);
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < m; v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e0 = loff[v], T = loff[v + 1] - e0;
+        for (int64_t k = 0; k < T; ++k) {
+            const uint32_t c = lists[e0 + k];
+            const int64_t at = bstart[c] + atomicAdd(&bfill[c], 1u);
+            bmem[at] = (uint32_t)v;
+            bslot[at] = (uint8_t)k;
+        }
     }
 }
 
@@ -126,7 +185,8 @@ __global__ void __launch_bounds__(kSortThreads) bucket_sort_kernel(const int64_t
                                                                    uint32_t *__restrict__ bmem,
                                                                    uint8_t *__restrict__ bslot,
                                                                    const uint64_t *__restrict__ prio,
-                                                                   int64_t *__restrict__ pos_of, int32_t T)
+                                                                   int64_t *__restrict__ pos_of,
+                                                                   const int64_t *__restrict__ loff)
 {
     __shared__ uint64_t key[kSortCap];
     __shared__ uint32_t vid[kSortCap];
@@ -136,7 +196,7 @@ __global__ void __launch_bounds__(kSortThreads) bucket_sort_kernel(const int64_t
         const int64_t base = bstart[c];
         const int64_t S = bstart[c + 1] - base;
         if (S > kSortCap) continue;
-        if (S == 1 && t == 0) pos_of[(int64_t)bmem[base] * T + bslot[base]] = base;
+        if (S == 1 && t == 0) pos_of[loff[bmem[base]] + bslot[base]] = base;
         if (S < 2) continue;
         int N = 2;
         while (N < S) N <<= 1;
@@ -180,7 +240,7 @@ __global__ void __launch_bounds__(kSortThreads) bucket_sort_kernel(const int64_t
         for (int e = t; e < S; e += kSortThreads) {
             bmem[base + e] = vid[e];
             bslot[base + e] = sl[e];
-            pos_of[(int64_t)vid[e] * T + sl[e]] = base + e;
+            pos_of[loff[vid[e]] + sl[e]] = base + e;
         }
     }
 }
@@ -215,7 +275,8 @@ __global__ void __launch_bounds__(kSortThreads) bucket_rank_copy_kernel(const in
                                                                         uint8_t *__restrict__ bslot,
                                                                         const uint32_t *__restrict__ tmp_mem,
                                                                         const uint8_t *__restrict__ tmp_slot,
-                                                                        int64_t *__restrict__ pos_of, int32_t T)
+                                                                        int64_t *__restrict__ pos_of,
+                                                                        const int64_t *__restrict__ loff)
 {
     for (int64_t c = blockIdx.x; c < P; c += gridDim.x) {
         const int64_t base = bstart[c];
@@ -226,7 +287,7 @@ __global__ void __launch_bounds__(kSortThreads) bucket_rank_copy_kernel(const in
             const uint8_t k = tmp_slot[base + p];
             bmem[base + p] = v;
             bslot[base + p] = k;
-            pos_of[(int64_t)v * T + k] = base + p;
+            pos_of[loff[v] + k] = base + p;
         }
     }
 }
@@ -259,14 +320,28 @@ unsigned grid_for(int64_t work, int threads, unsigned cap = 65535u * 4)
 
 }  // namespace
 
-void launch_sample_lists(uint64_t seed, uint32_t ell, int64_t m, const int32_t *ids, int64_t P, int32_t T,
+void launch_vertex_table(const Batch &b, int64_t m, int32_t *vinst, int64_t *loff, hipStream_t st)
+{
+    if (b.nb <= 0) throw Error(PICASSO_EINTERNAL, "vertex table of an empty batch");
+    vertex_table_kernel<<<grid_for(m + 1, 256), 256, 0, st>>>(b, m, vinst, loff);
+    PCHECK_LAUNCH();
+}
+
+void launch_bucket_table(const Batch &b, int64_t P, int32_t *binst, hipStream_t st)
+{
+    if (P <= 0) return;
+    bucket_table_kernel<<<grid_for(P, 256), 256, 0, st>>>(b, P, binst);
+    PCHECK_LAUNCH();
+}
+
+void launch_sample_lists(const Batch &b, uint32_t ell, int64_t m, const int32_t *ids, int32_t T_max,
                          uint32_t *lists, uint64_t *prio, hipStream_t st)
 {
     if (m <= 0) return;
-    const int B = T <= 64 ? 256 : (T <= 128 ? 128 : 64);
-    const size_t lds = (size_t)T * B * sizeof(uint32_t);
+    const int B = T_max <= 64 ? 256 : (T_max <= 128 ? 128 : 64);
+    const size_t lds = (size_t)T_max * B * sizeof(uint32_t);
     const int64_t blocks = (m + B - 1) / B;
-    sample_lists_kernel<<<(unsigned)blocks, B, lds, st>>>(seed, ell, m, ids, P, T, lists, prio);
+    sample_lists_kernel<<<(unsigned)blocks, B, lds, st>>>(b, ell, m, ids, lists, prio);
     PCHECK_LAUNCH();
 }
 
@@ -277,11 +352,11 @@ void launch_bucket_count(const uint32_t *lists, int64_t entries, uint32_t *bcnt,
     PCHECK_LAUNCH();
 }
 
-void launch_bucket_scatter(const uint32_t *lists, int64_t m, int32_t T, const int64_t *bstart, uint32_t *bfill,
-                           uint32_t *bmem, uint8_t *bslot, hipStream_t st)
+void launch_bucket_scatter(const uint32_t *lists, int64_t m, const int64_t *loff, const int64_t *bstart,
+                           uint32_t *bfill, uint32_t *bmem, uint8_t *bslot, hipStream_t st)
 {
     if (m <= 0) return;
-    bucket_scatter_kernel<<<grid_for(m * T, 256), 256, 0, st>>>(lists, m, T, bstart, bfill, bmem, bslot);
+    bucket_scatter_kernel<<<grid_for(m, 256), 256, 0, st>>>(lists, m, loff, bstart, bfill, bmem, bslot);
     PCHECK_LAUNCH();
 }
 
@@ -328,17 +403,18 @@ void launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t st)
 }
 
 void launch_bucket_sort(const int64_t *bstart, int64_t P, uint32_t *bmem, uint8_t *bslot, const uint64_t *prio,
-                        int64_t *pos_of, int32_t T, bool has_large, uint32_t *tmp_mem, uint8_t *tmp_slot,
-                        hipStream_t st)
+                        int64_t *pos_of, const int64_t *loff, bool has_large, uint32_t *tmp_mem,
+                        uint8_t *tmp_slot, hipStream_t st)
 {
     if (P <= 0) return;
     const unsigned grid = (unsigned)(P < (1 << 20) ? P : (1 << 20));
-    bucket_sort_kernel<<<grid, kSortThreads, 0, st>>>(bstart, P, bmem, bslot, prio, pos_of, T);
+    bucket_sort_kernel<<<grid, kSortThreads, 0, st>>>(bstart, P, bmem, bslot, prio, pos_of, loff);
     PCHECK_LAUNCH();
     if (has_large) {
         bucket_rank_kernel<<<grid, kSortThreads, 0, st>>>(bstart, P, bmem, bslot, prio, tmp_mem, tmp_slot);
         PCHECK_LAUNCH();
-        bucket_rank_copy_kernel<<<grid, kSortThreads, 0, st>>>(bstart, P, bmem, bslot, tmp_mem, tmp_slot, pos_of, T);
+        bucket_rank_copy_kernel<<<grid, kSortThreads, 0, st>>>(bstart, P, bmem, bslot, tmp_mem, tmp_slot, pos_of,
+                                                                 loff);
         PCHECK_LAUNCH();
     }
 }

@@ -119,7 +119,8 @@ __global__ void __launch_bounds__(kWave * kRelWaves) relate_kernel(RelateArgs a)
         const int64_t rt = item - a.tile_off[c];
         const int64_t base = a.bstart[c];
         const int64_t S = a.bstart[c + 1] - base;
-        if (S <= a.mfma_max_members) continue;  // done by the MFMA kernel
+        if (S <= a.mfma_max_members) continue;        // done by the MFMA kernel
+        if (a.inst[a.binst[c]].rel != REL) continue;  // the other relation's launch
         const int64_t nw = (S + 63) >> 6;
         uint64_t *Rm = a.R + a.rb_off[c];
         const int64_t i = rt * kWave + lane;
@@ -215,7 +216,11 @@ __global__ void __launch_bounds__(kMfmaThreads) relate_mfma_kernel(RelateArgs a,
     for (int64_t c = blockIdx.x; c < a.P; c += gridDim.x) {
         const int64_t base = a.bstart[c];
         const int64_t S = a.bstart[c + 1] - base;
-        if (S < 2 || S > a.mfma_max_members) continue;
+        if (S < 1 || S > a.mfma_max_members || a.inst[a.binst[c]].rel != REL) continue;
+        if (S == 1) {  // a single member: its one row word holds no pair
+            if (t == 0) a.R[a.rb_off[c]] = 0ull;
+            continue;
+        }
         const int nt = (int)((S + 31) >> 5);
         const int Sp = nt * 32;           // padded rows (zero strings)
         __syncthreads();
@@ -258,7 +263,13 @@ __global__ void __launch_bounds__(kMfmaThreads) relate_mfma_kernel(RelateArgs a,
                     bv = *reinterpret_cast<const v4i *>(rb + boff);
                 } else {
                     bv = *reinterpret_cast<const v4i *>(rb + off);
-                    if (off >= qpad) bv = bv * 255;  // 0/1 bytes -> 0/-1 bytes
+                    if (off >= qpad) {
+                        // 0/1 bytes -> 0/-1 bytes: spread bit 0 of each byte over
+                        // its byte (no carry crosses a byte boundary)
+                        bv |= bv << 1;
+                        bv |= bv << 2;
+                        bv |= bv << 4;
+                    }
                 }
                 acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(av, bv, acc, 0, 0, 0);
             }
@@ -369,7 +380,7 @@ __global__ void __launch_bounds__(kDupThreads) dup_kernel(DupArgs a)
         const int64_t nw = (S + 63) >> 6;
         uint64_t *Dm = a.D + a.rb_off[c];
         bool overflow = false;
-        int64_t lo = 0, win = kDupWindow;
+        int64_t lo = a.inst[a.binst[c]].pal, win = kDupWindow;  // colours below c of this instance
         while (lo < c) {
             const int64_t hi = lo + win < c ? lo + win : c;
             const int words = (int)((hi - lo + 31) >> 5);
@@ -394,7 +405,7 @@ __global__ void __launch_bounds__(kDupThreads) dup_kernel(DupArgs a)
                                 else h = mid;
                             }
                             mem[j] = l;
-                            col[j] = a.lists[(int64_t)mv[l] * a.T + (e - koff[l])];
+                            col[j] = a.lists[a.loff[mv[l]] + (e - koff[l])];
                         }
                     }
 #pragma unroll
@@ -470,7 +481,7 @@ __global__ void __launch_bounds__(256) dup_slow_kernel(DupArgs a, int64_t n_slow
         for (int64_t p = threadIdx.x; p < S; p += blockDim.x) {
             const int kp = a.bslot[base + p];
             if (kp == 0) continue;
-            const uint32_t *Lp = a.lists + (int64_t)a.bmem[base + p] * a.T;
+            const uint32_t *Lp = a.lists + a.loff[a.bmem[base + p]];
             for (int64_t w = 0; w < nw; ++w) {
                 uint64_t bits = Rm[p * nw + w];
                 while (bits) {
@@ -478,7 +489,7 @@ __global__ void __launch_bounds__(256) dup_slow_kernel(DupArgs a, int64_t n_slow
                     bits &= bits - 1;
                     const int kq = a.bslot[base + q];
                     if (kq == 0) continue;
-                    const uint32_t *Lq = a.lists + (int64_t)a.bmem[base + q] * a.T;
+                    const uint32_t *Lq = a.lists + a.loff[a.bmem[base + q]];
                     int x = 0, y = 0;
                     bool shared = false;
                     while (x < kp && y < kq) {
@@ -509,7 +520,7 @@ __global__ void __launch_bounds__(kWave) count_kernel(CsrArgs a)
         for (int64_t p = threadIdx.x; p < S; p += kWave) {
             int cnt = 0;
             for (int64_t w = 0; w < nw; ++w) cnt += __popcll(Rm[p * nw + w] & ~Dm[p * nw + w]);
-            a.slot_cnt[(int64_t)a.bmem[base + p] * a.T + a.bslot[base + p]] = cnt;
+            a.slot_cnt[a.loff[a.bmem[base + p]] + a.bslot[base + p]] = cnt;
         }
     }
 }
@@ -542,7 +553,7 @@ __global__ void __launch_bounds__(kWave * kFillWaves) fill_kernel(CsrArgs a)
             for (int64_t p = threadIdx.x; p < S; p += blockDim.x) {
                 const uint32_t v = a.bmem[base + p];
                 mv[p] = v;
-                seg[p] = a.slot_off[(int64_t)v * a.T + a.bslot[base + p]];
+                seg[p] = a.slot_off[a.loff[v] + a.bslot[base + p]];
             }
             for (int64_t w = threadIdx.x; w < S * nw; w += blockDim.x) rows[w] = Rm[w] & ~Dm[w];
             __syncthreads();
@@ -559,7 +570,7 @@ __global__ void __launch_bounds__(kWave * kFillWaves) fill_kernel(CsrArgs a)
         } else {
             for (int64_t p = wave; p < S; p += kFillWaves) {
                 const uint32_t vp = a.bmem[base + p];
-                int64_t at = a.slot_off[(int64_t)vp * a.T + a.bslot[base + p]];
+                int64_t at = a.slot_off[a.loff[vp] + a.bslot[base + p]];
                 for (int64_t w = 0; w < nw; ++w) {
                     const uint64_t bits = Rm[p * nw + w] & ~Dm[p * nw + w];
                     const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bits >> 32),
@@ -572,10 +583,10 @@ __global__ void __launch_bounds__(kWave * kFillWaves) fill_kernel(CsrArgs a)
     }
 }
 
-__global__ void rowptr_kernel(const int64_t *slot_off, int64_t m, int32_t T, int64_t *rowptr)
+__global__ void rowptr_kernel(const int64_t *slot_off, int64_t m, const int64_t *loff, int64_t *rowptr)
 {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v <= m; v += (int64_t)gridDim.x * blockDim.x)
-        rowptr[v] = slot_off[v * T];
+        rowptr[v] = slot_off[loff[v]];
 }
 
 unsigned grid_cap(int64_t items, int64_t cap = 1 << 22)
@@ -684,10 +695,10 @@ void launch_fill(const CsrArgs &a, hipStream_t st)
     PCHECK_LAUNCH();
 }
 
-void launch_rowptr(const int64_t *slot_off, int64_t m, int32_t T, int64_t *rowptr, hipStream_t st)
+void launch_rowptr(const int64_t *slot_off, int64_t m, const int64_t *loff, int64_t *rowptr, hipStream_t st)
 {
     const int64_t b = (m + 1 + 255) / 256;
-    rowptr_kernel<<<grid_cap(b, 65535 * 16), 256, 0, st>>>(slot_off, m, T, rowptr);
+    rowptr_kernel<<<grid_cap(b, 65535 * 16), 256, 0, st>>>(slot_off, m, loff, rowptr);
     PCHECK_LAUNCH();
 }
 

@@ -1,10 +1,11 @@
-"""Write stored oracle results for the full-size single-instance workloads.
+"""Write stored oracle results for the full-size workloads.
 
 Calls only the CPU oracle (oracle/) and the seeded input generator; the
 HIP path is never involved.  Each JSON file holds the colour count, the
 SHA-256 of the little-endian int32 colour array and the per-iteration sizes.
 
     python tests/golden/make_golden.py C2 [seed ...]
+    python tests/golden/make_golden.py C3 [workers]   # the 512-instance batch
 """
 import hashlib
 import json
@@ -23,8 +24,51 @@ from paper_2401_06713_amd import workloads as wl  # noqa: E402
 CONFIGS = {"C1": wl.C1, "C2": wl.C2, "C4": wl.C4}
 
 
+def _batch_one(i):
+    cfg = wl.batch_instances()[i]
+    x, z = wl.make(cfg)
+    t = time.time()
+    nc, col, st = oracle.color(x, z, cfg.q, cfg.seed, cfg.frac, cfg.alpha, cfg.relation)
+    return {
+        "index": i,
+        "n": cfg.n,
+        "q": cfg.q,
+        "pI": cfg.probs[0],
+        "seed": cfg.seed,
+        "relation": cfg.relation,
+        "n_colors": nc,
+        "n_iters": len(st),
+        "colors_sha256": hashlib.sha256(np.ascontiguousarray(col, dtype="<i4").tobytes()).hexdigest(),
+        "oracle_seconds": round(time.time() - t, 2),
+    }
+
+
+def batch_main(workers):
+    from multiprocessing import Pool
+
+    oracle.build(force=False)
+    cfgs = wl.batch_instances()
+    count = len(cfgs)
+    # largest first, so the pool ends evenly
+    order = sorted(range(count), key=lambda i: -cfgs[i].n)
+    with Pool(workers) as pool:
+        recs = []
+        for k, r in enumerate(pool.imap_unordered(_batch_one, order)):
+            recs.append(r)
+            if k % 32 == 0:
+                print(f"{k + 1}/{count}", flush=True)
+    recs.sort(key=lambda r: r["index"])
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c3_batch.json")
+    with open(out, "w") as f:
+        json.dump({"config": "C3 512 instances, n log-uniform [500, 50000], q in 20..64",
+                   "frac": 0.125, "alpha": 2.0, "instances": recs}, f, indent=0)
+    print(out, sum(r["n_colors"] for r in recs), flush=True)
+
+
 def main():
     name = sys.argv[1]
+    if name == "C3":
+        return batch_main(int(sys.argv[2]) if len(sys.argv) > 2 else 6)
     seeds = [int(s) for s in sys.argv[2:]] or [0]
     cfg = CONFIGS[name]
     oracle.build(force=False)

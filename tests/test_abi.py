@@ -33,3 +33,8 @@ def test_stats_struct_layout():
     # picasso_iter_stats: 7 int64 + 2 int32 + 6 double = 112 bytes
     assert ctypes.sizeof(pk.IterStats) == 112
     assert ctypes.sizeof(pk.Stats) == 7 * 8 + 8 + 8 + 112 * pk.MAX_ITER_STATS
+
+
+def test_instance_stats_struct_layout():
+    # picasso_instance_stats: 5 int64 + 2 int32 = 48 bytes
+    assert ctypes.sizeof(pk.InstanceStats) == 48
