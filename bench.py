@@ -66,11 +66,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="C2", choices=["C1", "C2", "C4"])
+    ap.add_argument("--config", default="C2", choices=["C1", "C2", "C3", "C4"])
     ap.add_argument("--path", default="auto", choices=["auto", "valu", "mfma"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape tuner (defaults are used)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -85,27 +86,63 @@ def main():
     import torch
 
     import paper_2401_06713_amd as pk
+    from paper_2401_06713_amd import tune
     from paper_2401_06713_amd import workloads as wl
 
-    cfg = {"C1": wl.C1, "C2": wl.C2, "C4": wl.C4}[args.config]
-    log(f"bench: generating {cfg.name}")
-    x, z = wl.make(cfg)
     torch.cuda.set_device(0)
-    xd = torch.from_numpy(x.view(np.int64)).cuda()
-    zd = torch.from_numpy(z.view(np.int64)).cuda()
-    out = torch.empty(cfg.n, dtype=torch.int32, device="cuda")
-    h = pk.Picasso(xd, zd, cfg.q)
-    h.set_option(pk.OPT_PAIR_PATH, {"auto": 0, "valu": 1, "mfma": 2}[args.path])
+    batch = args.config == "C3"
+    if batch:
+        cfgs = wl.batch_instances()
+        log(f"bench: generating {len(cfgs)} batch instances")
+        insts = [wl.make(c) for c in cfgs]
+        h = pk.PicassoBatch([(x, z, c.q) for (x, z), c in zip(insts, cfgs)])
+        out = torch.empty(h.n, dtype=torch.int32, device="cuda")
+        run_args = ([c.seed for c in cfgs], [c.frac for c in cfgs], [c.alpha for c in cfgs],
+                    [c.relation for c in cfgs])
+
+        def step():
+            return int(h.color_batch_device(out, *run_args).sum())
+
+        cfg = max(cfgs, key=lambda c: c.n)  # the CPU baseline's sample instance
+        x, z = insts[cfgs.index(cfg)]
+        workload = {"workload": f"C3 batch of {len(cfgs)} instances, n log-uniform [500, 50000], q in 20..64, "
+                                "pI in [0.5, 0.85], anticommute or QWC per instance",
+                    "instances": len(cfgs), "total_strings": h.n, "palette_frac": 0.125, "list_size_alpha": 2.0}
+    else:
+        cfg = {"C1": wl.C1, "C2": wl.C2, "C4": wl.C4}[args.config]
+        log(f"bench: generating {cfg.name}")
+        x, z = wl.make(cfg)
+        xd = torch.from_numpy(x.view(np.int64)).cuda()
+        zd = torch.from_numpy(z.view(np.int64)).cuda()
+        out = torch.empty(cfg.n, dtype=torch.int32, device="cuda")
+        h = pk.Picasso(xd, zd, cfg.q)
+        run_args = (args.seed, cfg.frac, cfg.alpha, cfg.relation)
+
+        def step():
+            return h.color_device(out, *run_args)
+
+        workload = {"workload": cfg.name, "n": cfg.n, "q": cfg.q, "probs": list(cfg.probs), "seed": args.seed,
+                    "palette_frac": cfg.frac, "list_size_alpha": cfg.alpha,
+                    "relation": ["anticommute", "qwc"][cfg.relation]}
+    tuned = None
+    if args.path == "auto" and not args.no_tune:
+        if batch:
+            tuned = tune.tune(h, *run_args, use_cache=False, log=log)
+        else:
+            tuned = tune.tune(h, [args.seed], [cfg.frac], [cfg.alpha], [cfg.relation], use_cache=False, log=log)
+        log(f"bench: tuned {tuned}")
+    else:
+        h.set_option(pk.OPT_PAIR_PATH, {"auto": 0, "valu": 1, "mfma": 2}[args.path])
     h.set_option(pk.OPT_TIMING, 1)
 
     for i in range(args.warmup):
-        nc = h.color_device(out, args.seed, cfg.frac, cfg.alpha, cfg.relation)
+        nc = step()
         log(f"bench: warmup {i + 1}/{args.warmup}: {nc} colours")
     torch.cuda.synchronize()
     per_step = []
     t0 = time.perf_counter()
     for i in range(args.steps):
-        nc = h.color_device(out, args.seed, cfg.frac, cfg.alpha, cfg.relation)
+        nc = step()
         per_step.append(h.stats())
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -115,17 +152,18 @@ def main():
     pair_tests = st["pair_tests"]
     edges = st["edges"]
 
-    # dominant kernel: the pair count pass (every pair test), timed with HIP
-    # events on the library's stream around each launch
+    # dominant kernel: the pair pass (every pair test), timed with HIP events
+    # on the library's stream around its launches
     count_ms = sum(it["ms_count"] for s in per_step for it in s["iters"])
     fill_ms = sum(it["ms_fill"] for s in per_step for it in s["iters"])
     color_ms = sum(it["ms_color"] for s in per_step for it in s["iters"])
     launches = sum(len(s["iters"]) for s in per_step)
-    W = (cfg.q + 63) // 64
+    q_ops = h.q  # MFMA work per pair: a dot product of 2q bytes (largest q of a batch)
+    W = (h.q + 63) // 64
     ops_per_test = 8 * W + 1
     mfma = any(it["pair_path"] == pk.PATH_MFMA for it in st["iters"])
     if mfma:
-        ops = sum(2 * (2 * cfg.q) * s["pair_tests"] for s in per_step)
+        ops = sum(2 * (2 * q_ops) * s["pair_tests"] for s in per_step)
         achieved = ops / (count_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": MFMA_I8_PEAK_TOPS, "unit": "TOPS",
                 "frac": achieved / MFMA_I8_PEAK_TOPS, "traffic": None}
@@ -134,10 +172,13 @@ def main():
         achieved = ops / (count_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
                 "frac": achieved / VALU_PEAK_TOPS, "traffic": None}
-    roof["kernel"] = "pair count pass"
+    roof["kernel"] = "pair pass (relation bit matrices)"
     roof["avg_launch_ms"] = count_ms / max(launches, 1)
     roof["launches"] = launches
 
+    workload["pair_path"] = args.path
+    if tuned:
+        workload["tuned"] = {k: tuned[k] for k in ("cap", "jp_batch", "graph")}
     line = {
         "metric": METRIC,
         "value": pair_tests / (ms_step * 1e-3),
@@ -151,16 +192,14 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": cfg.name, "n": cfg.n, "q": cfg.q, "probs": list(cfg.probs), "seed": args.seed,
-                   "palette_frac": cfg.frac, "list_size_alpha": cfg.alpha,
-                   "relation": ["anticommute", "qwc"][cfg.relation], "pair_path": args.path},
+        "config": workload,
         "end_to_end_s": ms_step * 1e-3,
         "n_colors": nc,
         "iterations": st["n_iters"],
         "pair_tests": pair_tests,
         "conflict_edges": edges,
         "conflict_edges_per_s": edges / (ms_step * 1e-3),
-        "phase_ms_per_step": {"pair_count": count_ms / args.steps, "pair_fill": fill_ms / args.steps,
+        "phase_ms_per_step": {"pair_pass": count_ms / args.steps, "pair_fill": fill_ms / args.steps,
                               "list_color": color_ms / args.steps},
         "peak_device_bytes": st["peak_device_bytes"],
         "roofline": roof,

@@ -67,9 +67,13 @@ enum {
     PICASSO_OPT_TIMING = 5,     /* 1: record per-phase times (adds event syncs)  */
     PICASSO_OPT_JP_BATCH = 6,   /* colouring rounds launched between two host
                                    checks of progress, at most (1..1024; 16)    */
-    PICASSO_OPT_GRAPH = 7       /* 1 (default): a full batch of colouring rounds
+    PICASSO_OPT_GRAPH = 7,      /* 1 (default): a full batch of colouring rounds
                                    is captured once per iteration into a HIP
                                    graph and replayed; 0: plain launches        */
+    PICASSO_OPT_MFMA_CAP = 8    /* MFMA pair path: buckets of at most this many
+                                   members take the MFMA kernel, larger ones the
+                                   popcount tile kernel; -1 (default) = as many
+                                   as the kernel's LDS rows hold for this q      */
 };
 
 #define PICASSO_PATH_AUTO 0
@@ -182,6 +186,13 @@ int64_t picasso_color_device(picasso_handle h, uint64_t seed, double palette_fra
 int64_t picasso_color_batch(picasso_handle h, const uint64_t *seeds, const double *palette_fracs,
                             const double *list_sizes, const int32_t *relations, int32_t *out_colors,
                             int64_t *out_n_colors);
+
+/* As picasso_color_batch, but out_colors is a device pointer (int32, the
+ * total number of strings); out_n_colors stays on the host.  The result is
+ * complete when the call returns. */
+int64_t picasso_color_batch_device(picasso_handle h, const uint64_t *seeds, const double *palette_fracs,
+                                   const double *list_sizes, const int32_t *relations, int32_t *out_colors,
+                                   int64_t *out_n_colors);
 
 /* Copy the last colouring call's statistics (for a batch: iterations
  * aggregated over the instances: m, P, pair_tests, edges, colored summed,

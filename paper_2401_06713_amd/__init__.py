@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(_PKG, "libpicasso.so")
 REL_ANTICOMMUTE = 0
 REL_QWC = 1
 PATH_AUTO, PATH_VALU, PATH_MFMA = 0, 1, 2
-OPT_MEM_BUDGET, OPT_PAIR_PATH, OPT_FIXED_T, OPT_STREAM, OPT_TIMING, OPT_JP_BATCH, OPT_GRAPH = 1, 2, 3, 4, 5, 6, 7
+(OPT_MEM_BUDGET, OPT_PAIR_PATH, OPT_FIXED_T, OPT_STREAM, OPT_TIMING, OPT_JP_BATCH, OPT_GRAPH,
+ OPT_MFMA_CAP) = 1, 2, 3, 4, 5, 6, 7, 8
 MAX_T = 256
 MAX_ITER_STATS = 256
 
@@ -36,6 +37,7 @@ EXPORTS = (
     "picasso_color",
     "picasso_color_device",
     "picasso_color_batch",
+    "picasso_color_batch_device",
     "picasso_get_stats",
     "picasso_get_instance_stats",
     "picasso_sample_lists",
@@ -150,6 +152,8 @@ def lib() -> ctypes.CDLL:
     L.picasso_create_batch.argtypes = [i32, p, p, p, p]
     L.picasso_color_batch.restype = i64
     L.picasso_color_batch.argtypes = [p, p, p, p, p, p, p]
+    L.picasso_color_batch_device.restype = i64
+    L.picasso_color_batch_device.argtypes = [p, p, p, p, p, p, p]
     L.picasso_get_instance_stats.restype = i32
     L.picasso_get_instance_stats.argtypes = [p, i32, p]
     L.picasso_destroy.restype = None
@@ -361,15 +365,29 @@ class PicassoBatch(Picasso):
     def color_batch(self, seeds, palette_fracs, list_sizes, relations):
         """Returns (n_colors int64[count], [colors int32[n_i] per instance])."""
         k = self.count
-        seeds = np.ascontiguousarray(np.broadcast_to(np.asarray(seeds, dtype=np.uint64), (k,)))
-        fr = np.ascontiguousarray(np.broadcast_to(np.asarray(palette_fracs, dtype=np.float64), (k,)))
-        al = np.ascontiguousarray(np.broadcast_to(np.asarray(list_sizes, dtype=np.float64), (k,)))
-        rel = np.ascontiguousarray(np.broadcast_to(np.asarray(relations, dtype=np.int32), (k,)))
+        seeds, fr, al, rel = self._batch_args(seeds, palette_fracs, list_sizes, relations)
         out = np.empty(max(self.n, 1), dtype=np.int32)
         nc = np.zeros(max(k, 1), dtype=np.int64)
         _check(lib().picasso_color_batch(self._h, _ptr(seeds), _ptr(fr), _ptr(al), _ptr(rel), _ptr(out), _ptr(nc)))
         cols = [out[self.offsets[i]:self.offsets[i + 1]].copy() for i in range(k)]
         return nc[:k], cols
+
+    def color_batch_device(self, out, seeds, palette_fracs, list_sizes, relations):
+        """Colours into a device int32 tensor `out` (total strings); returns
+        n_colors int64[count] (instance i's colours at out[offsets[i]:offsets[i+1]])."""
+        assert out.is_cuda and out.numel() >= self.n
+        k = self.count
+        args = self._batch_args(seeds, palette_fracs, list_sizes, relations)
+        nc = np.zeros(max(k, 1), dtype=np.int64)
+        _check(lib().picasso_color_batch_device(self._h, *map(_ptr, args), ctypes.c_void_p(out.data_ptr()), _ptr(nc)))
+        return nc[:k]
+
+    def _batch_args(self, seeds, palette_fracs, list_sizes, relations):
+        k = self.count
+        return (np.ascontiguousarray(np.broadcast_to(np.asarray(seeds, dtype=np.uint64), (k,))),
+                np.ascontiguousarray(np.broadcast_to(np.asarray(palette_fracs, dtype=np.float64), (k,))),
+                np.ascontiguousarray(np.broadcast_to(np.asarray(list_sizes, dtype=np.float64), (k,))),
+                np.ascontiguousarray(np.broadcast_to(np.asarray(relations, dtype=np.int32), (k,))))
 
 
 class Mlp:

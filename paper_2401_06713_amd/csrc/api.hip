@@ -76,6 +76,7 @@ struct picasso_ctx {
     int32_t timing = 0;
     int32_t jp_batch = 16;   // colouring rounds per host check, at most
     int32_t use_graph = 1;   // replay colouring rounds from a captured graph
+    int64_t mfma_cap = -1;   // largest bucket for the MFMA kernel (-1: as large as LDS allows)
     Arena arena;
     DevBuf x, z;
     // iteration buffers
@@ -314,7 +315,11 @@ int64_t build_conflict_graph(picasso_ctx *h, const Batch &b, int64_t m, int64_t 
         if (mfma && !mfma_supported(h->q, rel))
             throw Error(PICASSO_EINVAL, "the MFMA pair path does not support this q and relation");
         ra.relation = rel;
-        ra.mfma_max_members = mfma ? mfma_member_cap(h->q, rel) : -1;
+        ra.mfma_max_members = -1;
+        if (mfma) {
+            ra.mfma_max_members = mfma_member_cap(h->q, rel);
+            if (h->mfma_cap >= 0 && h->mfma_cap < ra.mfma_max_members) ra.mfma_max_members = h->mfma_cap;
+        }
         any_mfma |= mfma;
         if (mfma) launch_relate_mfma(ra, h->q, st);
         if (!mfma || bi.max_size > ra.mfma_max_members) launch_relate(ra, st);
@@ -919,6 +924,10 @@ int32_t picasso_set_option(picasso_handle h, int32_t key, int64_t value)
                 case PICASSO_OPT_GRAPH:
                     h->use_graph = value != 0;
                     break;
+                case PICASSO_OPT_MFMA_CAP:
+                    if (value < -1 || value > 4096) throw Error(PICASSO_EINVAL, "MFMA bucket cap must be in [-1, 4096]");
+                    h->mfma_cap = value;
+                    break;
                 default:
                     throw Error(PICASSO_EINVAL, "unknown option");
             }
@@ -973,9 +982,9 @@ int64_t picasso_color(picasso_handle h, uint64_t seed, double palette_frac, doub
         PICASSO_EINTERNAL);
 }
 
-int64_t picasso_color_batch(picasso_handle h, const uint64_t *seeds, const double *palette_fracs,
-                            const double *list_sizes, const int32_t *relations, int32_t *out_colors,
-                            int64_t *out_n_colors)
+static int64_t color_batch_impl(picasso_handle h, const uint64_t *seeds, const double *palette_fracs,
+                                const double *list_sizes, const int32_t *relations, int32_t *out_colors,
+                                int64_t *out_n_colors, bool device_out)
 {
     return guarded(
         [&]() -> int64_t {
@@ -990,13 +999,27 @@ int64_t picasso_color_batch(picasso_handle h, const uint64_t *seeds, const doubl
                 for (int32_t i = 0; i < h->nb; ++i) out_n_colors[i] = 0;
                 return 0;
             }
-            int32_t *d_out = buf<int32_t>(h, h->out_colors, (size_t)h->n);
+            int32_t *d_out = device_out ? out_colors : buf<int32_t>(h, h->out_colors, (size_t)h->n);
             RunArgs ra{seeds, palette_fracs, list_sizes, relations};
             const int64_t nc = color_all(h, ra, d_out, out_n_colors);
-            download(h, out_colors, d_out, (size_t)h->n * sizeof(int32_t));
+            if (!device_out) download(h, out_colors, d_out, (size_t)h->n * sizeof(int32_t));
             return nc;
         },
         PICASSO_EINTERNAL);
+}
+
+int64_t picasso_color_batch(picasso_handle h, const uint64_t *seeds, const double *palette_fracs,
+                            const double *list_sizes, const int32_t *relations, int32_t *out_colors,
+                            int64_t *out_n_colors)
+{
+    return color_batch_impl(h, seeds, palette_fracs, list_sizes, relations, out_colors, out_n_colors, false);
+}
+
+int64_t picasso_color_batch_device(picasso_handle h, const uint64_t *seeds, const double *palette_fracs,
+                                   const double *list_sizes, const int32_t *relations, int32_t *out_colors,
+                                   int64_t *out_n_colors)
+{
+    return color_batch_impl(h, seeds, palette_fracs, list_sizes, relations, out_colors, out_n_colors, true);
 }
 
 int32_t picasso_get_instance_stats(picasso_handle h, int32_t count, picasso_instance_stats *out)
