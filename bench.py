@@ -67,11 +67,14 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="C2", choices=["C1", "C2", "C3", "C4"])
-    ap.add_argument("--path", default="auto", choices=["auto", "valu", "mfma"])
+    ap.add_argument("--path", default="valu", choices=["auto", "valu", "mfma"],
+                    help="pair pass: popcount tile kernel (valu), int8 MFMA kernel with popcount for buckets "
+                         "above its LDS cap (mfma), or the library's choice (auto)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape tuner (defaults are used)")
+    ap.add_argument("--tune", action="store_true",
+                    help="run the launch-shape tuner first (its colourings run before the warm-up)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -125,7 +128,7 @@ def main():
                     "palette_frac": cfg.frac, "list_size_alpha": cfg.alpha,
                     "relation": ["anticommute", "qwc"][cfg.relation]}
     tuned = None
-    if args.path == "auto" and not args.no_tune:
+    if args.tune:
         if batch:
             tuned = tune.tune(h, *run_args, use_cache=False, log=log)
         else:

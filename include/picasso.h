@@ -66,7 +66,7 @@ enum {
                                    stream alive while the handle uses it.        */
     PICASSO_OPT_TIMING = 5,     /* 1: record per-phase times (adds event syncs)  */
     PICASSO_OPT_JP_BATCH = 6,   /* colouring rounds launched between two host
-                                   checks of progress, at most (1..1024; 16)    */
+                                   checks of progress, at most (1..1024; 32)    */
     PICASSO_OPT_GRAPH = 7,      /* 1 (default): a full batch of colouring rounds
                                    is captured once per iteration into a HIP
                                    graph and replayed; 0: plain launches        */

@@ -74,7 +74,7 @@ struct picasso_ctx {
     int32_t pair_path = PICASSO_PATH_AUTO;
     int32_t fixed_T = 0;
     int32_t timing = 0;
-    int32_t jp_batch = 16;   // colouring rounds per host check, at most
+    int32_t jp_batch = 32;   // colouring rounds per host check, at most
     int32_t use_graph = 1;   // replay colouring rounds from a captured graph
     int64_t mfma_cap = -1;   // largest bucket for the MFMA kernel (-1: as large as LDS allows)
     Arena arena;
@@ -652,13 +652,12 @@ int64_t color_all(picasso_ctx *h, const RunArgs &ra, int32_t *d_out, int64_t *n_
         tm.mark();
         hv.resize((size_t)3 * na);
         download(h, hv.data(), iout, hv.size() * sizeof(int64_t));
-        int64_t m_next = 0, used_now = 0;
+        int64_t m_next = 0;
         for (int32_t a = 0; a < na; ++a) {
             const int32_t i = act[a];
             const InstRec &r = h->h_inst[a];
             picasso_instance_stats &is = h->istats[i];
             n_colors[i] += hv[a];
-            used_now += hv[a];
             mi[i] = hv[na + a];
             m_next += mi[i];
             off[i] += r.P;

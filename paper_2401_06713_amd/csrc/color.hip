@@ -75,6 +75,52 @@ __device__ __forceinline__ void wake(const JpArgs &a, int64_t c2, int32_t *out, 
         out[atomicAdd(out_count, 1)] = (int32_t)c2;
 }
 
+// Slot k of v (list entries from l0, T of them) was found free: v takes
+// colour L(v)[k] or an earlier one, never a later one.  Every later slot
+// still unknown in its bucket is marked not-taken there and its bucket is
+// woken (members after v in it may have waited on v).  Groups of 4 slots:
+// independent loads, one wait so the marks are complete before any wake,
+// independent exchanges, one append per group.
+__device__ __forceinline__ void release_later_slots(const JpArgs &a, int64_t l0, int k, int T, int32_t *out,
+                                                    int32_t *out_count)
+{
+    constexpr int G = 4;
+    for (int k0 = k + 1; k0 < T; k0 += G) {
+        int64_t pos[G];
+        uint32_t cc[G];
+        bool need[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const bool ok = k0 + j < T;
+            pos[j] = ok ? a.pos_of[l0 + k0 + j] : 0;
+            cc[j] = ok ? a.lists[l0 + k0 + j] : 0u;
+            need[j] = ok;
+        }
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+            if (need[j]) need[j] = __hip_atomic_load(&a.st[pos[j]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                                   ST_UNKNOWN;
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+            if (need[j]) __hip_atomic_store(&a.st[pos[j]], ST_NOT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_s_waitcnt(0);
+        uint32_t old[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+            old[j] = need[j] ? __hip_atomic_exchange(&a.dirty[cc[j]], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                             : 1u;
+        int n = 0;
+#pragma unroll
+        for (int j = 0; j < G; ++j) n += old[j] == 0u;
+        if (n) {
+            int at = atomicAdd(out_count, n);
+#pragma unroll
+            for (int j = 0; j < G; ++j)
+                if (old[j] == 0u) out[at++] = (int32_t)cc[j];
+        }
+    }
+}
+
 // First slot of v not known blocked (T if all are).
 __device__ __forceinline__ int first_open(const uint64_t *blk, int T)
 {
@@ -90,15 +136,22 @@ __device__ __forceinline__ int first_open(const uint64_t *blk, int T)
 
 constexpr int kJpStage = 1024;  // members whose (vertex, slot) are staged in LDS
 
-// Resolve what can be resolved in bucket c (passes until nothing changes).
+// Resolve what can be resolved in bucket c.  A member depends only on the
+// members before it in the bucket's priority order (a vertex appears in a
+// bucket once), so one sweep in that order reaches the fixpoint: the wave
+// walks the bucket in chunks of 64 members, each lane loading its member's
+// relation row prefix, colour and slot masks once; dependencies inside a
+// chunk settle in registers (ballots), and the chunk's final taken/unknown
+// bits are what later chunks see.
 // Cross-bucket effects wake the buckets they may unblock:
 //  - a slot of v found free for the first time: v will not take any later
-//    slot, so the buckets of v's later slots are woken;
+//    slot, so v's later slots still unknown are marked not-taken and their
+//    buckets woken;
 //  - a blocked slot that completes v's blocked prefix up to slot f: the
 //    bucket of f is woken (v may now take it).
 // Taking a colour needs no wake of its own: the slot was found free first.
 __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t *tak, uint64_t *unk, uint32_t *mv,
-                               uint8_t *mk, int *changed_any, int32_t *out, int32_t *out_count)
+                               uint8_t *mk, int32_t *out, int32_t *out_count)
 {
     const int lane = threadIdx.x;
     const int64_t base = a.bstart[c];
@@ -118,35 +171,46 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t *tak, uint64
         if (s == ST_UNKNOWN) atomicOr((unsigned long long *)&unk[p >> 6], 1ull << (p & 63));
         else if (s == ST_TAKEN) atomicOr((unsigned long long *)&tak[p >> 6], 1ull << (p & 63));
     }
-    while (true) {
-        if (lane == 0) *changed_any = 0;
-        __syncthreads();
-        int changed = 0;
-        for (int64_t p = lane; p < S; p += kWave) {
-            const uint64_t bit = 1ull << (p & 63);
-            if (!(unk[p >> 6] & bit)) continue;
-            const int64_t v = staged ? mv[p] : a.bmem[base + p];
-            const int k = staged ? mk[p] : a.bslot[base + p];
-            uint64_t *blk = a.blk + v * a.fw;
-            uint64_t *fre = a.fre + v * a.fw;
-            const int64_t l0 = a.loff[v];
-            const int T = (int)(a.loff[v + 1] - l0);
-            const int32_t cv = load_i32(&a.col[v]);
+    __syncthreads();
+    const uint64_t below = (1ull << lane) - 1ull;  // lanes before this one
+    for (int64_t ch = 0; ch < nw; ++ch) {
+        uint64_t unk_ch = unk[ch];
+        if (unk_ch == 0ull) continue;  // wave-uniform
+        uint64_t tak_ch = tak[ch];
+        const int64_t p = ch * kWave + lane;
+        bool open = (unk_ch >> lane) & 1ull;  // still to decide in this sweep
+        bool hit_tak_prev = false, hit_unk_prev = false;
+        uint64_t own = 0ull;
+        int64_t v = 0, l0 = 0;
+        int k = 0, T = 0;
+        int32_t cv = COL_UNDECIDED;
+        uint64_t fre0 = 0ull;  // v's free-slot mask (one word) as loaded for this chunk
+        if (open) {
+            // earlier chunks are final for this sweep
+            for (int64_t w = 0; w < ch; ++w) {
+                const uint64_t r = Rm[p * nw + w];
+                hit_tak_prev |= (r & tak[w]) != 0ull;
+                hit_unk_prev |= (r & unk[w]) != 0ull;
+            }
+            own = Rm[p * nw + ch] & below;
+            v = staged ? mv[p] : a.bmem[base + p];
+            k = staged ? mk[p] : a.bslot[base + p];
+            l0 = a.loff[v];
+            T = (int)(a.loff[v + 1] - l0);
+            cv = load_i32(&a.col[v]);
+            if (a.fw == 1) fre0 = load_u64(&a.fre[v]);
+        }
+        while (true) {
             uint8_t ns = ST_UNKNOWN;
-            if (cv != COL_UNDECIDED) {
-                ns = cv == (int32_t)c ? ST_TAKEN : ST_NOT;
-            } else {
-                bool hit_tak = false, hit_unk = false;
-                const int64_t pw = p >> 6;
-                for (int64_t w = 0; w <= pw; ++w) {
-                    uint64_t r = Rm[p * nw + w];
-                    if (w == pw) r &= bit - 1ull;  // earlier members only
-                    hit_tak |= (r & tak[w]) != 0ull;
-                    hit_unk |= (r & unk[w]) != 0ull;
-                }
-                if (hit_tak) {
+            bool wait = false;  // free here, waiting for v's lower slots: no change in this sweep
+            if (open) {
+                uint64_t *blk = a.blk + v * a.fw;
+                uint64_t *fre = a.fre + v * a.fw;
+                const uint64_t kb = 1ull << (k & 63);
+                if (cv != COL_UNDECIDED) {
+                    ns = cv == (int32_t)c ? ST_TAKEN : ST_NOT;
+                } else if (hit_tak_prev || (own & tak_ch)) {
                     ns = ST_NOT;
-                    const uint64_t kb = 1ull << (k & 63);
                     const uint64_t old = atomicOr((unsigned long long *)&blk[k >> 6], kb);
                     if (atomicAdd(&a.nblk[v], 1) == T - 1) {  // the last slot was blocked
                         __hip_atomic_store(&a.col[v], COL_FAILED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -161,34 +225,34 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t *tak, uint64
                         }
                         if (f > k && f < T) wake(a, a.lists[l0 + f], out, out_count);
                     }
-                } else if (any_below(fre, k)) {
+                } else if (a.fw == 1 ? (fre0 & (kb - 1ull)) != 0ull : any_below(fre, k)) {
                     ns = ST_NOT;  // an earlier slot is free: v takes that colour or an earlier one
-                } else if (!hit_unk) {
-                    const uint64_t kb = 1ull << (k & 63);
+                } else if (!hit_unk_prev && !(own & unk_ch)) {
                     const uint64_t was = atomicOr((unsigned long long *)&fre[k >> 6], kb);
                     if (all_below(blk, k)) {
                         __hip_atomic_store(&a.col[v], (int32_t)c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         atomicAdd(a.progress, 1ull);
                         ns = ST_TAKEN;
+                    } else {
+                        wait = true;
                     }
-                    if (!(was & kb)) {
-                        const uint32_t *Lv = a.lists + l0;
-                        for (int k2 = k + 1; k2 < T; ++k2) wake(a, Lv[k2], out, out_count);
-                    }
+                    if (!(was & kb)) release_later_slots(a, l0, k, T, out, out_count);
                 }
             }
-            if (ns != ST_UNKNOWN) {
-                __hip_atomic_store(&a.st[base + p], ns, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (ns == ST_TAKEN) atomicOr((unsigned long long *)&tak[p >> 6], bit);
-                atomicAnd((unsigned long long *)&unk[p >> 6], ~bit);
-                changed = 1;
-            }
+            const bool decided = ns != ST_UNKNOWN;
+            const uint64_t dec = __ballot(decided);
+            const uint64_t tk = __ballot(ns == ST_TAKEN);
+            if (decided) __hip_atomic_store(&a.st[base + p], ns, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (decided || wait) open = false;
+            tak_ch |= tk;
+            unk_ch &= ~dec;
+            if (!dec) break;  // lanes still open wait on an undecided earlier member
         }
-        if (changed) *changed_any = 1;
+        if (lane == 0) {
+            tak[ch] = tak_ch;
+            unk[ch] = unk_ch;
+        }
         __syncthreads();
-        const bool more = *changed_any != 0;
-        __syncthreads();
-        if (!more) break;
     }
 }
 
@@ -196,14 +260,13 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t *tak, uint64
 // (wl[cur], count in wl_count[cur]); state changes append the buckets they
 // may unblock to wl[cur ^ 1].  No workgroup waits on another: rounds are
 // separate launches in stream order.
-__global__ void __launch_bounds__(kWave) jp_round_kernel(JpArgs a, int cur)
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(6))) jp_round_kernel(JpArgs a, int cur)
 {
     extern __shared__ uint64_t sbits[];  // taken[nw_max], unknown[nw_max]
     uint64_t *tak = sbits;
     uint64_t *unk = sbits + a.nw_max;
     __shared__ uint32_t mv[kJpStage];
     __shared__ uint8_t mk[kJpStage];
-    __shared__ int changed_any;
     __shared__ int go;
     const int32_t n_in = a.wl_count[cur];
     int32_t *out = a.wl[cur ^ 1];
@@ -213,7 +276,7 @@ __global__ void __launch_bounds__(kWave) jp_round_kernel(JpArgs a, int cur)
         if (threadIdx.x == 0)
             go = __hip_atomic_exchange(&a.dirty[c], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
         __syncthreads();
-        if (go) resolve_bucket(a, c, tak, unk, mv, mk, &changed_any, out, out_count);
+        if (go) resolve_bucket(a, c, tak, unk, mv, mk, out, out_count);
         __syncthreads();
     }
 }

@@ -29,7 +29,7 @@ import numpy as np
 import paper_2401_06713_amd as pk
 
 CACHE_ENV = "PICASSO_TUNE_CACHE"
-DEFAULT = {"cap": -1, "jp_batch": 16, "graph": 1}
+DEFAULT = {"cap": -1, "jp_batch": 32, "graph": 1}
 CAPS = (0, 32, 64, 128, 256, -1)
 JP_BATCHES = (4, 8, 16, 32, 64)
 GRAPHS = (0, 1)
