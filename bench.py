@@ -73,6 +73,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the timed steps, copy MIB MiB device to device once (a plain copy of known size "
+                         "that calibrates the HBM byte counters of a profiler run)")
     ap.add_argument("--tune", action="store_true",
                     help="run the launch-shape tuner first (its colourings run before the warm-up)")
     args = ap.parse_args()
@@ -208,6 +211,14 @@ def main():
         "roofline": roof,
     }
     h.close()
+    if args.copy_calibration > 0:
+        src = torch.ones(args.copy_calibration << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = args.copy_calibration << 20
+        del src, dst
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a bounded sample")
         line["cpu_baseline"] = cpu_baseline(cfg, x, z, args.cpu_budget)

@@ -306,6 +306,16 @@ class Picasso:
         return rowptr, adj[: 2 * ne]
 
 
+    def conflict_rowptr(self, seed: int, ell: int, ids, P: int, T: int, relation: int):
+        """Returns (|E_c|, rowptr int64[m+1]): the CSR row pointers (vertex
+        degrees) without copying the adjacency to the host."""
+        ids = np.ascontiguousarray(ids, dtype=np.int32)
+        m = ids.shape[0]
+        rowptr = np.zeros(m + 1, dtype=np.int64)
+        ne = _check(lib().picasso_conflict_graph(self._h, seed, ell, m, _ptr(ids), P, T, relation, _ptr(rowptr),
+                                                 None, 0))
+        return ne, rowptr
+
     def features(self, seed: int, ell: int, ids, relation: int) -> np.ndarray:
         """(ln m, q, mean Pauli weight, sampled relation density, ell)."""
         ids = np.ascontiguousarray(ids, dtype=np.int32)

@@ -5,6 +5,12 @@ tests/golden/make_golden.py (which calls only the CPU oracle), plus
 properties that hold at any size: every colour class is independent in the
 relation graph, colours lie in their iteration's palette, and each
 iteration's sizes match.
+
+C4 (n=2,000,000, q=128): too large for a whole oracle run, so checked by
+properties at full size (validity of every colour class, iteration sizes
+from the parameter rule, both pair paths identical) and exactly at sampled
+vertices: iteration-1 degree and the sequential greedy choice, computed by
+the oracle from the vertex's bucket-mates.
 """
 import hashlib
 import json
@@ -88,3 +94,56 @@ def test_c2_matches_oracle(seed, path):
         if path != pk.PATH_AUTO:
             assert a["pair_path"] == path
     check_valid(x, z, col, cfg.relation)
+
+
+def test_c4_full_size_properties_and_samples(orc):
+    cfg = wl.C4
+    n, rel = cfg.n, cfg.relation
+    say("C4 generating")
+    x, z = wl.make(cfg)
+    ids = np.arange(n, dtype=np.int32)
+    with pk.Picasso(x, z, cfg.q) as h:
+        h.set_option(pk.OPT_PAIR_PATH, pk.PATH_VALU)
+        nc, col = h.color(0, cfg.frac, cfg.alpha, rel)
+        st = h.stats()
+        say("C4 valu", nc, "colours", st["n_iters"], "iterations", round(st["ms_total"], 1), "ms")
+        h.set_option(pk.OPT_PAIR_PATH, pk.PATH_AUTO)
+        nc2, col2 = h.color(0, cfg.frac, cfg.alpha, rel)
+        assert nc2 == nc and np.array_equal(col2, col)
+        P, T = orc.params(n, cfg.frac, cfg.alpha)
+        ne, rowptr = h.conflict_rowptr(0, 1, ids, P, T, rel)
+    # whole-run properties
+    assert (col >= 0).all() and np.unique(col).size == nc
+    m, off = n, 0
+    for it in st["iters"]:
+        Pl, Tl = orc.params(m, cfg.frac, cfg.alpha)
+        assert (it["m"], it["P"], it["T"], it["offset"]) == (m, Pl, Tl, off)
+        got = (col >= off) & (col < off + Pl)
+        assert got.sum() == it["colored"]
+        m -= it["colored"]
+        off += Pl
+    assert m == 0
+    check_valid(x, z, col, rel)
+    # iteration 1 against the oracle's lists and priorities
+    L = orc.sample_lists(0, 1, ids, P, T)
+    prio = orc.priorities(0, 1, ids)
+    sizes = np.bincount(L.ravel(), minlength=P).astype(np.int64)
+    assert st["iters"][0]["pair_tests"] == int((sizes * (sizes - 1) // 2).sum())
+    assert st["iters"][0]["edges"] == ne == rowptr[-1] // 2
+    order = np.argsort(L.ravel(), kind="stable")
+    bstart = np.r_[0, np.cumsum(sizes)]
+    ch = orc.decode(x, z, cfg.q)
+    rng = np.random.default_rng(44)
+    for v in rng.choice(n, 48, replace=False):
+        mates = np.unique(np.concatenate([order[bstart[c]:bstart[c + 1]] // T for c in L[v]])).astype(np.int32)
+        e, _, _ = orc.conflict_edges_bucketed(ch, mates, L[mates], P, rel)
+        lv = int(np.searchsorted(mates, v))
+        nb = mates[np.r_[e[e[:, 0] == lv, 1], e[e[:, 1] == lv, 0]]]
+        assert rowptr[v + 1] - rowptr[v] == nb.size, v
+        earlier = nb[(prio[nb] < prio[v]) | ((prio[nb] == prio[v]) & (nb < v))]
+        taken = set(int(c) for c in col[earlier] if c < P)
+        free = [int(c) for c in L[v] if int(c) not in taken]
+        if free:
+            assert col[v] == free[0], v
+        else:
+            assert col[v] >= P, v
