@@ -78,7 +78,7 @@ struct picasso_ctx {
     int32_t use_graph = 1;   // replay colouring rounds from a captured graph
     int64_t mfma_cap = -1;   // largest bucket for the MFMA kernel (-1: as large as LDS allows)
     Arena arena;
-    DevBuf x, z;
+    DevBuf x, z, xz;  // bit-planes, and the interleaved copy the member gather reads
     // iteration buffers
     DevBuf ids, next_ids, lists, prio, bcnt, bstart, bmem, bslot, pos_of, tmp_mem, tmp_slot, tiles, words, tile_off,
         rb_off, R, D, bx, bz, tile_bucket, nslow, slow, slot_cnt, slot_off, rowptr, adj, col, blk, fre, nblk, st,
@@ -297,8 +297,7 @@ int64_t build_conflict_graph(picasso_ctx *h, const Batch &b, int64_t m, int64_t 
     ra.total_row_tiles = bi.row_tiles;
     ra.rb_off = static_cast<const int64_t *>(h->rb_off.p);
     ra.ids = static_cast<const int32_t *>(h->ids.p);
-    ra.x = static_cast<const uint64_t *>(h->x.p);
-    ra.z = static_cast<const uint64_t *>(h->z.p);
+    ra.xz = static_cast<const uint64_t *>(h->xz.p);
     ra.W = h->W;
     ra.binst = b.binst;
     ra.inst = b.inst;
@@ -386,7 +385,7 @@ int64_t build_conflict_graph(picasso_ctx *h, const Batch &b, int64_t m, int64_t 
 // launched one by one or replayed from a graph captured once per
 // iteration (the rounds' arguments do not change within an iteration).
 struct RoundGraph {
-    hipGraphExec_t exec[2] = {nullptr, nullptr};  // starting from list 0 / list 1
+    hipGraphExec_t exec[2] = {nullptr, nullptr};  // starting from list 0 / list 1, captured on first use
     int32_t rounds = 0;
     ~RoundGraph()
     {
@@ -395,27 +394,25 @@ struct RoundGraph {
     }
 };
 
-void capture_rounds(picasso_ctx *h, const JpArgs &j, RoundGraph &g, int32_t rounds)
+void capture_rounds(picasso_ctx *h, const JpArgs &j, RoundGraph &g, int32_t rounds, int start)
 {
-    for (int start = 0; start < 2; ++start) {
-        hipGraph_t graph = nullptr;
-        PCHECK_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-        int cur = start;
-        try {
-            for (int r = 0; r < rounds; ++r) {
-                launch_jp_round(j, cur, h->stream);
-                cur ^= 1;
-            }
-        } catch (...) {
-            (void)hipStreamEndCapture(h->stream, &graph);
-            if (graph) (void)hipGraphDestroy(graph);
-            throw;
+    hipGraph_t graph = nullptr;
+    PCHECK_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    int cur = start;
+    try {
+        for (int r = 0; r < rounds; ++r) {
+            launch_jp_round(j, cur, h->stream);
+            cur ^= 1;
         }
-        PCHECK_HIP(hipStreamEndCapture(h->stream, &graph));
-        const hipError_t e = hipGraphInstantiate(&g.exec[start], graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        PCHECK_HIP(e);
+    } catch (...) {
+        (void)hipStreamEndCapture(h->stream, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
     }
+    PCHECK_HIP(hipStreamEndCapture(h->stream, &graph));
+    const hipError_t e = hipGraphInstantiate(&g.exec[start], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    PCHECK_HIP(e);
     g.rounds = rounds;
 }
 
@@ -464,7 +461,7 @@ int32_t color_buckets(picasso_ctx *h, const Batch &b, int64_t m, int64_t E, int6
     bool fresh = true;  // the lists hold every bucket
     while (true) {
         if (h->use_graph && batch == max_batch && max_batch > 1) {
-            if (!graph.rounds) capture_rounds(h, j, graph, batch);
+            if (!graph.exec[cur]) capture_rounds(h, j, graph, batch, cur);
             PCHECK_HIP(hipGraphLaunch(graph.exec[cur], st));
             if (batch & 1) cur ^= 1;
         } else {
@@ -782,6 +779,8 @@ picasso_handle create_impl(int64_t n, int32_t q, const uint64_t *x, const uint64
             PCHECK_HIP(hipMemcpyAsync(dx, x, cb, kind, h->stream));
             PCHECK_HIP(hipMemcpyAsync(dz, z, cb, kind, h->stream));
         }
+        uint64_t *dxz = static_cast<uint64_t *>(h->arena.ensure(h->xz, 2 * bytes));
+        launch_interleave(dx, dz, n, W, dxz, h->stream);
         if (device_src && n > 0) {
             int32_t *bad = buf<int32_t>(h, h->scalars, 16);
             launch_fill_i32(bad, 1, 0, h->stream);
@@ -880,7 +879,7 @@ void picasso_destroy(picasso_handle h)
     if (!h) return;
     (void)hipSetDevice(h->device);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
-    DevBuf *all[] = {&h->x,       &h->z,        &h->ids,     &h->next_ids, &h->lists,   &h->prio,     &h->bcnt,
+    DevBuf *all[] = {&h->x,       &h->z,       &h->xz,        &h->ids,     &h->next_ids, &h->lists,   &h->prio,     &h->bcnt,
                      &h->bstart,  &h->bmem,     &h->bslot,   &h->pos_of,   &h->tmp_mem, &h->tmp_slot, &h->tiles,
                      &h->words,   &h->tile_off, &h->rb_off,  &h->R,        &h->D,       &h->nslow,    &h->slow,
                      &h->slot_cnt, &h->slot_off, &h->rowptr, &h->adj,      &h->col,     &h->blk,      &h->fre,

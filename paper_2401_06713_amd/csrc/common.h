@@ -147,7 +147,7 @@ struct RelateArgs {
     int64_t total_row_tiles;
     const int64_t *rb_off;    // [P+1] word offset of each bucket's bit matrix
     const int32_t *ids;       // local -> original id
-    const uint64_t *x, *z;    // all n strings, n x W
+    const uint64_t *xz;       // all n strings, row i = [x words | z words] (n x 2W)
     int32_t W;
     int32_t relation;         // the relation this launch evaluates
     const int32_t *binst;     // instance of each bucket
@@ -157,6 +157,8 @@ struct RelateArgs {
     const int32_t *tile_bucket;  // owner bucket of each row tile (set by launch_relate_prep)
     int64_t mfma_max_members;    // buckets up to this size go to the MFMA kernel (-1: none)
 };
+// Interleaved copy of the strings: row i = [x_i words | z_i words].
+void launch_interleave(const uint64_t *x, const uint64_t *z, int64_t n, int32_t W, uint64_t *xz, hipStream_t st);
 // Gathers member strings into bucket order and the row-tile owners.
 void launch_relate_prep(RelateArgs &a, int64_t entries, uint64_t *bx, uint64_t *bz, int32_t *tile_bucket,
                         hipStream_t st);
@@ -228,7 +230,9 @@ struct JpArgs {
 // Every bucket onto worklist 0 (marked waiting); worklist 1 empty.
 void launch_jp_all(const JpArgs &a, hipStream_t st);
 // One worklist round reading list `cur` and filling list cur ^ 1; then list
-// `cur` is emptied.
+// `cur` is emptied by a separate one-thread kernel (three lists in rotation,
+// with each round emptying the list the next round fills, measured about
+// twice as slow per round on MI355X).
 void launch_jp_round(const JpArgs &a, int cur, hipStream_t st);
 void launch_csr_to_relation(int64_t m, const int64_t *rowptr, const int32_t *adj, const uint32_t *lists,
                             const int64_t *loff, const int64_t *pos_of, const int64_t *bstart, const int64_t *rb_off,

@@ -292,20 +292,37 @@ __global__ void __launch_bounds__(kMfmaThreads) relate_mfma_kernel(RelateArgs a,
 }
 
 // Strings of the bucket members in bucket order (one contiguous row per
-// bucket entry), so the relation kernel's loads are coalesced.
+// bucket entry), so the relation kernel's loads are coalesced.  Each member
+// string is read from the interleaved copy (its W x words then its W z
+// words, 16 W contiguous bytes): one random access per entry.
+template <int W>
 __global__ void gather_members_kernel(const uint32_t *__restrict__ bmem, int64_t entries,
-                                      const int32_t *__restrict__ ids, const uint64_t *__restrict__ x,
-                                      const uint64_t *__restrict__ z, int32_t W, uint64_t *__restrict__ bx,
-                                      uint64_t *__restrict__ bz)
+                                      const int32_t *__restrict__ ids, const uint64_t *__restrict__ xz,
+                                      uint64_t *__restrict__ bx, uint64_t *__restrict__ bz)
 {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < entries;
          e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t g = (int64_t)ids[bmem[e]] * W;
+        const uint64_t *src = xz + (int64_t)ids[bmem[e]] * (2 * W);
+        uint64_t v[2 * W];
+#pragma unroll
+        for (int w = 0; w < 2 * W; ++w) v[w] = src[w];
+#pragma unroll
         for (int w = 0; w < W; ++w) {
-            bx[e * W + w] = x[g + w];
-            bz[e * W + w] = z[g + w];
+            bx[e * W + w] = v[w];
+            bz[e * W + w] = v[W + w];
         }
     }
+}
+
+// x/z bit-planes -> per-string interleaved rows [x words | z words].
+__global__ void interleave_kernel(const uint64_t *__restrict__ x, const uint64_t *__restrict__ z, int64_t n,
+                                  int32_t W, uint64_t *__restrict__ xz)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        for (int w = 0; w < W; ++w) {
+            xz[i * 2 * W + w] = x[i * W + w];
+            xz[i * 2 * W + W + w] = z[i * W + w];
+        }
 }
 
 // Owner bucket of every row tile.
@@ -318,25 +335,40 @@ __global__ void tile_bucket_kernel(const int64_t *__restrict__ tile_off, int64_t
 // ---- pairs sharing a smaller colour -------------------------------------
 // Member p of bucket c has prefix L(v_p)[0..k_p), the colours below c.  Two
 // members share a smaller colour iff some colour occurs in both prefixes.
-// Per window of at most kDupWindow colours (halved while the list below
-// overflows), two LDS bitmaps mark colours seen once and seen again; the (colour, member) entries of colours seen again are
-// listed, sorted by colour, and every two members in a run of one colour get
-// their bit set in D.  Entries are fetched in batches of independent loads
-// (entry e -> member by a search of the prefix-length scan).
+// A pass over the bucket's prefix entries marks each colour in two LDS
+// bitmaps (seen once, seen again); a second pass lists the entries whose
+// bit was seen again, as (colour, member); the list is sorted and every two
+// members in a run of one colour get their bit set in D.
+//  - First attempt: one pass over all entries, bits indexed by a
+//    multiplicative hash of the colour.  Two colours sharing a bit only add
+//    entries to the list (runs are taken on the colour itself).  Each
+//    thread keeps the entries it fetched in registers for the second pass.
+//  - If that list overflows (narrow palettes, where most prefix colours are
+//    shared), exact windows of colours below c, halved until the list fits;
+//    below 64 colours the bucket takes the exact per-pair check.
+// Each member's list start is staged in LDS with the prefix-length scan, so
+// an entry costs one load (entry e -> member by a search of the scan).
 constexpr int kDupThreads = 256;
-constexpr int kDupWindow = 1 << 16;          // colours per pass
-constexpr int kDupWords = kDupWindow / 32;   // bitmap words
-constexpr int kDupMembers = 1024;            // larger buckets take the exact per-pair check
-constexpr int kDupList = 2048;               // listed entries per pass (power of two)
+constexpr int kDupHashBits = 15;                 // hashed bitmap: 2^15 bits
+constexpr int kDupBits = 1 << 15;                // bits per bitmap (window of colours)
+constexpr int kDupWords = kDupBits / 32;
+constexpr int kDupMembers = 1024;                // larger buckets take the exact per-pair check
+constexpr int kDupList = 2048;                   // listed entries (power of two)
+constexpr int kDupHeld = 16;                     // entries a thread keeps between the passes
 constexpr int kDupBatch = 8;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint32_t dup_hash(uint32_t colour)
+{
+    return (colour * 0x9E3779B1u) >> (32 - kDupHashBits);
+}
 
 __global__ void __launch_bounds__(kDupThreads) dup_kernel(DupArgs a)
 {
     __shared__ uint32_t seen[kDupWords], again[kDupWords];
-    __shared__ uint32_t mv[kDupMembers];
+    __shared__ int64_t lbase[kDupMembers];  // first list entry of each member's vertex
     __shared__ int32_t koff[kDupMembers + 1];
-    __shared__ uint64_t list[kDupList];  // colour << 32 | member
+    __shared__ uint64_t list[kDupList];     // colour << 32 | member
     __shared__ int wsum[kDupThreads / 64];
     __shared__ int lcount;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -348,14 +380,14 @@ __global__ void __launch_bounds__(kDupThreads) dup_kernel(DupArgs a)
             if (t == 0) a.slow[atomicAdd(a.n_slow, 1)] = (uint32_t)c;
             continue;
         }
-        // members and the exclusive scan of their prefix lengths
+        // member list starts and the exclusive scan of their prefix lengths
         __syncthreads();
         int chunk_base = 0;
         for (int p0 = 0; p0 < S; p0 += kDupThreads) {
             const int p = p0 + t;
             int k = 0;
             if (p < S) {
-                mv[p] = a.bmem[base + p];
+                lbase[p] = a.loff[a.bmem[base + p]];
                 k = a.bslot[base + p];
             }
             int inc = k;
@@ -376,65 +408,37 @@ __global__ void __launch_bounds__(kDupThreads) dup_kernel(DupArgs a)
             __syncthreads();
         }
         const int total = chunk_base;
-        if (total == 0) continue;
+        if (total < 2) continue;
         const int64_t nw = (S + 63) >> 6;
         uint64_t *Dm = a.D + a.rb_off[c];
-        bool overflow = false;
-        int64_t lo = a.inst[a.binst[c]].pal, win = kDupWindow;  // colours below c of this instance
-        while (lo < c) {
-            const int64_t hi = lo + win < c ? lo + win : c;
-            const int words = (int)((hi - lo + 31) >> 5);
+        auto fetch = [&](int e, uint32_t &col, int &mem) {
+            int l = 0, h = S;  // koff[l] <= e < koff[h]
+            while (h - l > 1) {
+                const int mid = (l + h) >> 1;
+                if (koff[mid] <= e) l = mid;
+                else h = mid;
+            }
+            mem = l;
+            col = a.lists[lbase[l] + (e - koff[l])];
+        };
+        auto mark = [&](uint32_t b) {
+            const uint32_t bit = 1u << (b & 31);
+            if (atomicOr(&seen[b >> 5], bit) & bit) atomicOr(&again[b >> 5], bit);
+        };
+        auto enlist = [&](uint32_t b, uint32_t cc, int mem) {
+            if (again[b >> 5] & (1u << (b & 31))) {
+                const int at = atomicAdd(&lcount, 1);
+                if (at < kDupList) list[at] = ((uint64_t)cc << 32) | (uint32_t)mem;
+            }
+        };
+        auto clear = [&](int words) {
             __syncthreads();
             for (int w = t; w < words; w += kDupThreads) seen[w] = again[w] = 0u;
             if (t == 0) lcount = 0;
             __syncthreads();
-            for (int round = 0; round < 2; ++round) {  // 0: mark, 1: list colours seen again
-                for (int e0 = t; e0 < total; e0 += kDupThreads * kDupBatch) {
-                    uint32_t col[kDupBatch];
-                    int mem[kDupBatch];
-#pragma unroll
-                    for (int j = 0; j < kDupBatch; ++j) {
-                        const int e = e0 + j * kDupThreads;
-                        col[j] = kNone;
-                        mem[j] = 0;
-                        if (e < total) {
-                            int l = 0, h = S;  // koff[l] <= e < koff[h]
-                            while (h - l > 1) {
-                                const int mid = (l + h) >> 1;
-                                if (koff[mid] <= e) l = mid;
-                                else h = mid;
-                            }
-                            mem[j] = l;
-                            col[j] = a.lists[a.loff[mv[l]] + (e - koff[l])];
-                        }
-                    }
-#pragma unroll
-                    for (int j = 0; j < kDupBatch; ++j) {
-                        const uint32_t cc = col[j];
-                        if (cc == kNone || cc < lo || cc >= hi) continue;
-                        const uint32_t b = cc - (uint32_t)lo;
-                        const uint32_t bit = 1u << (b & 31);
-                        if (round == 0) {
-                            if (atomicOr(&seen[b >> 5], bit) & bit) atomicOr(&again[b >> 5], bit);
-                        } else if (again[b >> 5] & bit) {
-                            const int at = atomicAdd(&lcount, 1);
-                            if (at < kDupList) list[at] = ((uint64_t)cc << 32) | (uint32_t)mem[j];
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-            const int n = lcount;
-            if (n > kDupList) {  // too many shared colours for the list: narrower window
-                if (win <= 64) {
-                    overflow = true;  // exact per-pair check
-                    break;
-                }
-                win >>= 1;
-                continue;
-            }
-            lo = hi;
-            if (n < 2) continue;
+        };
+        // sorts the list (n entries) by (colour, member)
+        auto sort_list = [&](int n) {
             int N = 2;
             while (N < n) N <<= 1;
             for (int e = n + t; e < N; e += kDupThreads) list[e] = ~0ull;
@@ -453,7 +457,9 @@ __global__ void __launch_bounds__(kDupThreads) dup_kernel(DupArgs a)
                     }
                     __syncthreads();
                 }
-            // each entry pairs with the later entries of its colour run
+        };
+        // each listed entry pairs with the later entries of its colour run
+        auto pair_runs = [&](int n) {
             for (int e = t; e < n; e += kDupThreads) {
                 const uint32_t ce = (uint32_t)(list[e] >> 32), pe = (uint32_t)list[e];
                 for (int f = e + 1; f < n && (uint32_t)(list[f] >> 32) == ce; ++f) {
@@ -462,6 +468,99 @@ __global__ void __launch_bounds__(kDupThreads) dup_kernel(DupArgs a)
                     atomicOr((unsigned long long *)&Dm[(int64_t)pf * nw + (pe >> 6)], 1ull << (pe & 63));
                 }
             }
+        };
+        // first attempt: hashed bits over all entries (held in registers
+        // between the passes when they fit, fetched twice otherwise)
+        clear(kDupWords);
+        if (total <= kDupThreads * kDupHeld) {
+            uint32_t col[kDupHeld];
+            int mem[kDupHeld];
+#pragma unroll
+            for (int j = 0; j < kDupHeld; ++j) {
+                const int e = t + j * kDupThreads;
+                col[j] = kNone;
+                mem[j] = 0;
+                if (e < total) fetch(e, col[j], mem[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < kDupHeld; ++j)
+                if (col[j] != kNone) mark(dup_hash(col[j]));
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < kDupHeld; ++j)
+                if (col[j] != kNone) enlist(dup_hash(col[j]), col[j], mem[j]);
+        } else {
+            for (int round = 0; round < 2; ++round) {  // 0: mark, 1: list colours seen again
+                for (int e0 = t; e0 < total; e0 += kDupThreads * kDupBatch) {
+                    uint32_t col[kDupBatch];
+                    int mem[kDupBatch];
+#pragma unroll
+                    for (int j = 0; j < kDupBatch; ++j) {
+                        const int e = e0 + j * kDupThreads;
+                        col[j] = kNone;
+                        mem[j] = 0;
+                        if (e < total) fetch(e, col[j], mem[j]);
+                    }
+#pragma unroll
+                    for (int j = 0; j < kDupBatch; ++j) {
+                        if (col[j] == kNone) continue;
+                        if (round == 0) mark(dup_hash(col[j]));
+                        else enlist(dup_hash(col[j]), col[j], mem[j]);
+                    }
+                }
+                if (round == 0) __syncthreads();
+            }
+        }
+        __syncthreads();
+        const int n0 = lcount;
+        if (n0 <= kDupList) {
+            if (n0 >= 2) {
+                sort_list(n0);
+                pair_runs(n0);
+            }
+            continue;
+        }
+        // exact windows of colours below c
+        bool overflow = false;
+        int64_t lo = a.inst[a.binst[c]].pal, win = kDupBits;  // colours below c of this instance
+        while (lo < c) {
+            const int64_t hi = lo + win < c ? lo + win : c;
+            clear((int)((hi - lo + 31) >> 5));
+            for (int round = 0; round < 2; ++round) {  // 0: mark, 1: list colours seen again
+                for (int e0 = t; e0 < total; e0 += kDupThreads * kDupBatch) {
+                    uint32_t col[kDupBatch];
+                    int mem[kDupBatch];
+#pragma unroll
+                    for (int j = 0; j < kDupBatch; ++j) {
+                        const int e = e0 + j * kDupThreads;
+                        col[j] = kNone;
+                        mem[j] = 0;
+                        if (e < total) fetch(e, col[j], mem[j]);
+                    }
+#pragma unroll
+                    for (int j = 0; j < kDupBatch; ++j) {
+                        const uint32_t cc = col[j];
+                        if (cc == kNone || cc < lo || cc >= hi) continue;
+                        if (round == 0) mark(cc - (uint32_t)lo);
+                        else enlist(cc - (uint32_t)lo, cc, mem[j]);
+                    }
+                }
+                __syncthreads();
+            }
+            const int n = lcount;
+            if (n > kDupList) {  // narrower window
+                if (win <= 64) {
+                    overflow = true;
+                    break;
+                }
+                win >>= 1;
+                continue;
+            }
+            if (n >= 2) {
+                sort_list(n);
+                pair_runs(n);
+            }
+            lo = hi;
         }
         if (overflow && t == 0) a.slow[atomicAdd(a.n_slow, 1)] = (uint32_t)c;
     }
@@ -601,8 +700,14 @@ void launch_relate_prep(RelateArgs &a, int64_t entries, uint64_t *bx, uint64_t *
                         hipStream_t st)
 {
     if (entries > 0) {
-        gather_members_kernel<<<grid_cap((entries + 255) / 256, 65535 * 16), 256, 0, st>>>(a.bmem, entries, a.ids,
-                                                                                        a.x, a.z, a.W, bx, bz);
+        const unsigned grid = grid_cap((entries + 255) / 256, 65535 * 16);
+        switch (a.W) {
+            case 1: gather_members_kernel<1><<<grid, 256, 0, st>>>(a.bmem, entries, a.ids, a.xz, bx, bz); break;
+            case 2: gather_members_kernel<2><<<grid, 256, 0, st>>>(a.bmem, entries, a.ids, a.xz, bx, bz); break;
+            case 3: gather_members_kernel<3><<<grid, 256, 0, st>>>(a.bmem, entries, a.ids, a.xz, bx, bz); break;
+            case 4: gather_members_kernel<4><<<grid, 256, 0, st>>>(a.bmem, entries, a.ids, a.xz, bx, bz); break;
+            default: throw Error(PICASSO_EINTERNAL, "gather: unsupported word count");
+        }
         PCHECK_LAUNCH();
     }
     if (a.P > 0) {
@@ -699,6 +804,13 @@ void launch_rowptr(const int64_t *slot_off, int64_t m, const int64_t *loff, int6
 {
     const int64_t b = (m + 1 + 255) / 256;
     rowptr_kernel<<<grid_cap(b, 65535 * 16), 256, 0, st>>>(slot_off, m, loff, rowptr);
+    PCHECK_LAUNCH();
+}
+
+void launch_interleave(const uint64_t *x, const uint64_t *z, int64_t n, int32_t W, uint64_t *xz, hipStream_t st)
+{
+    if (n <= 0) return;
+    interleave_kernel<<<grid_cap((n + 255) / 256, 65535 * 16), 256, 0, st>>>(x, z, n, W, xz);
     PCHECK_LAUNCH();
 }
 
