@@ -32,12 +32,12 @@ HBM_PEAK_GBS = 8000.0
 PAIR_TRAFFIC = {
     "workload": "C2 n=200000 q=48 pI=0.7",
     "path": "valu",
-    "source": "paper_2401_06713_amd/csrc/pairs.hip",
-    "sha256": "76b28afa240598b7db75568f480d1cfca51dc7659179240d03ee0c745fbb8448",
-    "fetch_kib": 56652.6875,
-    "fetch_scale": 1048576.0 / 524308.375,
-    "write_kib": 195842.09375,
-    "write_scale": 1.0,
+    "source": "paper_2401_06713_amd/csrc/relate.hip",
+    "sha256": "4b815f05c8c93ace88f28f30c59caa1a59e28ccf52c3ae237e00bc279199e50e",
+    "fetch_kib": 57593.875,
+    "fetch_scale": 1048576.0 / 524308.125,
+    "write_kib": 199404.1875,
+    "write_scale": 1048576.0 / 1048576.0,
 }
 
 

@@ -138,7 +138,7 @@ void launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t st);
 void launch_bucket_shapes(const int64_t *bstart, int64_t P, int64_t *tiles, int64_t *words, hipStream_t st);
 void exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, bool with_total, void *tmp, hipStream_t st);
 
-// pairs.hip: the intra-bucket pair kernels.
+// relate.hip: the relation bit matrices (popcount and int8 MFMA forms).
 struct RelateArgs {
     const int64_t *bstart;    // [P+1]
     const uint32_t *bmem;     // local vertex of each bucket entry (priority order)
@@ -170,6 +170,7 @@ bool mfma_supported(int32_t q, int32_t relation);
 int64_t mfma_member_cap(int32_t q, int32_t relation);
 void launch_relate_mfma(const RelateArgs &a, int32_t q, hipStream_t st);
 
+// pairs.hip: pairs sharing a smaller colour (dedup) and the CSR.
 struct DupArgs {
     const int64_t *bstart;
     const uint32_t *bmem;
