@@ -70,10 +70,16 @@ enum {
     PICASSO_OPT_GRAPH = 7,      /* 1 (default): a full batch of colouring rounds
                                    is captured once per iteration into a HIP
                                    graph and replayed; 0: plain launches        */
-    PICASSO_OPT_MFMA_CAP = 8    /* MFMA pair path: buckets of at most this many
+    PICASSO_OPT_MFMA_CAP = 8,   /* MFMA pair path: buckets of at most this many
                                    members take the MFMA kernel, larger ones the
                                    popcount tile kernel; -1 (default) = as many
                                    as the kernel's LDS rows hold for this q      */
+    PICASSO_OPT_TAIL = 9        /* 1 (default): an instance with at most 256
+                                   vertices left (and lists within the kernel's
+                                   LDS) finishes its iterations in one device
+                                   workgroup; 0: every iteration takes the full
+                                   path.  Results are identical.  Iterations
+                                   run there report pair_path 0 and no times.  */
 };
 
 #define PICASSO_PATH_AUTO 0
@@ -93,7 +99,8 @@ typedef struct {
     int64_t colored;    /* vertices coloured in this iteration                 */
     int64_t offset;     /* first global colour id of this iteration's palette
                            (single-instance handles; 0 for batches)           */
-    int32_t pair_path;  /* PICASSO_PATH_VALU or PICASSO_PATH_MFMA              */
+    int32_t pair_path;  /* PICASSO_PATH_VALU or PICASSO_PATH_MFMA (0: the tail
+                           kernel, see PICASSO_OPT_TAIL)                        */
     int32_t jp_rounds;  /* colouring rounds                                    */
     double ms_lists, ms_buckets, ms_count, ms_fill, ms_color, ms_compact;
 } picasso_iter_stats;

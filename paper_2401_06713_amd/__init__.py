@@ -20,7 +20,7 @@ REL_ANTICOMMUTE = 0
 REL_QWC = 1
 PATH_AUTO, PATH_VALU, PATH_MFMA = 0, 1, 2
 (OPT_MEM_BUDGET, OPT_PAIR_PATH, OPT_FIXED_T, OPT_STREAM, OPT_TIMING, OPT_JP_BATCH, OPT_GRAPH,
- OPT_MFMA_CAP) = 1, 2, 3, 4, 5, 6, 7, 8
+ OPT_MFMA_CAP, OPT_TAIL) = 1, 2, 3, 4, 5, 6, 7, 8, 9
 MAX_T = 256
 MAX_ITER_STATS = 256
 

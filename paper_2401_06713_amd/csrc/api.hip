@@ -77,12 +77,14 @@ struct picasso_ctx {
     int32_t jp_batch = 32;   // colouring rounds per host check, at most
     int32_t use_graph = 1;   // replay colouring rounds from a captured graph
     int64_t mfma_cap = -1;   // largest bucket for the MFMA kernel (-1: as large as LDS allows)
+    int32_t use_tail = 1;    // finish instances with few vertices left in the tail kernel
     Arena arena;
     DevBuf x, z, xz;  // bit-planes, and the interleaved copy the member gather reads
     // iteration buffers
     DevBuf ids, next_ids, lists, prio, bcnt, bstart, bmem, bslot, pos_of, tmp_mem, tmp_slot, tiles, words, tile_off,
         rb_off, R, D, bx, bz, tile_bucket, nslow, slow, slot_cnt, slot_off, rowptr, adj, col, blk, fre, nblk, st,
-        dirty, wl, flags, pos, used, scan_tmp, scalars, out_colors, inst, vinst, loff, binst, inst_out;
+        dirty, wl, flags, pos, used, scan_tmp, scalars, out_colors, inst, vinst, loff, binst, inst_out, tail_recs,
+        tail_table, tail_outs, tail_iters, tail_ranges;
     std::vector<InstRec> h_inst;  // table of the active instances (kept until the copy has completed)
     picasso_stats stats;
     std::vector<picasso_instance_stats> istats;
@@ -541,6 +543,142 @@ struct RunArgs {
     int32_t max_sched = 0;
 };
 
+// Adds one iteration's record (one instance's share, or the whole batch's)
+// to the call's statistics; iteration `idx` counts from 0.
+void add_iter(picasso_stats &S, std::vector<int64_t> &iter_edges, int64_t idx, const picasso_iter_stats &it)
+{
+    if ((int64_t)iter_edges.size() <= idx) iter_edges.resize((size_t)idx + 1, 0);
+    iter_edges[(size_t)idx] += it.edges;
+    if (idx < PICASSO_MAX_ITER_STATS) {
+        picasso_iter_stats &d = S.iters[idx];
+        d.m += it.m;
+        d.P += it.P;
+        d.T = std::max(d.T, it.T);
+        d.pair_tests += it.pair_tests;
+        d.edges += it.edges;
+        d.colored += it.colored;
+        d.offset = it.offset;
+        d.pair_path = std::max(d.pair_path, it.pair_path);
+        d.jp_rounds += it.jp_rounds;
+        d.ms_lists += it.ms_lists;
+        d.ms_buckets += it.ms_buckets;
+        d.ms_count += it.ms_count;
+        d.ms_fill += it.ms_fill;
+        d.ms_color += it.ms_color;
+        d.ms_compact += it.ms_compact;
+    }
+    S.n_iters = std::max<int32_t>(S.n_iters, (int32_t)(idx + 1));
+    S.palette_total += it.P;
+    S.pair_tests += it.pair_tests;
+    S.edges += it.edges;
+}
+
+// Whether every iteration of an instance with m vertices left fits the tail
+// kernel's LDS; fills the instance's (P, T) table for 0..m vertices.
+bool tail_table(int64_t m, double frac, double alpha, int32_t fixed_T, std::vector<int32_t> &table)
+{
+    const size_t at = table.size();
+    table.resize(at + 2 * ((size_t)kTailMax + 1), 0);
+    for (int64_t k = 1; k <= m; ++k) {
+        int64_t P;
+        int32_t T;
+        params(k, frac, alpha, fixed_T, P, T);
+        if (P > kTailMax || (int64_t)T * k > kTailListCap) {
+            table.resize(at);
+            return false;
+        }
+        table[at + 2 * k] = (int32_t)P;
+        table[at + 2 * k + 1] = T;
+    }
+    return true;
+}
+
+// After an iteration: hands the instances with 0 < m <= kTailMax (and every
+// iteration within the tail kernel's limits) to the tail kernel, which
+// finishes them; the other instances' vertices (contiguous runs of
+// h->next_ids) are gathered to the front of h->ids when some left.  Returns
+// the vertices left for the next iteration.  mi/off/n_colors and the
+// statistics are updated for the finished instances.
+int64_t run_tails(picasso_ctx *h, const RunArgs &ra, const std::vector<int32_t> &act, std::vector<int64_t> &mi,
+                  std::vector<int64_t> &off, uint32_t ell, int64_t *n_colors, int32_t *d_out, picasso_stats &S,
+                  std::vector<int64_t> &iter_edges, bool &gathered)
+{
+    hipStream_t st = h->stream;
+    std::vector<TailRec> trs;
+    std::vector<int32_t> tinst, table;
+    std::vector<int64_t> ranges;
+    int64_t src = 0, kept = 0;
+    for (const int32_t i : act) {
+        const int64_t mn = mi[i];
+        if (mn > 0 && mn <= kTailMax && tail_table(mn, ra.fracs[i], ra.alphas[i], h->fixed_T, table)) {
+            TailRec tr{};
+            tr.src = src;
+            tr.m = mn;
+            tr.sbase = h->inst_base[i];
+            tr.cbase = off[i];
+            tr.seed = ra.seeds[i];
+            tr.ell = (int32_t)ell + 1;
+            tr.rel = ra.rels[i];
+            tr.table = (int32_t)(table.size() - 2 * ((size_t)kTailMax + 1));
+            tr.iter0 = (int32_t)(trs.size() * kTailMax);
+            trs.push_back(tr);
+            tinst.push_back(i);
+        } else if (mn > 0) {
+            ranges.push_back(src);
+            ranges.push_back(kept);
+            kept += mn;
+        }
+        src += mn;
+    }
+    gathered = false;
+    if (trs.empty()) return kept;
+    const int32_t nt = (int32_t)trs.size();
+    TailRec *d_recs = buf<TailRec>(h, h->tail_recs, trs.size());
+    int32_t *d_table = buf<int32_t>(h, h->tail_table, table.size());
+    TailOut *d_outs = buf<TailOut>(h, h->tail_outs, trs.size());
+    TailIter *d_iters = buf<TailIter>(h, h->tail_iters, trs.size() * kTailMax);
+    upload(h, d_recs, trs.data(), trs.size() * sizeof(TailRec));
+    upload(h, d_table, table.data(), table.size() * sizeof(int32_t));
+    const int32_t *next = static_cast<const int32_t *>(h->next_ids.p);
+    launch_tail(d_recs, nt, next, static_cast<const uint64_t *>(h->xz.p), h->W, d_table, d_out, d_outs, d_iters, st);
+    if (kept > 0) {
+        int64_t *d_ranges = buf<int64_t>(h, h->tail_ranges, ranges.size());
+        upload(h, d_ranges, ranges.data(), ranges.size() * sizeof(int64_t));
+        int32_t *ids = buf<int32_t>(h, h->ids, (size_t)kept);
+        launch_gather_ranges(next, ids, d_ranges, (int32_t)(ranges.size() / 2), kept, st);
+        gathered = true;
+    }
+    std::vector<TailOut> outs(trs.size());
+    std::vector<TailIter> its(trs.size() * kTailMax);
+    download(h, outs.data(), d_outs, outs.size() * sizeof(TailOut));
+    download(h, its.data(), d_iters, its.size() * sizeof(TailIter));
+    for (int32_t b = 0; b < nt; ++b) {
+        const int32_t i = tinst[b];
+        picasso_instance_stats &is = h->istats[i];
+        n_colors[i] += outs[b].n_colors;
+        for (int32_t j = 0; j < outs[b].n_iters; ++j) {
+            const TailIter &ti = its[(size_t)b * kTailMax + j];
+            picasso_iter_stats it{};
+            it.m = ti.m;
+            it.P = ti.P;
+            it.T = ti.T;
+            it.pair_tests = ti.pair_tests;
+            it.edges = ti.edges;
+            it.colored = ti.colored;
+            it.offset = h->nb == 1 ? ti.offset : 0;
+            it.pair_path = 0;
+            add_iter(S, iter_edges, (int64_t)ell + j, it);
+            off[i] += ti.P;
+            is.n_iters++;
+            is.palette_total += ti.P;
+            is.edges += ti.edges;
+            is.max_edges = std::max<int64_t>(is.max_edges, ti.edges);
+        }
+        mi[i] = 0;
+    }
+    return kept;
+}
+
 // Colours every instance of the handle (Alg. 1 loop, all instances side by
 // side: iteration l advances every instance that still has uncoloured
 // vertices).  Colours land in d_out at each string's packed index;
@@ -562,7 +700,7 @@ int64_t color_all(picasso_ctx *h, const RunArgs &ra, int32_t *d_out, int64_t *n_
         h->istats[i].n = h->inst_n[i];
     }
     std::vector<int32_t> act;
-    std::vector<int64_t> hv;
+    std::vector<int64_t> hv, iter_edges;
     int64_t m = h->n;
     uint32_t ell = 1;
     while (m > 0) {
@@ -668,17 +806,20 @@ int64_t color_all(picasso_ctx *h, const RunArgs &ra, int32_t *d_out, int64_t *n_
         it.ms_buckets = tm.ms(0, 1);
         it.ms_color = tm.ms(2, 3);
         it.ms_compact = tm.ms(3, 4);
-        std::swap(h->ids, h->next_ids);
-        if (S.n_iters < PICASSO_MAX_ITER_STATS) S.iters[S.n_iters] = it;
-        S.n_iters++;
-        S.palette_total += Ptot;
-        S.pair_tests += it.pair_tests;
-        S.edges += it.edges;
-        if (it.edges > S.max_edges) S.max_edges = it.edges;
+        add_iter(S, iter_edges, ell - 1, it);
+        // instances with few vertices left finish in the tail kernel; the
+        // others' vertices move to the front of the next vertex set
+        bool gathered = false;
+        if (!ra.mlp && h->use_tail) {
+            const int64_t kept = run_tails(h, ra, act, mi, off, ell, n_colors, d_out, S, iter_edges, gathered);
+            m_next = kept;
+        }
+        if (!gathered) std::swap(h->ids, h->next_ids);
         m = m_next;
         ++ell;
     }
     PCHECK_HIP(hipStreamSynchronize(st));
+    for (size_t k = 0; k < iter_edges.size(); ++k) S.max_edges = std::max(S.max_edges, iter_edges[k]);
     int64_t total = 0;
     for (int32_t i = 0; i < h->nb; ++i) {
         h->istats[i].n_colors = n_colors[i];
@@ -885,7 +1026,8 @@ void picasso_destroy(picasso_handle h)
                      &h->slot_cnt, &h->slot_off, &h->rowptr, &h->adj,      &h->col,     &h->blk,      &h->fre,
                      &h->nblk,    &h->st,       &h->dirty,   &h->wl,       &h->flags,   &h->pos,      &h->used,
                      &h->scan_tmp, &h->bx,      &h->bz,      &h->tile_bucket,
-                     &h->scalars, &h->out_colors, &h->inst,    &h->vinst,    &h->loff,    &h->binst,    &h->inst_out};
+                     &h->scalars, &h->out_colors, &h->inst,    &h->vinst,    &h->loff,    &h->binst,    &h->inst_out, &h->tail_recs,
+                     &h->tail_table, &h->tail_outs, &h->tail_iters, &h->tail_ranges};
     for (DevBuf *b : all) h->arena.release(*b);
     if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
     delete h;
@@ -921,6 +1063,9 @@ int32_t picasso_set_option(picasso_handle h, int32_t key, int64_t value)
                     break;
                 case PICASSO_OPT_GRAPH:
                     h->use_graph = value != 0;
+                    break;
+                case PICASSO_OPT_TAIL:
+                    h->use_tail = value != 0;
                     break;
                 case PICASSO_OPT_MFMA_CAP:
                     if (value < -1 || value > 4096) throw Error(PICASSO_EINVAL, "MFMA bucket cap must be in [-1, 4096]");

@@ -32,17 +32,12 @@ namespace {
 constexpr int kWave = 64;
 constexpr uint8_t ST_UNKNOWN = 0, ST_TAKEN = 1, ST_NOT = 2;
 
-__device__ __forceinline__ int32_t load_i32(const int32_t *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 __device__ __forceinline__ uint64_t load_u64(const uint64_t *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Bits [0, k) of a multi-word mask: all set / any set.
+// Bits [0, k) of a multi-word mask all set.
 __device__ __forceinline__ bool all_below(const uint64_t *m, int k)
 {
     for (int w = 0; w < (k >> 6); ++w)
@@ -52,15 +47,6 @@ __device__ __forceinline__ bool all_below(const uint64_t *m, int k)
         if ((load_u64(&m[k >> 6]) & need) != need) return false;
     }
     return true;
-}
-
-__device__ __forceinline__ bool any_below(const uint64_t *m, int k)
-{
-    for (int w = 0; w < (k >> 6); ++w)
-        if (load_u64(&m[w])) return true;
-    if (k & 63)
-        if (load_u64(&m[k >> 6]) & ((1ull << (k & 63)) - 1ull)) return true;
-    return false;
 }
 
 // Put bucket c2 on the next round's worklist unless it is already waiting.
@@ -139,10 +125,17 @@ constexpr int kJpStage = 1024;  // members whose (vertex, slot) are staged in LD
 // Resolve what can be resolved in bucket c.  A member depends only on the
 // members before it in the bucket's priority order (a vertex appears in a
 // bucket once), so one sweep in that order reaches the fixpoint: the wave
-// walks the bucket in chunks of 64 members, each lane loading its member's
-// relation row prefix, colour and slot masks once; dependencies inside a
-// chunk settle in registers (ballots), and the chunk's final taken/unknown
-// bits are what later chunks see.
+// walks the bucket in chunks of 64 members, each lane testing its member's
+// relation row prefix against the chunk states (taken / unknown bits in LDS);
+// dependencies inside a chunk settle in registers (ballots), and the chunk's
+// final taken/unknown bits are what later chunks see.
+// A member waiting on an earlier unknown member needs nothing but its row:
+// per-vertex state is read only by members that decide.  What other buckets
+// decide about v reaches this bucket through the status bytes: a slot found
+// free marks v's later slots not-taken there, and v's earlier slots are
+// blocked, so a vertex coloured elsewhere never looks undecided here for long
+// (and any step taken on it meanwhile is harmless: blocking a slot of a
+// coloured vertex, or finding a slot free that it will not take).
 // Cross-bucket effects wake the buckets they may unblock:
 //  - a slot of v found free for the first time: v will not take any later
 //    slot, so v's later slots still unknown are marked not-taken and their
@@ -159,17 +152,23 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t *tak, uint64
     const int64_t nw = (S + 63) >> 6;
     const uint64_t *Rm = a.R + a.rb_off[c];
     const bool staged = S <= kJpStage;
+    // the bucket's taken/unknown words, one ballot per chunk of 64 members
     __syncthreads();
-    for (int64_t w = lane; w < nw; w += kWave) tak[w] = unk[w] = 0ull;
-    __syncthreads();
-    for (int64_t p = lane; p < S; p += kWave) {
-        const uint8_t s = a.st[base + p];
-        if (staged) {
-            mv[p] = a.bmem[base + p];
-            mk[p] = a.bslot[base + p];
+    for (int64_t w = 0; w < nw; ++w) {
+        const int64_t p = w * kWave + lane;
+        uint8_t s = ST_NOT;
+        if (p < S) {
+            s = a.st[base + p];
+            if (staged) {
+                mv[p] = a.bmem[base + p];
+                mk[p] = a.bslot[base + p];
+            }
         }
-        if (s == ST_UNKNOWN) atomicOr((unsigned long long *)&unk[p >> 6], 1ull << (p & 63));
-        else if (s == ST_TAKEN) atomicOr((unsigned long long *)&tak[p >> 6], 1ull << (p & 63));
+        const uint64_t u = __ballot(s == ST_UNKNOWN), tk = __ballot(s == ST_TAKEN);
+        if (lane == 0) {
+            unk[w] = u;
+            tak[w] = tk;
+        }
     }
     __syncthreads();
     const uint64_t below = (1ull << lane) - 1ull;  // lanes before this one
@@ -181,10 +180,6 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t *tak, uint64
         bool open = (unk_ch >> lane) & 1ull;  // still to decide in this sweep
         bool hit_tak_prev = false, hit_unk_prev = false;
         uint64_t own = 0ull;
-        int64_t v = 0, l0 = 0;
-        int k = 0, T = 0;
-        int32_t cv = COL_UNDECIDED;
-        uint64_t fre0 = 0ull;  // v's free-slot mask (one word) as loaded for this chunk
         if (open) {
             // earlier chunks are final for this sweep
             for (int64_t w = 0; w < ch; ++w) {
@@ -193,50 +188,47 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t *tak, uint64
                 hit_unk_prev |= (r & unk[w]) != 0ull;
             }
             own = Rm[p * nw + ch] & below;
-            v = staged ? mv[p] : a.bmem[base + p];
-            k = staged ? mk[p] : a.bslot[base + p];
-            l0 = a.loff[v];
-            T = (int)(a.loff[v + 1] - l0);
-            cv = load_i32(&a.col[v]);
-            if (a.fw == 1) fre0 = load_u64(&a.fre[v]);
         }
         while (true) {
             uint8_t ns = ST_UNKNOWN;
             bool wait = false;  // free here, waiting for v's lower slots: no change in this sweep
             if (open) {
-                uint64_t *blk = a.blk + v * a.fw;
-                uint64_t *fre = a.fre + v * a.fw;
-                const uint64_t kb = 1ull << (k & 63);
-                if (cv != COL_UNDECIDED) {
-                    ns = cv == (int32_t)c ? ST_TAKEN : ST_NOT;
-                } else if (hit_tak_prev || (own & tak_ch)) {
-                    ns = ST_NOT;
-                    const uint64_t old = atomicOr((unsigned long long *)&blk[k >> 6], kb);
-                    if (atomicAdd(&a.nblk[v], 1) == T - 1) {  // the last slot was blocked
-                        __hip_atomic_store(&a.col[v], COL_FAILED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        atomicAdd(a.progress, 1ull);
-                    } else {
-                        int f;
-                        if (a.fw == 1) {
-                            const uint64_t nb = ~(old | kb);
-                            f = nb ? __builtin_ctzll(nb) : 64;
+                const bool blocked = hit_tak_prev || (own & tak_ch);
+                if (blocked || !(hit_unk_prev || (own & unk_ch))) {
+                    const int64_t v = staged ? mv[p] : a.bmem[base + p];
+                    const int k = staged ? mk[p] : a.bslot[base + p];
+                    const int64_t l0 = a.loff[v];
+                    const int T = (int)(a.loff[v + 1] - l0);
+                    uint64_t *blk = a.blk + v * a.fw;
+                    uint64_t *fre = a.fre + v * a.fw;
+                    const uint64_t kb = 1ull << (k & 63);
+                    if (blocked) {
+                        ns = ST_NOT;
+                        const uint64_t old = atomicOr((unsigned long long *)&blk[k >> 6], kb);
+                        if (atomicAdd(&a.nblk[v], 1) == T - 1) {  // the last slot was blocked
+                            __hip_atomic_store(&a.col[v], COL_FAILED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            atomicAdd(a.progress, 1ull);
                         } else {
-                            f = first_open(blk, T);
+                            int f;
+                            if (a.fw == 1) {
+                                const uint64_t nb = ~(old | kb);
+                                f = nb ? __builtin_ctzll(nb) : 64;
+                            } else {
+                                f = first_open(blk, T);
+                            }
+                            if (f > k && f < T) wake(a, a.lists[l0 + f], out, out_count);
                         }
-                        if (f > k && f < T) wake(a, a.lists[l0 + f], out, out_count);
-                    }
-                } else if (a.fw == 1 ? (fre0 & (kb - 1ull)) != 0ull : any_below(fre, k)) {
-                    ns = ST_NOT;  // an earlier slot is free: v takes that colour or an earlier one
-                } else if (!hit_unk_prev && !(own & unk_ch)) {
-                    const uint64_t was = atomicOr((unsigned long long *)&fre[k >> 6], kb);
-                    if (all_below(blk, k)) {
-                        __hip_atomic_store(&a.col[v], (int32_t)c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        atomicAdd(a.progress, 1ull);
-                        ns = ST_TAKEN;
                     } else {
-                        wait = true;
+                        const uint64_t was = atomicOr((unsigned long long *)&fre[k >> 6], kb);
+                        if (all_below(blk, k)) {
+                            __hip_atomic_store(&a.col[v], (int32_t)c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            atomicAdd(a.progress, 1ull);
+                            ns = ST_TAKEN;
+                        } else {
+                            wait = true;
+                        }
+                        if (!(was & kb)) release_later_slots(a, l0, k, T, out, out_count);
                     }
-                    if (!(was & kb)) release_later_slots(a, l0, k, T, out, out_count);
                 }
             }
             const bool decided = ns != ST_UNKNOWN;

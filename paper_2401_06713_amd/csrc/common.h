@@ -250,6 +250,36 @@ void launch_instance_totals(const Batch &b, const int64_t *pos, const int64_t *s
 void launch_compact_ids(int64_t m, const int32_t *ids, const int32_t *flag, const int64_t *pos, int32_t *next_ids,
                         hipStream_t st);
 
+// tail.hip: every remaining iteration of an instance with at most kTailMax
+// uncoloured vertices, one workgroup per instance.
+constexpr int kTailMax = 256;        // vertices
+constexpr int kTailListCap = 16384;  // list entries (m x T) of any iteration
+struct TailRec {
+    int64_t src;    // first vertex id in the ids array
+    int64_t m;      // vertices left
+    int64_t sbase;  // first packed string of the instance
+    int64_t cbase;  // instance-local id of the next palette's first colour
+    uint64_t seed;
+    int32_t ell;    // number of the next iteration
+    int32_t rel;
+    int32_t table;  // (P, T) of m vertices at table[table + 2m], table[table + 2m + 1]
+    int32_t iter0;  // first slot for the instance's iteration records
+};
+struct TailOut {
+    int64_t n_colors;  // distinct colours used by the tail iterations
+    int32_t n_iters;
+    int32_t reserved;
+};
+struct TailIter {
+    int64_t m, P, T, pair_tests, edges, colored, offset;
+};
+void launch_tail(const TailRec *recs, int32_t n, const int32_t *ids, const uint64_t *xz, int32_t W,
+                 const int32_t *table, int32_t *out_colors, TailOut *outs, TailIter *iters, hipStream_t st);
+// dst[j] for j < total from src ranges: ranges holds nr (src start, dst start)
+// pairs, ascending dst starts.
+void launch_gather_ranges(const int32_t *src, int32_t *dst, const int64_t *ranges, int32_t nr, int64_t total,
+                          hipStream_t st);
+
 // learned.hip: features of the current vertex set and the predictor network.
 constexpr int kMlpIn = 5, kMlpHidden = 64, kMlpOut = 2;
 constexpr int kMlpParams = kMlpHidden * kMlpIn + kMlpHidden + kMlpHidden * kMlpHidden + kMlpHidden +

@@ -164,3 +164,20 @@ def test_batch_c3_full_size_golden():
         assert nc[i] == g["n_colors"], i
         assert hashlib.sha256(np.ascontiguousarray(cols[i], dtype="<i4").tobytes()).hexdigest() == \
             g["colors_sha256"], i
+
+
+def test_tail_kernel_matches_full_path(mixed):
+    """Instances finished by the tail kernel (at most 256 vertices left) give
+    the same colours and per-iteration sizes as the full path."""
+    insts, refs = mixed
+    nc_on, cols_on, st_on, ist_on = color_batch(insts, pk.PATH_AUTO, ((pk.OPT_TAIL, 1),))
+    nc_off, cols_off, st_off, ist_off = color_batch(insts, pk.PATH_AUTO, ((pk.OPT_TAIL, 0),))
+    assert np.array_equal(nc_on, nc_off)
+    for a, b in zip(cols_on, cols_off):
+        assert np.array_equal(a, b)
+    assert ist_on == ist_off
+    assert st_on["n_iters"] == st_off["n_iters"]
+    for a, b in zip(st_on["iters"], st_off["iters"]):
+        for k in ("m", "P", "T", "pair_tests", "edges", "colored"):
+            assert a[k] == b[k], (k, a[k], b[k])
+    assert any(it["pair_path"] == 0 for it in st_on["iters"])

@@ -92,7 +92,9 @@ def test_c2_matches_oracle(seed, path):
         for k in ("m", "P", "T", "pair_tests", "edges", "colored", "offset"):
             assert a[k] == b[k], (k, a[k], b[k])
         if path != pk.PATH_AUTO:
-            assert a["pair_path"] == path
+            assert a["pair_path"] in (path, 0)  # 0: finished in the tail kernel
+    if path != pk.PATH_AUTO:
+        assert st["iters"][0]["pair_path"] == path
     check_valid(x, z, col, cfg.relation)
 
 
