@@ -24,10 +24,13 @@ constexpr int kWave = 64;
 // ---- pairs sharing a smaller colour -------------------------------------
 // Member p of bucket c has prefix L(v_p)[0..k_p), the colours below c.  Two
 // members share a smaller colour iff some colour occurs in both prefixes.
-// A pass over the bucket's prefix entries marks each colour in two LDS
+// When the instance's colours below c span at most kDupSpan, each member's
+// prefix becomes a bitset over that span and D's rows are written whole from
+// pairwise intersections.  Otherwise, a pass over the bucket's prefix entries marks each colour in two LDS
 // bitmaps (seen once, seen again); a second pass lists the entries whose
-// bit was seen again, as (colour, member); the list is sorted and every two
-// members in a run of one colour get their bit set in D.
+// bit was seen again, as (colour, member); every two members listed with one
+// colour get their bit set in D (lists of up to kDupScan entries by comparing
+// each entry with the later ones, longer ones by sorting and pairing runs).
 //  - First attempt: one pass over all entries, bits indexed by a
 //    multiplicative hash of the colour.  Two colours sharing a bit only add
 //    entries to the list (runs are taken on the colour itself).  Each
@@ -44,6 +47,8 @@ constexpr int kDupWords = kDupBits / 32;
 constexpr int kDupMembers = 1024;                // larger buckets take the exact per-pair check
 constexpr int kDupList = 2048;                   // listed entries (power of two)
 constexpr int kDupHeld = 16;                     // entries a thread keeps between the passes
+constexpr int kDupScan = 512;                    // lists up to this long are paired without sorting
+constexpr int kDupSpan = 512;                    // colour ranges up to this wide use member bitsets
 constexpr int kDupBatch = 8;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
@@ -98,8 +103,13 @@ __global__ void __launch_bounds__(kDupThreads) dup_kernel(DupArgs a)
         }
         const int total = chunk_base;
         if (total < 2) continue;
+        if (t == 0) koff[S] = total;
         const int64_t nw = (S + 63) >> 6;
         uint64_t *Dm = a.D + a.rb_off[c];
+        auto set_pair = [&](uint32_t pe, uint32_t pf) {
+            atomicOr((unsigned long long *)&Dm[(int64_t)pe * nw + (pf >> 6)], 1ull << (pf & 63));
+            atomicOr((unsigned long long *)&Dm[(int64_t)pf * nw + (pe >> 6)], 1ull << (pe & 63));
+        };
         auto fetch = [&](int e, uint32_t &col, int &mem) {
             int l = 0, h = S;  // koff[l] <= e < koff[h]
             while (h - l > 1) {
@@ -147,17 +157,60 @@ __global__ void __launch_bounds__(kDupThreads) dup_kernel(DupArgs a)
                     __syncthreads();
                 }
         };
-        // each listed entry pairs with the later entries of its colour run
-        auto pair_runs = [&](int n) {
+        // short lists: every two listed entries of one colour, found by
+        // comparing each entry with the later ones (no sort, no barrier)
+        auto pair_scan = [&](int n) {
             for (int e = t; e < n; e += kDupThreads) {
                 const uint32_t ce = (uint32_t)(list[e] >> 32), pe = (uint32_t)list[e];
-                for (int f = e + 1; f < n && (uint32_t)(list[f] >> 32) == ce; ++f) {
-                    const uint32_t pf = (uint32_t)list[f];
-                    atomicOr((unsigned long long *)&Dm[(int64_t)pe * nw + (pf >> 6)], 1ull << (pf & 63));
-                    atomicOr((unsigned long long *)&Dm[(int64_t)pf * nw + (pe >> 6)], 1ull << (pe & 63));
+                for (int f = e + 1; f < n; ++f) {
+                    const uint64_t lf = list[f];
+                    if ((uint32_t)(lf >> 32) == ce) set_pair(pe, (uint32_t)lf);
                 }
             }
         };
+        // each listed entry of a sorted list pairs with the later entries of its colour run
+        auto pair_runs = [&](int n) {
+            for (int e = t; e < n; e += kDupThreads) {
+                const uint32_t ce = (uint32_t)(list[e] >> 32), pe = (uint32_t)list[e];
+                for (int f = e + 1; f < n && (uint32_t)(list[f] >> 32) == ce; ++f) set_pair(pe, (uint32_t)list[f]);
+            }
+        };
+        // narrow colour range below c: each member's prefix as a bitset over
+        // it, and D's rows written whole as "bitsets intersect" (pairs sharing
+        // a colour are then common, too many to list one by one)
+        const int64_t pal = a.inst[a.binst[c]].pal;
+        const int sw = (int)((c - pal + 63) >> 6);  // bitset words per member
+        if (c - pal <= kDupSpan && (int64_t)S * sw <= kDupList) {
+            uint64_t *bits = list;  // S x sw words
+            __syncthreads();
+            for (int p = t; p < S; p += kDupThreads) {
+                uint64_t b[kDupSpan / 64];
+#pragma unroll
+                for (int w = 0; w < kDupSpan / 64; ++w) b[w] = 0ull;
+                const int k = koff[p + 1] - koff[p];
+                for (int i = 0; i < k; ++i) {
+                    const uint32_t cc = a.lists[lbase[p] + i] - (uint32_t)pal;
+#pragma unroll
+                    for (int w = 0; w < kDupSpan / 64; ++w)
+                        if ((int)(cc >> 6) == w) b[w] |= 1ull << (cc & 63);
+                }
+                for (int w = 0; w < sw; ++w) bits[p * sw + w] = b[w];
+            }
+            __syncthreads();
+            for (int64_t x = t; x < (int64_t)S * nw; x += kDupThreads) {
+                const int p = (int)(x / nw), w = (int)(x - (int64_t)p * nw);
+                uint64_t row = 0ull;
+                for (int b = 0; b < 64; ++b) {
+                    const int q = w * 64 + b;
+                    if (q >= S || q == p) continue;
+                    uint64_t any = 0ull;
+                    for (int u = 0; u < sw; ++u) any |= bits[p * sw + u] & bits[q * sw + u];
+                    if (any) row |= 1ull << b;
+                }
+                Dm[x] = row;
+            }
+            continue;
+        }
         // first attempt: hashed bits over all entries (held in registers
         // between the passes when they fit, fetched twice otherwise)
         clear(kDupWords);
@@ -203,15 +256,17 @@ __global__ void __launch_bounds__(kDupThreads) dup_kernel(DupArgs a)
         __syncthreads();
         const int n0 = lcount;
         if (n0 <= kDupList) {
-            if (n0 >= 2) {
+            if (n0 > kDupScan) {
                 sort_list(n0);
                 pair_runs(n0);
+            } else if (n0 >= 2) {
+                pair_scan(n0);
             }
             continue;
         }
         // exact windows of colours below c
         bool overflow = false;
-        int64_t lo = a.inst[a.binst[c]].pal, win = kDupBits;  // colours below c of this instance
+        int64_t lo = pal, win = kDupBits;  // colours below c of this instance
         while (lo < c) {
             const int64_t hi = lo + win < c ? lo + win : c;
             clear((int)((hi - lo + 31) >> 5));
@@ -245,9 +300,11 @@ __global__ void __launch_bounds__(kDupThreads) dup_kernel(DupArgs a)
                 win >>= 1;
                 continue;
             }
-            if (n >= 2) {
+            if (n > kDupScan) {
                 sort_list(n);
                 pair_runs(n);
+            } else if (n >= 2) {
+                pair_scan(n);
             }
             lo = hi;
         }
