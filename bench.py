@@ -121,7 +121,7 @@ def main():
     import torch
 
     import paper_2401_06713_amd as pk
-    from paper_2401_06713_amd import tune
+    from paper_2401_06713_amd import learn, tune
     from paper_2401_06713_amd import workloads as wl
 
     torch.cuda.set_device(0)
@@ -249,6 +249,34 @@ def main():
         "roofline": roof,
     }
     h.close()
+    if not batch and os.path.exists(learn.PREDICTOR):
+        # learned parameters (the stored network) against the fixed ones, each
+        # on a fresh handle so that peak device bytes count only its own run
+        log("bench: learned vs fixed parameters")
+        mlp = pk.Mlp(np.load(learn.PREDICTOR))
+        cmp = {}
+        for name in ("fixed", "learned"):
+            hh = pk.Picasso(xd, zd, cfg.q)
+            hh.set_option(pk.OPT_PAIR_PATH, pk.PATH_VALU)
+            hh.set_option(pk.OPT_TAIL, 0)  # the learned run consults the network every iteration
+            run = (lambda: hh.color(args.seed, cfg.frac, cfg.alpha, cfg.relation)[0]) if name == "fixed" else \
+                (lambda: hh.color_learned(mlp, args.seed, cfg.relation)[0])
+            run()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(3):
+                ncl = run()
+            ms_l = (time.perf_counter() - t1) * 1e3 / 3
+            sl = hh.stats()
+            cmp[name] = {"n_colors": ncl, "ms": ms_l, "max_edges": sl["max_edges"],
+                         "peak_device_bytes": sl["peak_device_bytes"], "iterations": sl["n_iters"]}
+            if name == "learned":
+                cmp[name]["first_iteration_params"] = [sl["iters"][0]["P"], sl["iters"][0]["T"]]
+            hh.close()
+        mlp.close()
+        cmp["note"] = "host-output calls, tail kernel off for both (the learned run consults the network " \
+                      "every iteration); network trained on sweeps over 200 instances, n in [1e3, 3e4]"
+        line["learned_vs_fixed"] = cmp
     if args.copy_calibration > 0:
         src = torch.ones(args.copy_calibration << 20, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)

@@ -32,8 +32,12 @@ import paper_2401_06713_amd as pk
 from paper_2401_06713_amd import workloads as wl
 
 FIXED = (0.125, 2.0)
+# Network parameters trained by `python -m paper_2401_06713_amd.learn --train 200 --n-hi 30000`
+# (sweeps over 200 instances, n log-uniform in [1e3, 3e4], q in 16..96).
+PREDICTOR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "predictor.npy")
 GRID_F = (0.02, 0.04, 0.06, 0.08, 0.10, 0.125, 0.15, 0.20, 0.25)
 GRID_A = (1.0, 1.5, 2.0, 2.5, 3.0, 3.5, 4.0)
+GROUP_STRINGS = 2_000_000  # strings per batched sweep call
 
 
 @dataclass
@@ -87,24 +91,76 @@ def training_instances(count: int, seed: int = 10**6, n_lo: int = 1000, n_hi: in
     return out
 
 
+def iteration_sets(col: np.ndarray, frac: float):
+    """Per-iteration vertex sets of a finished fixed-parameter colouring,
+    rebuilt from its colours: iteration l uses the colour ids
+    [offset_l, offset_l + P_l) with P_l = max(1, ceil(frac m_l)), so its
+    vertex set is the vertices whose colour is at least offset_l."""
+    sets = []
+    off, m = 0, col.shape[0]
+    while m > 0:
+        ids = np.nonzero(col >= off)[0].astype(np.int32)
+        assert ids.size == m
+        sets.append(ids)
+        off += max(1, math.ceil(frac * m))
+        m = int((col >= off).sum())
+    return sets
+
+
 def sweep(cfgs, beta: float = 0.5, grid_f=GRID_F, grid_a=GRID_A, log=print):
-    """Returns (features rows, targets rows, per-instance records)."""
+    """Returns (features rows, targets rows, per-instance records).
+
+    All training instances sit in one batch handle: the fixed run and every
+    grid point are one batched colouring each; per-instance colour counts
+    and largest |E_c| come from the instance statistics."""
+    insts = [wl.make(c) for c in cfgs]
+    fixed, runs, cols = [None] * len(cfgs), [[] for _ in cfgs], [None] * len(cfgs)
+    # groups of at most GROUP_STRINGS strings: at the grid's small palettes and
+    # long lists the bucket matrices take about m T^2 / (8 f) bytes
+    groups, cur, size = [], [], 0
+    for i, c in enumerate(cfgs):
+        if cur and size + c.n > GROUP_STRINGS:
+            groups.append(cur)
+            cur, size = [], 0
+        cur.append(i)
+        size += c.n
+    if cur:
+        groups.append(cur)
+    for gi, idx in enumerate(groups):
+        seeds = [cfgs[i].seed for i in idx]
+        rels = [cfgs[i].relation for i in idx]
+        with pk.PicassoBatch([(insts[i][0], insts[i][1], cfgs[i].q) for i in idx]) as hb:
+            t = time.perf_counter()
+            nc_fixed, gcols = hb.color_batch(seeds, FIXED[0], FIXED[1], rels)
+            ms_fixed = (time.perf_counter() - t) * 1e3
+            ist = hb.instance_stats()
+            for k, i in enumerate(idx):
+                fixed[i] = Run(*FIXED, int(nc_fixed[k]), ist[k]["max_edges"], ms_fixed, 0)
+                cols[i] = gcols[k]
+            for f in grid_f:
+                for a in grid_a:
+                    t = time.perf_counter()
+                    nc, _ = hb.color_batch(seeds, f, a, rels)
+                    ms = (time.perf_counter() - t) * 1e3
+                    ist = hb.instance_stats()
+                    for k, i in enumerate(idx):
+                        runs[i].append(Run(f, a, int(nc[k]), ist[k]["max_edges"], ms, 0))
+        if log:
+            log(f"sweep: group {gi + 1}/{len(groups)} ({len(idx)} instances) done")
     X, Y, recs = [], [], []
     for i, cfg in enumerate(cfgs):
-        x, z = wl.make(cfg)
+        x, z = insts[i]
         with pk.Picasso(x, z, cfg.q) as h:
-            nc, col = h.color(cfg.seed, *FIXED, cfg.relation)
-            st = h.stats()
-            fixed = Run(*FIXED, nc, st["max_edges"], st["ms_total"], st["peak_device_bytes"])
-            feats = iteration_features(h, col, st, cfg.seed, cfg.relation)
-            runs = [run_once(h, cfg.seed, f, a, cfg.relation) for f in grid_f for a in grid_a]
-        best = label(runs, fixed, beta)
+            feats = np.array([h.features(cfg.seed, k + 1, ids, cfg.relation)
+                              for k, ids in enumerate(iteration_sets(cols[i], FIXED[0]))], dtype=np.float64)
+        best = label(runs[i], fixed[i], beta)
         X.append(feats)
         Y.append(np.repeat(pk.unsquash(best.frac, best.alpha)[None, :], len(feats), axis=0))
-        recs.append({"config": asdict(cfg), "fixed": asdict(fixed), "best": asdict(best)})
-        if log:
-            log(f"sweep {i + 1}/{len(cfgs)} n={cfg.n} q={cfg.q}: fixed C={fixed.colors} E={fixed.max_edges}; "
-                f"best f={best.frac} a={best.alpha} C={best.colors} E={best.max_edges}")
+        recs.append({"config": asdict(cfg), "fixed": asdict(fixed[i]), "best": asdict(best)})
+    if log:
+        gain = np.mean([objective(r, f, beta) for r, f in
+                        ((label(rr, ff, beta), ff) for rr, ff in zip(runs, fixed))])
+        log(f"sweep: {len(cfgs)} instances, mean best J {gain:.3f} (fixed = 1)")
     return np.concatenate(X), np.concatenate(Y), recs
 
 
@@ -124,38 +180,86 @@ def train(X, Y, steps: int = 2000, batch: int = 256, lr: float = 3e-3, seed: int
 
 
 def evaluate(mlp: pk.Mlp, cfgs, beta: float = 0.5):
-    """Per instance: fixed vs learned colours, largest |E_c|, time, peak bytes."""
+    """Per instance: fixed vs learned colours, largest |E_c|, time, peak bytes.
+
+    The learned run consults the network every iteration, so it does not use
+    the tail kernel; the fixed run is timed the same way (`fixed`), and with
+    the tail kernel as well (`fixed_tail_ms`)."""
     out = []
     for cfg in cfgs:
         x, z = wl.make(cfg)
+        # a fresh handle per method, so each peak counts only its own buffers
         with pk.Picasso(x, z, cfg.q) as h:
             h.color(cfg.seed, *FIXED, cfg.relation)  # warm-up
+            tail = run_once(h, cfg.seed, *FIXED, cfg.relation)
+        with pk.Picasso(x, z, cfg.q) as h:
+            h.set_option(pk.OPT_TAIL, 0)
+            h.color(cfg.seed, *FIXED, cfg.relation)
             fixed = run_once(h, cfg.seed, *FIXED, cfg.relation)
+        with pk.Picasso(x, z, cfg.q) as h:
+            h.color_learned(mlp, cfg.seed, cfg.relation)  # warm-up
             t = time.perf_counter()
             nc, _, sched = h.color_learned(mlp, cfg.seed, cfg.relation)
             ms = (time.perf_counter() - t) * 1e3
             st = h.stats()
         learned = Run(float(sched[0, 0]), float(sched[0, 1]), nc, st["max_edges"], ms, st["peak_device_bytes"])
-        out.append({"n": cfg.n, "q": cfg.q, "fixed": asdict(fixed), "learned": asdict(learned),
-                    "J_learned": objective(learned, fixed, beta)})
+        out.append({"n": cfg.n, "q": cfg.q, "fixed": asdict(fixed), "fixed_tail_ms": tail.ms,
+                    "learned": asdict(learned), "J_learned": objective(learned, fixed, beta)})
     return out
+
+
+def heldout_instances(count: int, n: int, q: int, pI: float, seed: int = 7_000_000):
+    """Held-out instances: n strings on q qubits, identity with probability
+    pI and X/Y/Z equal; anticommute relation; instance i uses seed seed + i."""
+    r = (1 - pI) / 3
+    return [wl.Config(f"heldout[{i}]", n, q, (pI, r, r, r), seed + i, FIXED[0], FIXED[1], 0) for i in range(count)]
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--train", type=int, default=60, help="training instances")
+    ap.add_argument("--train", type=int, default=1000, help="training instances")
+    ap.add_argument("--n-lo", type=int, default=1000)
     ap.add_argument("--n-hi", type=int, default=100_000)
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--beta", type=float, default=0.5)
+    ap.add_argument("--heldout", type=int, default=20)
+    ap.add_argument("--heldout-n", type=int, default=500_000)
+    ap.add_argument("--heldout-q", type=int, default=96)
+    ap.add_argument("--heldout-pi", type=float, default=0.75)
     ap.add_argument("--out", default="predictor")
+    ap.add_argument("--params", default=None, help="evaluate these saved network parameters (.npy) only")
     args = ap.parse_args()
-    cfgs = training_instances(args.train, n_hi=args.n_hi)
-    X, Y, recs = sweep(cfgs, args.beta)
-    mlp, loss = train(X, Y, steps=args.steps)
-    np.save(args.out + ".npy", mlp.get_params())
+    say = lambda *a: print(*a, flush=True)  # noqa: E731
+    if args.params:
+        mlp, loss, rows, sweep_s, n_train = pk.Mlp(np.load(args.params)), None, 0, 0.0, 0
+    else:
+        cfgs = training_instances(args.train, n_lo=args.n_lo, n_hi=args.n_hi)
+        t = time.perf_counter()
+        X, Y, recs = sweep(cfgs, args.beta, log=say)
+        sweep_s = time.perf_counter() - t
+        mlp, loss = train(X, Y, steps=args.steps, log=say)
+        rows, n_train = int(X.shape[0]), len(cfgs)
+        np.save(args.out + ".npy", mlp.get_params())
+    held = heldout_instances(args.heldout, args.heldout_n, args.heldout_q, args.heldout_pi)
+    res = evaluate(mlp, held, args.beta)
+    summary = {
+        "beta": args.beta, "train_instances": n_train, "rows": rows, "final_loss": loss,
+        "sweep_seconds": sweep_s,
+        "heldout": {"count": len(held), "n": args.heldout_n, "q": args.heldout_q, "pI": args.heldout_pi,
+                    "mean_J_learned": float(np.mean([r["J_learned"] for r in res])),
+                    "colors_ratio": float(np.mean([r["learned"]["colors"] / r["fixed"]["colors"] for r in res])),
+                    "max_edges_ratio": float(np.mean([r["learned"]["max_edges"] / r["fixed"]["max_edges"]
+                                                      for r in res])),
+                    "ms_ratio": float(np.mean([r["learned"]["ms"] / r["fixed"]["ms"] for r in res])),
+                    "peak_bytes_ratio": float(np.mean([r["learned"]["peak_bytes"] / r["fixed"]["peak_bytes"]
+                                                       for r in res])),
+                    "instances": res},
+    }
     with open(args.out + ".json", "w") as f:
-        json.dump({"beta": args.beta, "rows": int(X.shape[0]), "final_loss": loss, "sweep": recs}, f, indent=1)
-    print("saved", os.path.abspath(args.out + ".npy"))
+        json.dump(summary, f, indent=1)
+    say("held-out:", json.dumps({k: v for k, v in summary["heldout"].items() if k != "instances"}))
+    if not args.params:
+        say("saved", os.path.abspath(args.out + ".npy"))
 
 
 if __name__ == "__main__":
