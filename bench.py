@@ -102,6 +102,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-fixed comparison")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the timed steps, copy MIB MiB device to device once (a plain copy of known size "
                          "that calibrates the HBM byte counters of a profiler run)")
@@ -249,7 +250,7 @@ def main():
         "roofline": roof,
     }
     h.close()
-    if not batch and os.path.exists(learn.PREDICTOR):
+    if not batch and not args.no_learned and os.path.exists(learn.PREDICTOR):
         # learned parameters (the stored network) against the fixed ones, each
         # on a fresh handle so that peak device bytes count only its own run
         log("bench: learned vs fixed parameters")
