@@ -48,7 +48,6 @@ __global__ void __launch_bounds__(kTailThreads) tail_kernel(const TailRec *__res
     __shared__ int32_t col[kTailMax];               // palette colour, -1 uncoloured
     __shared__ int32_t cnt[kTailMax];               // bucket sizes
     __shared__ int32_t flag[kTailMax + 1];
-    __shared__ uint64_t forbid[kTailMax / 64];      // colours held by earlier conflicting vertices
     __shared__ unsigned long long acc[2];           // pair tests, edges
     __shared__ int used_n, m_sh;
     const TailRec r = recs[blockIdx.x];
@@ -149,31 +148,52 @@ __global__ void __launch_bounds__(kTailThreads) tail_kernel(const TailRec *__res
                 }
             }
         __syncthreads();
-        // sequential greedy in that order
-        for (int i = 0; i < m; ++i) {
-            const int v = order[i];
-            for (int w = t; w < (P + 63) / 64; w += kTailThreads) forbid[w] = 0ull;
-            __syncthreads();
-            for (int j = t; j < i; j += kTailThreads) {
-                const int u = order[j];
-                const int cu = col[u];
-                if (cu >= 0 && ((rel[v * rw + (u >> 5)] >> (u & 31)) & 1u))
-                    atomicOr((unsigned long long *)&forbid[cu >> 6], 1ull << (cu & 63));
-            }
-            __syncthreads();
-            if (t == 0) {
-                int take = -1;
-                for (int k = 0; k < T; ++k) {
-                    const int c = lists[v * T + k];
-                    if (!((forbid[c >> 6] >> (c & 63)) & 1ull)) {
-                        take = c;
-                        break;
+        // sequential greedy in that order, run by one wave (no workgroup
+        // barrier per vertex): for each vertex the lanes scan the earlier
+        // vertices, the colours held by conflicting ones are OR-reduced, and
+        // a ballot over the list slots picks the first colour not held
+        if (t < 64) {
+            const int lane = t;
+            for (int i = 0; i < m; ++i) {
+                const int v = order[i];
+                uint64_t f[kTailMax / 64];
+#pragma unroll
+                for (int w = 0; w < kTailMax / 64; ++w) f[w] = 0ull;
+                for (int j = lane; j < i; j += 64) {
+                    const int u = order[j];
+                    const int cu = col[u];
+                    if (cu >= 0 && ((rel[v * rw + (u >> 5)] >> (u & 31)) & 1u)) {
+#pragma unroll
+                        for (int w = 0; w < kTailMax / 64; ++w)
+                            if ((cu >> 6) == w) f[w] |= 1ull << (cu & 63);
                     }
                 }
-                col[v] = take;
+#pragma unroll
+                for (int w = 0; w < kTailMax / 64; ++w)
+                    for (int d = 32; d > 0; d >>= 1) f[w] |= __shfl_xor(f[w], d, 64);
+                int take = -1;
+                for (int k0 = 0; k0 < T && take < 0; k0 += 64) {
+                    const int k = k0 + lane;
+                    bool free_slot = false;
+                    if (k < T) {
+                        const int c = lists[v * T + k];
+                        uint64_t fw = 0ull;
+#pragma unroll
+                        for (int w = 0; w < kTailMax / 64; ++w)
+                            if ((c >> 6) == w) fw = f[w];
+                        free_slot = !((fw >> (c & 63)) & 1ull);
+                    }
+                    const uint64_t ok = __ballot(free_slot);
+                    if (ok) take = lists[v * T + k0 + __builtin_ctzll(ok)];
+                }
+                if (lane == 0) col[v] = take;
+                // the colour is in LDS before any lane reads it for a later vertex
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
-            __syncthreads();  // col[v] seen and forbid read before the next vertex clears it
         }
+        __syncthreads();
         // outputs, used colours, next vertex set (ascending ids kept)
         for (int c = t; c < P; c += kTailThreads) cnt[c] = 0;
         __syncthreads();
