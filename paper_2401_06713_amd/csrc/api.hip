@@ -83,7 +83,7 @@ struct picasso_ctx {
     // iteration buffers
     DevBuf ids, next_ids, lists, prio, bcnt, bstart, bmem, bslot, pos_of, tmp_mem, tmp_slot, tiles, words, tile_off,
         rb_off, R, D, bx, bz, tile_bucket, nslow, slow, slot_cnt, slot_off, rowptr, adj, col, blk, fre, nblk, st,
-        dirty, wl, flags, pos, used, scan_tmp, scalars, out_colors, inst, vinst, loff, binst, inst_out, tail_recs,
+        dirty, wake_at, wl, flags, pos, used, scan_tmp, scalars, out_colors, inst, vinst, loff, binst, inst_out, tail_recs,
         tail_table, tail_outs, tail_iters, tail_ranges;
     std::vector<InstRec> h_inst;  // table of the active instances (kept until the copy has completed)
     picasso_stats stats;
@@ -441,6 +441,7 @@ int32_t color_buckets(picasso_ctx *h, const Batch &b, int64_t m, int64_t E, int6
     j.nblk = buf<int32_t>(h, h->nblk, (size_t)std::max<int64_t>(m, 1));
     j.st = buf<uint8_t>(h, h->st, (size_t)std::max<int64_t>(E, 1));
     j.dirty = buf<uint32_t>(h, h->dirty, (size_t)P);
+    j.wake_at = buf<unsigned long long>(h, h->wake_at, (size_t)P);
     int32_t *wl = buf<int32_t>(h, h->wl, (size_t)2 * P + 2);
     j.wl[0] = wl;
     j.wl[1] = wl + P;
@@ -1027,7 +1028,7 @@ void picasso_destroy(picasso_handle h)
                      &h->nblk,    &h->st,       &h->dirty,   &h->wl,       &h->flags,   &h->pos,      &h->used,
                      &h->scan_tmp, &h->bx,      &h->bz,      &h->tile_bucket,
                      &h->scalars, &h->out_colors, &h->inst,    &h->vinst,    &h->loff,    &h->binst,    &h->inst_out, &h->tail_recs,
-                     &h->tail_table, &h->tail_outs, &h->tail_iters, &h->tail_ranges};
+                     &h->tail_table, &h->tail_outs, &h->tail_iters, &h->tail_ranges, &h->wake_at};
     for (DevBuf *b : all) h->arena.release(*b);
     if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
     delete h;

@@ -49,14 +49,18 @@ __device__ __forceinline__ bool all_below(const uint64_t *m, int k)
     return true;
 }
 
-// Put bucket c2 on the next round's worklist unless it is already waiting.
-// The wave first waits for its own outstanding memory operations, so the
-// state change that causes the wake is complete (state is written with
-// coherent stores and atomics) before the bucket can be taken off a list.
-// No cache flush or invalidate is needed: readers use coherent loads.
-__device__ __forceinline__ void wake(const JpArgs &a, int64_t c2, int32_t *out, int32_t *out_count)
+// Put bucket c2 on the next round's worklist unless it is already waiting,
+// noting the bucket position pos of the member whose state changed (members
+// before it cannot change because of it, so the next sweep of c2 starts at
+// its chunk).  The wave first waits for its own outstanding memory
+// operations, so the state change that causes the wake is complete (state is
+// written with coherent stores and atomics) before the bucket can be taken
+// off a list.  No cache flush or invalidate is needed: readers use coherent
+// loads.
+__device__ __forceinline__ void wake(const JpArgs &a, int64_t c2, int64_t pos, int32_t *out, int32_t *out_count)
 {
-    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_s_waitcnt(0);  // the state change is complete before its position is published
+    atomicMin(&a.wake_at[c2], (unsigned long long)pos);
     if (__hip_atomic_exchange(&a.dirty[c2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
         out[atomicAdd(out_count, 1)] = (int32_t)c2;
 }
@@ -89,7 +93,10 @@ __device__ __forceinline__ void release_later_slots(const JpArgs &a, int64_t l0,
 #pragma unroll
         for (int j = 0; j < G; ++j)
             if (need[j]) __hip_atomic_store(&a.st[pos[j]], ST_NOT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_s_waitcnt(0);  // the marks are complete before their positions are published
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+            if (need[j]) atomicMin(&a.wake_at[cc[j]], (unsigned long long)pos[j]);
         uint32_t old[G];
 #pragma unroll
         for (int j = 0; j < G; ++j)
@@ -121,6 +128,7 @@ __device__ __forceinline__ int first_open(const uint64_t *blk, int T)
 }
 
 constexpr int kJpStage = 1024;  // members whose (vertex, slot) are staged in LDS
+constexpr int kJpResweeps = 4;  // extra sweeps of a bucket woken again during its sweep
 
 // Resolve what can be resolved in bucket c.  A member depends only on the
 // members before it in the bucket's priority order (a vertex appears in a
@@ -143,8 +151,8 @@ constexpr int kJpStage = 1024;  // members whose (vertex, slot) are staged in LD
 //  - a blocked slot that completes v's blocked prefix up to slot f: the
 //    bucket of f is woken (v may now take it).
 // Taking a colour needs no wake of its own: the slot was found free first.
-__device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t *tak, uint64_t *unk, uint32_t *mv,
-                               uint8_t *mk, int32_t *out, int32_t *out_count)
+__device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t from, uint64_t *tak, uint64_t *unk,
+                               uint32_t *mv, uint8_t *mk, int32_t *out, int32_t *out_count)
 {
     const int lane = threadIdx.x;
     const int64_t base = a.bstart[c];
@@ -158,7 +166,9 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t *tak, uint64
         const int64_t p = w * kWave + lane;
         uint8_t s = ST_NOT;
         if (p < S) {
-            s = a.st[base + p];
+            // coherent load: a re-sweep in the same launch must see other
+            // workgroups' marks, which may sit in another XCD's cache otherwise
+            s = __hip_atomic_load(&a.st[base + p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (staged) {
                 mv[p] = a.bmem[base + p];
                 mk[p] = a.bslot[base + p];
@@ -172,7 +182,9 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t *tak, uint64
     }
     __syncthreads();
     const uint64_t below = (1ull << lane) - 1ull;  // lanes before this one
-    for (int64_t ch = 0; ch < nw; ++ch) {
+    // members before the first changed position keep their state this sweep
+    const int64_t ch0 = from <= (uint64_t)base ? 0 : (int64_t)((from - (uint64_t)base) >> 6);
+    for (int64_t ch = ch0; ch < nw; ++ch) {
         uint64_t unk_ch = unk[ch];
         if (unk_ch == 0ull) continue;  // wave-uniform
         uint64_t tak_ch = tak[ch];
@@ -216,7 +228,7 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t *tak, uint64
                             } else {
                                 f = first_open(blk, T);
                             }
-                            if (f > k && f < T) wake(a, a.lists[l0 + f], out, out_count);
+                            if (f > k && f < T) wake(a, a.lists[l0 + f], a.pos_of[l0 + f], out, out_count);
                         }
                     } else {
                         const uint64_t was = atomicOr((unsigned long long *)&fre[k >> 6], kb);
@@ -259,16 +271,28 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(6)))
     uint64_t *unk = sbits + a.nw_max;
     __shared__ uint32_t mv[kJpStage];
     __shared__ uint8_t mk[kJpStage];
-    __shared__ int go;
+    __shared__ unsigned long long from;
     const int32_t n_in = a.wl_count[cur];
     int32_t *out = a.wl[cur ^ 1];
     int32_t *out_count = &a.wl_count[cur ^ 1];
     for (int64_t i = blockIdx.x; i < n_in; i += gridDim.x) {
         const int64_t c = a.wl[cur][i];
-        if (threadIdx.x == 0)
-            go = __hip_atomic_exchange(&a.dirty[c], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+        if (threadIdx.x == 0) {
+            __hip_atomic_exchange(&a.dirty[c], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            from = __hip_atomic_exchange(&a.wake_at[c], ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         __syncthreads();
-        if (go) resolve_bucket(a, c, tak, unk, mv, mk, out, out_count);
+        // a bucket woken again while it was swept is swept again at once (its
+        // pending position consumed: the next round's visit finds nothing)
+        for (int sweep = 0; sweep <= kJpResweeps && from != ~0ull; ++sweep) {
+            resolve_bucket(a, c, from, tak, unk, mv, mk, out, out_count);
+            __syncthreads();
+            if (threadIdx.x == 0)
+                from = __hip_atomic_exchange(&a.wake_at[c], ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+        }
+        if (from != ~0ull && threadIdx.x == 0)  // not swept: keep the position for the next round
+            atomicMin(&a.wake_at[c], from);
         __syncthreads();
     }
 }
@@ -277,11 +301,13 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(6)))
 __global__ void jp_reset_kernel(int32_t *count) { *count = 0; }
 
 // Worklist of every bucket (the first round, and the host's recovery round).
-__global__ void wl_all_kernel(int64_t P, int32_t *wl, uint32_t *dirty, int32_t *wl_count)
+__global__ void wl_all_kernel(int64_t P, int32_t *wl, uint32_t *dirty, unsigned long long *wake_at,
+                              int32_t *wl_count)
 {
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < P; c += (int64_t)gridDim.x * blockDim.x) {
         wl[c] = (int32_t)c;
         dirty[c] = 1u;
+        wake_at[c] = 0ull;  // whole bucket
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         wl_count[0] = (int32_t)P;
@@ -375,7 +401,7 @@ unsigned grid_for(int64_t work, int threads, int64_t cap = 65535 * 16)
 void launch_jp_all(const JpArgs &a, hipStream_t st)
 {
     if (a.P <= 0) return;
-    wl_all_kernel<<<grid_for(a.P, 256), 256, 0, st>>>(a.P, a.wl[0], a.dirty, a.wl_count);
+    wl_all_kernel<<<grid_for(a.P, 256), 256, 0, st>>>(a.P, a.wl[0], a.dirty, a.wake_at, a.wl_count);
     PCHECK_LAUNCH();
 }
 

@@ -223,6 +223,7 @@ struct JpArgs {
     int32_t *nblk;          // blocked-slot count per vertex
     uint8_t *st;            // per bucket entry: unknown / taken / not taken
     uint32_t *dirty;        // per bucket: waiting on a worklist
+    unsigned long long *wake_at;  // per bucket: first bucket position changed since it was last taken
     int32_t *wl[2];         // worklists of buckets (P entries each)
     int32_t *wl_count;      // [2]
     unsigned long long *progress;  // decided vertices
