@@ -49,7 +49,8 @@ enum {
 enum {
     PICASSO_OK = 0,
     PICASSO_EINVAL = -1,   /* bad argument; nothing was changed                */
-    PICASSO_ENOMEM = -2,   /* the conflict graph does not fit the memory budget */
+    PICASSO_ENOMEM = -2,   /* a device allocation failed, or the CSR asked of
+                              picasso_conflict_graph exceeds the memory budget */
     PICASSO_EDEVICE = -3,  /* a HIP call failed; the message names it           */
     PICASSO_EINTERNAL = -4 /* internal invariant violated                        */
 };
@@ -57,7 +58,11 @@ enum {
 /* Options for picasso_set_option. */
 enum {
     PICASSO_OPT_MEM_BUDGET = 1, /* max device bytes for one iteration's conflict
-                                   graph (CSR); 0 = no limit beyond the device  */
+                                   graph (CSR); 0 = no limit beyond the device.
+                                   picasso_conflict_graph fails with ENOMEM above
+                                   it; the colouring calls count the edges and
+                                   skip writing the CSR (they colour from the
+                                   per-bucket relation matrices)                */
     PICASSO_OPT_PAIR_PATH = 2,  /* 0 auto, 1 popcount VALU, 2 int8 MFMA          */
     PICASSO_OPT_FIXED_T = 3,    /* >0: list size T fixed (clamped to P) instead of
                                    ceil(alpha ln m); 0 restores the formula      */
