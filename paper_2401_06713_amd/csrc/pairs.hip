@@ -47,7 +47,7 @@ constexpr int kDupWords = kDupBits / 32;
 constexpr int kDupMembers = 1024;                // larger buckets take the exact per-pair check
 constexpr int kDupList = 2048;                   // listed entries (power of two)
 constexpr int kDupHeld = 16;                     // entries a thread keeps between the passes
-constexpr int kDupScan = 512;                    // lists up to this long are paired without sorting
+constexpr int kDupScan = 512;                    // lists up to this long are paired by hash groups (fit the seen bitmap)
 constexpr int kDupSpan = 512;                    // colour ranges up to this wide use member bitsets
 constexpr int kDupBatch = 8;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
@@ -157,16 +157,52 @@ __global__ void __launch_bounds__(kDupThreads) dup_kernel(DupArgs a)
                     __syncthreads();
                 }
         };
-        // short lists: every two listed entries of one colour, found by
-        // comparing each entry with the later ones (no sort, no barrier)
+        // lists of up to kDupScan entries: a counting sort by an 8-bit hash of
+        // the colour into the (then free) bitmap space, and every two entries
+        // of one colour paired inside their hash group by one thread
         auto pair_scan = [&](int n) {
-            for (int e = t; e < n; e += kDupThreads) {
-                const uint32_t ce = (uint32_t)(list[e] >> 32), pe = (uint32_t)list[e];
-                for (int f = e + 1; f < n; ++f) {
-                    const uint64_t lf = list[f];
-                    if ((uint32_t)(lf >> 32) == ce) set_pair(pe, (uint32_t)lf);
+            uint32_t *hcnt = again;                                        // 256 counts
+            uint32_t *hoff = again + 256;                                  // 257 offsets
+            uint64_t *grp = reinterpret_cast<uint64_t *>(seen);            // n entries by group
+            __syncthreads();
+            for (int g = t; g < 256; g += kDupThreads) hcnt[g] = 0u;
+            __syncthreads();
+            for (int e = t; e < n; e += kDupThreads) atomicAdd(&hcnt[dup_hash((uint32_t)(list[e] >> 32)) & 255u], 1u);
+            __syncthreads();
+            if (t < 64) {  // exclusive scan of the 256 counts, one wave, 4 per lane
+                uint32_t v[4], sum = 0u;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    v[k] = hcnt[t * 4 + k];
+                    sum += v[k];
                 }
+                uint32_t inc = sum;
+                for (int d = 1; d < 64; d <<= 1) {
+                    const uint32_t o = __shfl_up(inc, d, 64);
+                    if (t >= d) inc += o;
+                }
+                uint32_t run = inc - sum;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    hoff[t * 4 + k] = run;
+                    run += v[k];
+                }
+                if (t == 63) hoff[256] = inc;
             }
+            __syncthreads();
+            for (int g = t; g < 256; g += kDupThreads) hcnt[g] = hoff[g];  // fill cursors
+            __syncthreads();
+            for (int e = t; e < n; e += kDupThreads) {
+                const uint64_t le = list[e];
+                grp[atomicAdd(&hcnt[dup_hash((uint32_t)(le >> 32)) & 255u], 1u)] = le;
+            }
+            __syncthreads();
+            for (int g = t; g < 256; g += kDupThreads)
+                for (uint32_t e = hoff[g]; e < hoff[g + 1]; ++e) {
+                    const uint32_t ce = (uint32_t)(grp[e] >> 32), pe = (uint32_t)grp[e];
+                    for (uint32_t f = e + 1; f < hoff[g + 1]; ++f)
+                        if ((uint32_t)(grp[f] >> 32) == ce) set_pair(pe, (uint32_t)grp[f]);
+                }
         };
         // each listed entry of a sorted list pairs with the later entries of its colour run
         auto pair_runs = [&](int n) {
