@@ -239,12 +239,26 @@ BucketInfo buckets_from_lists(picasso_ctx *h, Batch &b, int64_t m, int64_t E, in
     int32_t *binst = buf<int32_t>(h, h->binst, (size_t)P);
     launch_bucket_table(b, P, binst, st);
     b.binst = binst;
+    // matrix shapes and their offsets (they depend on the bucket sizes only),
+    // so that one round trip brings every total the host needs
+    int64_t *tiles = buf<int64_t>(h, h->tiles, (size_t)P);
+    int64_t *words = buf<int64_t>(h, h->words, (size_t)P);
+    int64_t *tile_off = buf<int64_t>(h, h->tile_off, (size_t)P + 1);
+    int64_t *rb_off = buf<int64_t>(h, h->rb_off, (size_t)P + 1);
+    launch_bucket_shapes(bstart, P, tiles, words, st);
+    exclusive_scan_i64(tiles, tile_off, P, true, tmp, st);
+    exclusive_scan_i64(words, rb_off, P, true, tmp, st);
     unsigned long long hs[2];
+    int64_t t2[2];
     PCHECK_HIP(hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, st));
+    PCHECK_HIP(hipMemcpyAsync(&t2[0], tile_off + P, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    PCHECK_HIP(hipMemcpyAsync(&t2[1], rb_off + P, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     PCHECK_HIP(hipStreamSynchronize(st));
     BucketInfo bi;
     bi.pair_tests = (int64_t)hs[0];
     bi.max_size = (int64_t)hs[1];
+    bi.row_tiles = t2[0];
+    bi.words = t2[1];
     if (bi.max_size > (int64_t)1 << 17)
         throw Error(PICASSO_EINVAL, "a colour bucket holds " + std::to_string(bi.max_size) +
                                         " vertices (limit 131072): palette too small for this many vertices");
@@ -253,19 +267,6 @@ BucketInfo buckets_from_lists(picasso_ctx *h, Batch &b, int64_t m, int64_t E, in
     uint8_t *tslot = large ? buf<uint8_t>(h, h->tmp_slot, (size_t)E) : nullptr;
     int64_t *pos_of = buf<int64_t>(h, h->pos_of, (size_t)std::max<int64_t>(E, 1));
     launch_bucket_sort(bstart, P, bmem, bslot, prio, pos_of, b.loff, large, tmem, tslot, st);
-    int64_t *tiles = buf<int64_t>(h, h->tiles, (size_t)P);
-    int64_t *words = buf<int64_t>(h, h->words, (size_t)P);
-    int64_t *tile_off = buf<int64_t>(h, h->tile_off, (size_t)P + 1);
-    int64_t *rb_off = buf<int64_t>(h, h->rb_off, (size_t)P + 1);
-    launch_bucket_shapes(bstart, P, tiles, words, st);
-    exclusive_scan_i64(tiles, tile_off, P, true, tmp, st);
-    exclusive_scan_i64(words, rb_off, P, true, tmp, st);
-    int64_t t2[2];
-    PCHECK_HIP(hipMemcpyAsync(&t2[0], tile_off + P, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    PCHECK_HIP(hipMemcpyAsync(&t2[1], rb_off + P, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    PCHECK_HIP(hipStreamSynchronize(st));
-    bi.row_tiles = t2[0];
-    bi.words = t2[1];
     return bi;
 }
 
@@ -347,8 +348,7 @@ int64_t build_conflict_graph(picasso_ctx *h, const Batch &b, int64_t m, int64_t 
     da.n_slow = nslow;
     if (T_max > 1) {
         launch_dup(da, st);
-        const int32_t n_slow = read_scalar(h, nslow);
-        launch_dup_slow(da, n_slow, st);
+        launch_dup_slow(da, st);  // its bucket count is read on the device
     }
     // edge counts per (vertex, slot), scan, row pointers
     CsrArgs ca{};
@@ -466,7 +466,9 @@ int32_t color_buckets(picasso_ctx *h, const Batch &b, int64_t m, int64_t E, int6
     RoundGraph graph;
     const int32_t max_batch = std::max<int32_t>(h->jp_batch, 1);
     int32_t rounds = 0;
-    int cur = 0, batch = std::min<int32_t>(2, max_batch);
+    // rounds with nothing to do exit at once, so a first batch of several
+    // rounds costs less than host checks between them
+    int cur = 0, batch = std::min<int32_t>(8, max_batch);
     unsigned long long at_restart = 0;
     bool fresh = true;  // the lists hold every bucket
     while (true) {

@@ -187,7 +187,7 @@ struct DupArgs {
     int32_t *n_slow;
 };
 void launch_dup(const DupArgs &a, hipStream_t st);
-void launch_dup_slow(const DupArgs &a, int64_t n_slow, hipStream_t st);
+void launch_dup_slow(const DupArgs &a, hipStream_t st);  // count of slow buckets read on the device
 
 struct CsrArgs {
     const int64_t *bstart;

@@ -350,8 +350,9 @@ __global__ void __launch_bounds__(kDupThreads) dup_kernel(DupArgs a)
 
 // Buckets the LDS pass cannot take: every relation pair is checked directly
 // by merging the two prefixes (rare: only very large buckets).
-__global__ void __launch_bounds__(256) dup_slow_kernel(DupArgs a, int64_t n_slow)
+__global__ void __launch_bounds__(256) dup_slow_kernel(DupArgs a)
 {
+    const int64_t n_slow = *a.n_slow;
     for (int64_t b = blockIdx.x; b < n_slow; b += gridDim.x) {
         const int64_t c = a.slow[b];
         const int64_t base = a.bstart[c];
@@ -485,10 +486,11 @@ void launch_dup(const DupArgs &a, hipStream_t st)
     PCHECK_LAUNCH();
 }
 
-void launch_dup_slow(const DupArgs &a, int64_t n_slow, hipStream_t st)
+void launch_dup_slow(const DupArgs &a, hipStream_t st)
 {
-    if (n_slow <= 0) return;
-    dup_slow_kernel<<<grid_cap(n_slow, 1 << 16), 256, 0, st>>>(a, n_slow);
+    if (a.P <= 0) return;
+    // a fixed grid; blocks past the device-side count of slow buckets exit
+    dup_slow_kernel<<<grid_cap(a.P, 1024), 256, 0, st>>>(a);
     PCHECK_LAUNCH();
 }
 
