@@ -41,11 +41,15 @@ PAIR_TRAFFIC = {
 }
 
 
-def recorded_traffic(workload: str, path: str):
+# The same two counter runs for the CSR fill kernel's iteration-1 launch
+# (edge compaction), valid for the source file of that kernel.
+FILL_TRAFFIC = None
+
+
+def recorded_traffic(workload: str, path: str, rec):
     import hashlib
 
-    rec = PAIR_TRAFFIC
-    if workload != rec["workload"] or path != rec["path"]:
+    if rec is None or workload != rec["workload"] or path != rec["path"]:
         return None
     with open(os.path.join(ROOT, rec["source"]), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != rec["sha256"]:
@@ -211,7 +215,7 @@ def main():
         peak, unit, bound = VALU_PEAK_TOPS, "Tops/s", "alu"
         ops_all = sum(ops_per_test * s["pair_tests"] for s in per_step)
     achieved = ops1 / (ms1 * 1e-3) / 1e12
-    traffic = recorded_traffic(workload["workload"], args.path) if not batch else None
+    traffic = recorded_traffic(workload["workload"], args.path, PAIR_TRAFFIC) if not batch else None
     roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
             "traffic": traffic,
             "kernel": "pair pass (relation bit matrices), iteration-1 launch",
@@ -220,6 +224,29 @@ def main():
                              "frac": ops_all / (count_ms * 1e-3) / 1e12 / peak}}
     if traffic:
         roof["traffic_unit"] = "bytes per launch (HBM, counter-scaled)"
+
+    # edge compaction (CSR fill), bound by HBM: it writes two int32 column
+    # indices per undirected conflict edge; reading the bucket relation rows
+    # and member ids is overhead of this design, not counted
+    fill1 = sum(it["ms_fill"] for it in first) / len(first)
+    edges1 = first[0]["edges"]
+    fill_bytes = 8 * edges1
+    fill_gbs = fill_bytes / (fill1 * 1e-3) / 1e9 if fill1 > 0 else None
+    fill = {"bound": "hbm", "kernel": "CSR fill (edge compaction), iteration-1 launch", "avg_launch_ms": fill1,
+            "edges_per_launch": edges1, "algorithmic_bytes": fill_bytes, "achieved": fill_gbs,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fill_gbs / HBM_PEAK_GBS if fill_gbs else None,
+            "traffic": None}
+    ftraffic = recorded_traffic(workload["workload"], args.path, FILL_TRAFFIC) if not batch else None
+    if ftraffic and fill1 > 0:
+        fill["traffic"] = ftraffic
+        fill["traffic_GBs"] = ftraffic / (fill1 * 1e-3) / 1e9
+        fill["traffic_unit"] = "bytes per launch (HBM, counter-scaled)"
+    graph_ms = sum(it["ms_graph"] for s in per_step for it in s["iters"]) / args.steps
+
+    # colour counts over colouring seeds 0-4 (untimed)
+    seeds_nc = None
+    if not batch:
+        seeds_nc = [int(h.color_device(out, sd, cfg.frac, cfg.alpha, cfg.relation)) for sd in range(5)]
 
     workload["pair_path"] = args.path
     if tuned:
@@ -244,11 +271,15 @@ def main():
         "pair_tests": pair_tests,
         "conflict_edges": edges,
         "conflict_edges_per_s": edges / (ms_step * 1e-3),
-        "phase_ms_per_step": {"pair_pass": count_ms / args.steps, "pair_fill": fill_ms / args.steps,
-                              "list_color": color_ms / args.steps},
+        "conflict_edges_per_s_graph_build": edges / (graph_ms * 1e-3) if graph_ms > 0 else None,
+        "phase_ms_per_step": {"graph_build": graph_ms, "pair_pass": count_ms / args.steps,
+                              "pair_fill": fill_ms / args.steps, "list_color": color_ms / args.steps},
         "peak_device_bytes": st["peak_device_bytes"],
         "roofline": roof,
+        "edge_compaction": fill,
     }
+    if seeds_nc:
+        line["n_colors_seeds_0_4"] = {"n_colors": seeds_nc, "mean": sum(seeds_nc) / len(seeds_nc)}
     h.close()
     if not batch and not args.no_learned and os.path.exists(learn.PREDICTOR):
         # learned parameters (the stored network) against the fixed ones, each

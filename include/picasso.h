@@ -41,8 +41,14 @@ typedef struct picasso_ctx *picasso_handle;
 enum {
     PICASSO_REL_ANTICOMMUTE = 0, /* edge iff the strings anticommute: odd number of
                                     anticommuting positions (Sec. IV-A, Eq. 5)      */
-    PICASSO_REL_QWC = 1          /* edge iff not qubit-wise commuting: some position
+    PICASSO_REL_QWC = 1,         /* edge iff not qubit-wise commuting: some position
                                     holds two different non-identity Paulis (Sec. III) */
+    PICASSO_REL_COMMUTE = 2      /* edge iff the strings commute: even number of
+                                    anticommuting positions.  The orientation of the
+                                    paper's unitary-partitioning application (Sec. II,
+                                    Sec. IV-A): colour classes are sets of mutually
+                                    anticommuting strings.  Identical strings commute,
+                                    so duplicates always conflict.                     */
 };
 
 /* Return codes. */
@@ -107,7 +113,12 @@ typedef struct {
     int32_t pair_path;  /* PICASSO_PATH_VALU or PICASSO_PATH_MFMA (0: the tail
                            kernel, see PICASSO_OPT_TAIL)                        */
     int32_t jp_rounds;  /* colouring rounds                                    */
-    double ms_lists, ms_buckets, ms_count, ms_fill, ms_color, ms_compact;
+    double ms_graph;   /* conflict-graph build: pair pass through CSR fill   */
+    double ms_buckets; /* list sampling and colour-bucket build              */
+    double ms_count;   /* pair pass (relation bit matrices)                  */
+    double ms_fill;    /* CSR fill (edge compaction)                          */
+    double ms_color;   /* list colouring rounds                               */
+    double ms_compact; /* output colours, counts and the next vertex set      */
 } picasso_iter_stats;
 
 /* Summary of the handle's last colouring call. */

@@ -22,6 +22,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 REL_ANTICOMMUTE = 0
 REL_QWC = 1
+REL_COMMUTE = 2
 
 
 def build(force: bool = True) -> str:

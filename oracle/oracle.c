@@ -42,6 +42,7 @@
 
 #define ORC_REL_ANTICOMMUTE 0
 #define ORC_REL_QWC 1
+#define ORC_REL_COMMUTE 2
 
 /* ------------------------------------------------------------------------ */
 /* Pauli strings and the pairwise relation (Sec. IV-A, Eq. 4-5; Sec. III)     */
@@ -80,6 +81,9 @@ int orc_qubit_anticommutes(char a, char b)
  *              positions is odd (Sec. IV-A, the parity rule after Eq. 5).
  * QWC:         "not qubit-wise commuting": some position anticommutes
  *              (qubit-wise commutativity, Sec. III).
+ * COMMUTE:     the strings commute (even count): the orientation of the
+ *              paper's own application (Sec. II and Sec. IV-A), whose colour
+ *              classes are sets of mutually anticommuting strings.
  * Returns 1 when the pair fails the grouping relation (a graph edge). */
 int orc_relation_chars(int32_t q, const char *a, const char *b, int32_t rel)
 {
@@ -87,6 +91,7 @@ int orc_relation_chars(int32_t q, const char *a, const char *b, int32_t rel)
     for (int k = 0; k < q; k++)
         if (orc_qubit_anticommutes(a[k], b[k])) count++;
     if (rel == ORC_REL_ANTICOMMUTE) return count % 2 == 1;
+    if (rel == ORC_REL_COMMUTE) return count % 2 == 0;
     return count > 0;
 }
 

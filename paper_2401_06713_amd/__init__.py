@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_PKG, "libpicasso.so")
 
 REL_ANTICOMMUTE = 0
 REL_QWC = 1
+REL_COMMUTE = 2
 PATH_AUTO, PATH_VALU, PATH_MFMA = 0, 1, 2
 (OPT_MEM_BUDGET, OPT_PAIR_PATH, OPT_FIXED_T, OPT_STREAM, OPT_TIMING, OPT_JP_BATCH, OPT_GRAPH,
  OPT_MFMA_CAP, OPT_TAIL) = 1, 2, 3, 4, 5, 6, 7, 8, 9
@@ -68,7 +69,7 @@ class IterStats(ctypes.Structure):
         ("offset", ctypes.c_int64),
         ("pair_path", ctypes.c_int32),
         ("jp_rounds", ctypes.c_int32),
-        ("ms_lists", ctypes.c_double),
+        ("ms_graph", ctypes.c_double),
         ("ms_buckets", ctypes.c_double),
         ("ms_count", ctypes.c_double),
         ("ms_fill", ctypes.c_double),

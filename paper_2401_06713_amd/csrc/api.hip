@@ -81,7 +81,7 @@ struct picasso_ctx {
     Arena arena;
     DevBuf x, z, xz;  // bit-planes, and the interleaved copy the member gather reads
     // iteration buffers
-    DevBuf ids, next_ids, lists, prio, bcnt, bstart, bmem, bslot, pos_of, tmp_mem, tmp_slot, tiles, words, tile_off,
+    DevBuf ids, next_ids, lists, prio, bcnt, bstart, bmem, bslot, pos_of, bent, tmp_mem, tmp_slot, tiles, words, tile_off,
         rb_off, R, D, bx, bz, tile_bucket, nslow, slow, slot_cnt, slot_off, rowptr, adj, col, blk, fre, nblk, st,
         dirty, wake_at, wl, flags, pos, used, scan_tmp, scalars, out_colors, inst, vinst, loff, binst, inst_out, tail_recs,
         tail_table, tail_outs, tail_iters, tail_ranges;
@@ -266,7 +266,8 @@ BucketInfo buckets_from_lists(picasso_ctx *h, Batch &b, int64_t m, int64_t E, in
     uint32_t *tmem = large ? buf<uint32_t>(h, h->tmp_mem, (size_t)E) : nullptr;
     uint8_t *tslot = large ? buf<uint8_t>(h, h->tmp_slot, (size_t)E) : nullptr;
     int64_t *pos_of = buf<int64_t>(h, h->pos_of, (size_t)std::max<int64_t>(E, 1));
-    launch_bucket_sort(bstart, P, bmem, bslot, prio, pos_of, b.loff, large, tmem, tslot, st);
+    int64_t *bent = buf<int64_t>(h, h->bent, (size_t)std::max<int64_t>(E, 1));
+    launch_bucket_sort(bstart, P, bmem, bslot, prio, pos_of, bent, b.loff, large, tmem, tslot, st);
     return bi;
 }
 
@@ -310,7 +311,7 @@ int64_t build_conflict_graph(picasso_ctx *h, const Batch &b, int64_t m, int64_t 
                        buf<int32_t>(h, h->tile_bucket, (size_t)std::max<int64_t>(bi.row_tiles, 1)), st);
     bool any_mfma = false;
     tm.mark();
-    for (int32_t rel = 0; rel < 2; ++rel) {
+    for (int32_t rel = 0; rel < 3; ++rel) {
         if (!(rel_mask >> rel & 1)) continue;
         const bool mfma = h->pair_path == PICASSO_PATH_MFMA ||
                           (h->pair_path == PICASSO_PATH_AUTO && mfma_supported(h->q, rel));
@@ -340,6 +341,7 @@ int64_t build_conflict_graph(picasso_ctx *h, const Batch &b, int64_t m, int64_t 
     da.rb_off = ra.rb_off;
     da.lists = static_cast<const uint32_t *>(h->lists.p);
     da.loff = b.loff;
+    da.bent = static_cast<const int64_t *>(h->bent.p);
     da.binst = b.binst;
     da.inst = b.inst;
     da.R = R;
@@ -360,6 +362,7 @@ int64_t build_conflict_graph(picasso_ctx *h, const Batch &b, int64_t m, int64_t 
     ca.R = R;
     ca.D = D;
     ca.loff = b.loff;
+    ca.bent = da.bent;
     ca.slot_cnt = buf<int32_t>(h, h->slot_cnt, (size_t)std::max<int64_t>(E, 1));
     launch_count(ca, st);
     int64_t *slot_off = buf<int64_t>(h, h->slot_off, (size_t)E + 1);
@@ -383,7 +386,7 @@ int64_t build_conflict_graph(picasso_ctx *h, const Batch &b, int64_t m, int64_t 
     ca.slot_off = slot_off;
     ca.adj = buf<int32_t>(h, h->adj, (size_t)std::max<int64_t>(total, 1));
     tm.mark();
-    launch_fill(ca, st);
+    launch_fill(ca, bi.max_size, st);
     tm.mark();
     if (ms_relate) *ms_relate = tm.ms(0, 1);
     if (ms_csr) *ms_csr = tm.ms(2, 3);
@@ -570,7 +573,7 @@ void add_iter(picasso_stats &S, std::vector<int64_t> &iter_edges, int64_t idx, c
         d.offset = it.offset;
         d.pair_path = std::max(d.pair_path, it.pair_path);
         d.jp_rounds += it.jp_rounds;
-        d.ms_lists += it.ms_lists;
+        d.ms_graph += it.ms_graph;
         d.ms_buckets += it.ms_buckets;
         d.ms_count += it.ms_count;
         d.ms_fill += it.ms_fill;
@@ -814,6 +817,7 @@ int64_t color_all(picasso_ctx *h, const RunArgs &ra, int32_t *d_out, int64_t *n_
         }
         it.colored = m - m_next;
         it.ms_buckets = tm.ms(0, 1);
+        it.ms_graph = tm.ms(1, 2);
         it.ms_color = tm.ms(2, 3);
         it.ms_compact = tm.ms(3, 4);
         add_iter(S, iter_edges, ell - 1, it);
@@ -883,7 +887,8 @@ void check_handle(picasso_handle h)
 
 void check_rel(int32_t rel)
 {
-    if (rel != PICASSO_REL_ANTICOMMUTE && rel != PICASSO_REL_QWC) throw Error(PICASSO_EINVAL, "unknown relation");
+    if (rel != PICASSO_REL_ANTICOMMUTE && rel != PICASSO_REL_QWC && rel != PICASSO_REL_COMMUTE)
+        throw Error(PICASSO_EINVAL, "unknown relation");
 }
 
 void check_single(picasso_ctx *h)
@@ -1031,7 +1036,7 @@ void picasso_destroy(picasso_handle h)
     (void)hipSetDevice(h->device);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     DevBuf *all[] = {&h->x,       &h->z,       &h->xz,        &h->ids,     &h->next_ids, &h->lists,   &h->prio,     &h->bcnt,
-                     &h->bstart,  &h->bmem,     &h->bslot,   &h->pos_of,   &h->tmp_mem, &h->tmp_slot, &h->tiles,
+                     &h->bstart,  &h->bmem,     &h->bslot,   &h->pos_of,   &h->bent, &h->tmp_mem, &h->tmp_slot, &h->tiles,
                      &h->words,   &h->tile_off, &h->rb_off,  &h->R,        &h->D,       &h->nslow,    &h->slow,
                      &h->slot_cnt, &h->slot_off, &h->rowptr, &h->adj,      &h->col,     &h->blk,      &h->fre,
                      &h->nblk,    &h->st,       &h->dirty,   &h->wl,       &h->flags,   &h->pos,      &h->used,

@@ -356,17 +356,31 @@ __global__ void csr_to_relation_kernel(int64_t m, const int64_t *rowptr, const i
 __global__ void finish_kernel(Batch b, int64_t m, const int32_t *col, const int32_t *ids, int32_t *out_colors,
                               uint32_t *used_bits, unsigned long long *n_used, int32_t *uncol_flag)
 {
+    // The first vertex to set a colour's bit counts that colour for its
+    // instance.  Those counts are summed over the wave before the atomic add
+    // (one counter per instance would otherwise take one add per colour).
+    const int lane = threadIdx.x & 63;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t c = col[i];
+        int32_t ii = -1;
+        bool first = false;
         if (c >= 0) {
-            const int32_t ii = b.vinst[i];
+            ii = b.vinst[i];
             const InstRec &r = b.inst[ii];
             if (out_colors) out_colors[ids[i]] = (int32_t)(r.cbase + (c - r.pal));
             const uint32_t bit = 1u << (c & 31);
-            if (!(atomicOr(&used_bits[c >> 5], bit) & bit)) atomicAdd(&n_used[ii], 1ull);
+            first = !(atomicOr(&used_bits[c >> 5], bit) & bit);
             uncol_flag[i] = 0;
         } else {
             uncol_flag[i] = 1;
+        }
+        const uint64_t firsts = __ballot(first);
+        if (firsts) {
+            const int lead = __builtin_ctzll(firsts);
+            const int32_t lead_ii = __shfl(ii, lead, 64);
+            const uint64_t same = __ballot(first && ii == lead_ii);
+            if (lane == lead) atomicAdd(&n_used[lead_ii], (unsigned long long)__popcll(same));
+            if (first && ii != lead_ii) atomicAdd(&n_used[ii], 1ull);
         }
     }
 }

@@ -124,10 +124,12 @@ void launch_check_padding(const uint64_t *x, const uint64_t *z, int64_t n, int32
                           hipStream_t st);
 
 // lists.hip: bucket order.  Sorts each bucket's members by (priority,
-// local index); pos_of[loff[v] + k] receives the bucket position of (v, k).
+// local index); pos_of[loff[v] + k] receives the bucket position of (v, k)
+// and bent[position] its list entry loff[v] + k (the inverse permutation, so
+// that kernels walking a bucket read their members' list entries in order).
 void launch_bucket_sort(const int64_t *bstart, int64_t P, uint32_t *bmem, uint8_t *bslot, const uint64_t *prio,
-                        int64_t *pos_of, const int64_t *loff, bool has_large, uint32_t *tmp_mem, uint8_t *tmp_slot,
-                        hipStream_t st);
+                        int64_t *pos_of, int64_t *bent, const int64_t *loff, bool has_large, uint32_t *tmp_mem,
+                        uint8_t *tmp_slot, hipStream_t st);
 // Sum of C(|B_c|, 2) into pairs[0], largest |B_c| into pairs[1].
 void launch_bucket_pairs(const uint32_t *bcnt, int64_t P, unsigned long long *pairs, hipStream_t st);
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
@@ -179,6 +181,7 @@ struct DupArgs {
     const int64_t *rb_off;
     const uint32_t *lists;  // rows sorted, row v at loff[v]
     const int64_t *loff;
+    const int64_t *bent;    // list entry loff[v] + k of each bucket member (v, k)
     const int32_t *binst;   // instance of each bucket (its palette start bounds the colours below it)
     const InstRec *inst;
     const uint64_t *R;      // relation matrices (the exact check visits relation pairs only)
@@ -197,12 +200,13 @@ struct CsrArgs {
     const int64_t *rb_off;
     const uint64_t *R, *D;
     const int64_t *loff;     // list entry of (v, 0)
+    const int64_t *bent;     // list entry of each bucket member
     int32_t *slot_cnt;       // count pass: edge count per list entry (vertex, slot)
     const int64_t *slot_off; // fill pass: exclusive scan of slot_cnt
     int32_t *adj;            // fill pass: CSR column indices
 };
 void launch_count(const CsrArgs &a, hipStream_t st);
-void launch_fill(const CsrArgs &a, hipStream_t st);
+void launch_fill(const CsrArgs &a, int64_t max_size, hipStream_t st);  // max_size: largest bucket
 void launch_rowptr(const int64_t *slot_off, int64_t m, const int64_t *loff, int64_t *rowptr, hipStream_t st);
 
 // color.hip

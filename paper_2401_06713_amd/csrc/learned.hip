@@ -49,7 +49,8 @@ __global__ void features_kernel(int64_t m, const int32_t *__restrict__ ids, cons
                 par ^= t;
                 any |= t;
             }
-            hsum += rel == PICASSO_REL_ANTICOMMUTE ? (unsigned long long)(__popcll(par) & 1) : (any != 0);
+            const unsigned long long odd = __popcll(par) & 1;
+            hsum += rel == PICASSO_REL_ANTICOMMUTE ? odd : rel == PICASSO_REL_COMMUTE ? 1 - odd : (any != 0);
         }
     for (int d = 32; d > 0; d >>= 1) {
         wsum += __shfl_down(wsum, d, 64);

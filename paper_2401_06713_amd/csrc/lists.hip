@@ -186,6 +186,7 @@ __global__ void __launch_bounds__(kSortThreads) bucket_sort_kernel(const int64_t
                                                                    uint8_t *__restrict__ bslot,
                                                                    const uint64_t *__restrict__ prio,
                                                                    int64_t *__restrict__ pos_of,
+                                                                   int64_t *__restrict__ bent,
                                                                    const int64_t *__restrict__ loff)
 {
     __shared__ uint64_t key[kSortCap];
@@ -196,7 +197,11 @@ __global__ void __launch_bounds__(kSortThreads) bucket_sort_kernel(const int64_t
         const int64_t base = bstart[c];
         const int64_t S = bstart[c + 1] - base;
         if (S > kSortCap) continue;
-        if (S == 1 && t == 0) pos_of[loff[bmem[base]] + bslot[base]] = base;
+        if (S == 1 && t == 0) {
+            const int64_t en = loff[bmem[base]] + bslot[base];
+            pos_of[en] = base;
+            bent[base] = en;
+        }
         if (S < 2) continue;
         int N = 2;
         while (N < S) N <<= 1;
@@ -240,7 +245,9 @@ __global__ void __launch_bounds__(kSortThreads) bucket_sort_kernel(const int64_t
         for (int e = t; e < S; e += kSortThreads) {
             bmem[base + e] = vid[e];
             bslot[base + e] = sl[e];
-            pos_of[loff[vid[e]] + sl[e]] = base + e;
+            const int64_t en = loff[vid[e]] + sl[e];
+            pos_of[en] = base + e;
+            bent[base + e] = en;
         }
     }
 }
@@ -276,6 +283,7 @@ __global__ void __launch_bounds__(kSortThreads) bucket_rank_copy_kernel(const in
                                                                         const uint32_t *__restrict__ tmp_mem,
                                                                         const uint8_t *__restrict__ tmp_slot,
                                                                         int64_t *__restrict__ pos_of,
+                                                                        int64_t *__restrict__ bent,
                                                                         const int64_t *__restrict__ loff)
 {
     for (int64_t c = blockIdx.x; c < P; c += gridDim.x) {
@@ -287,7 +295,9 @@ __global__ void __launch_bounds__(kSortThreads) bucket_rank_copy_kernel(const in
             const uint8_t k = tmp_slot[base + p];
             bmem[base + p] = v;
             bslot[base + p] = k;
-            pos_of[loff[v] + k] = base + p;
+            const int64_t en = loff[v] + k;
+            pos_of[en] = base + p;
+            bent[base + p] = en;
         }
     }
 }
@@ -403,18 +413,18 @@ void launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t st)
 }
 
 void launch_bucket_sort(const int64_t *bstart, int64_t P, uint32_t *bmem, uint8_t *bslot, const uint64_t *prio,
-                        int64_t *pos_of, const int64_t *loff, bool has_large, uint32_t *tmp_mem,
+                        int64_t *pos_of, int64_t *bent, const int64_t *loff, bool has_large, uint32_t *tmp_mem,
                         uint8_t *tmp_slot, hipStream_t st)
 {
     if (P <= 0) return;
     const unsigned grid = (unsigned)(P < (1 << 20) ? P : (1 << 20));
-    bucket_sort_kernel<<<grid, kSortThreads, 0, st>>>(bstart, P, bmem, bslot, prio, pos_of, loff);
+    bucket_sort_kernel<<<grid, kSortThreads, 0, st>>>(bstart, P, bmem, bslot, prio, pos_of, bent, loff);
     PCHECK_LAUNCH();
     if (has_large) {
         bucket_rank_kernel<<<grid, kSortThreads, 0, st>>>(bstart, P, bmem, bslot, prio, tmp_mem, tmp_slot);
         PCHECK_LAUNCH();
         bucket_rank_copy_kernel<<<grid, kSortThreads, 0, st>>>(bstart, P, bmem, bslot, tmp_mem, tmp_slot, pos_of,
-                                                                 loff);
+                                                                 bent, loff);
         PCHECK_LAUNCH();
     }
 }

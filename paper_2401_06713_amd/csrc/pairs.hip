@@ -81,7 +81,7 @@ __global__ void __launch_bounds__(kDupThreads) dup_kernel(DupArgs a)
             const int p = p0 + t;
             int k = 0;
             if (p < S) {
-                lbase[p] = a.loff[a.bmem[base + p]];
+                lbase[p] = a.bent[base + p] - a.bslot[base + p];
                 k = a.bslot[base + p];
             }
             int inc = k;
@@ -363,7 +363,7 @@ __global__ void __launch_bounds__(256) dup_slow_kernel(DupArgs a)
         for (int64_t p = threadIdx.x; p < S; p += blockDim.x) {
             const int kp = a.bslot[base + p];
             if (kp == 0) continue;
-            const uint32_t *Lp = a.lists + a.loff[a.bmem[base + p]];
+            const uint32_t *Lp = a.lists + (a.bent[base + p] - a.bslot[base + p]);
             for (int64_t w = 0; w < nw; ++w) {
                 uint64_t bits = Rm[p * nw + w];
                 while (bits) {
@@ -371,7 +371,7 @@ __global__ void __launch_bounds__(256) dup_slow_kernel(DupArgs a)
                     bits &= bits - 1;
                     const int kq = a.bslot[base + q];
                     if (kq == 0) continue;
-                    const uint32_t *Lq = a.lists + a.loff[a.bmem[base + q]];
+                    const uint32_t *Lq = a.lists + (a.bent[base + q] - a.bslot[base + q]);
                     int x = 0, y = 0;
                     bool shared = false;
                     while (x < kp && y < kq) {
@@ -402,7 +402,7 @@ __global__ void __launch_bounds__(kWave) count_kernel(CsrArgs a)
         for (int64_t p = threadIdx.x; p < S; p += kWave) {
             int cnt = 0;
             for (int64_t w = 0; w < nw; ++w) cnt += __popcll(Rm[p * nw + w] & ~Dm[p * nw + w]);
-            a.slot_cnt[a.loff[a.bmem[base + p]] + a.bslot[base + p]] = cnt;
+            a.slot_cnt[a.bent[base + p]] = cnt;
         }
     }
 }
@@ -410,18 +410,22 @@ __global__ void __launch_bounds__(kWave) count_kernel(CsrArgs a)
 // CSR rows: one wave per member row.  The 64 lanes test the 64 bits of a
 // row word, and a ballot prefix count (mbcnt) gives each set bit its slot in
 // the member's contiguous (vertex, slot) segment, so every store of the
-// wave lands in one run of the CSR.  When the bucket fits, its rows of
-// R & ~D, member ids and segment offsets are first staged in LDS with
-// independent loads.
+// wave lands in one run of the CSR.  When the bucket fits the stage, its
+// rows of R & ~D, member ids and segment offsets are first staged in LDS
+// with independent loads.  The stage is sized by the launch to the largest
+// bucket (capped), so that small buckets leave room for many workgroups per
+// CU: the staging loads are a chain of dependent reads whose latency only
+// other resident workgroups hide.
 constexpr int kFillWaves = 4;
-constexpr int kFillMembers = 1024;
-constexpr int kFillWords = 4096;
+constexpr int64_t kFillMembers = 1024;
+constexpr int64_t kFillWords = 4096;
 
-__global__ void __launch_bounds__(kWave * kFillWaves) fill_kernel(CsrArgs a)
+__global__ void __launch_bounds__(kWave * kFillWaves) fill_kernel(CsrArgs a, int64_t cap_members, int64_t cap_words)
 {
-    __shared__ uint64_t rows[kFillWords];
-    __shared__ int64_t seg[kFillMembers];
-    __shared__ uint32_t mv[kFillMembers];
+    extern __shared__ uint64_t fill_lds[];
+    uint64_t *rows = fill_lds;                                         // cap_words
+    int64_t *seg = reinterpret_cast<int64_t *>(fill_lds + cap_words); // cap_members
+    uint32_t *mv = reinterpret_cast<uint32_t *>(seg + cap_members);    // cap_members
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int64_t c = blockIdx.x; c < a.P; c += gridDim.x) {
         const int64_t base = a.bstart[c];
@@ -430,12 +434,12 @@ __global__ void __launch_bounds__(kWave * kFillWaves) fill_kernel(CsrArgs a)
         const int64_t nw = (S + 63) >> 6;
         const uint64_t *Rm = a.R + a.rb_off[c];
         const uint64_t *Dm = a.D + a.rb_off[c];
-        if (S <= kFillMembers && S * nw <= kFillWords) {
+        if (S <= cap_members && S * nw <= cap_words) {
             __syncthreads();
             for (int64_t p = threadIdx.x; p < S; p += blockDim.x) {
                 const uint32_t v = a.bmem[base + p];
                 mv[p] = v;
-                seg[p] = a.slot_off[a.loff[v] + a.bslot[base + p]];
+                seg[p] = a.slot_off[a.bent[base + p]];
             }
             for (int64_t w = threadIdx.x; w < S * nw; w += blockDim.x) rows[w] = Rm[w] & ~Dm[w];
             __syncthreads();
@@ -451,8 +455,7 @@ __global__ void __launch_bounds__(kWave * kFillWaves) fill_kernel(CsrArgs a)
             }
         } else {
             for (int64_t p = wave; p < S; p += kFillWaves) {
-                const uint32_t vp = a.bmem[base + p];
-                int64_t at = a.slot_off[a.loff[vp] + a.bslot[base + p]];
+                int64_t at = a.slot_off[a.bent[base + p]];
                 for (int64_t w = 0; w < nw; ++w) {
                     const uint64_t bits = Rm[p * nw + w] & ~Dm[p * nw + w];
                     const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bits >> 32),
@@ -501,10 +504,15 @@ void launch_count(const CsrArgs &a, hipStream_t st)
     PCHECK_LAUNCH();
 }
 
-void launch_fill(const CsrArgs &a, hipStream_t st)
+void launch_fill(const CsrArgs &a, int64_t max_size, hipStream_t st)
 {
     if (a.P <= 0) return;
-    fill_kernel<<<grid_cap(a.P, 1 << 20), kWave * kFillWaves, 0, st>>>(a);
+    // stage: every bucket up to the largest one present, within the caps
+    // (larger buckets read their rows from global memory directly)
+    const int64_t cap_members = std::min<int64_t>(std::max<int64_t>(max_size, 64), kFillMembers);
+    const int64_t cap_words = std::min<int64_t>(cap_members * ((cap_members + 63) >> 6), kFillWords);
+    const size_t lds = (size_t)cap_words * 8 + (size_t)cap_members * 12;
+    fill_kernel<<<grid_cap(a.P, 1 << 20), kWave * kFillWaves, lds, st>>>(a, cap_members, cap_words);
     PCHECK_LAUNCH();
 }
 

@@ -23,11 +23,21 @@ __device__ __forceinline__ uint32_t pair_bit(const uint32_t (&xi)[2 * W], const 
 #pragma unroll
     for (int h = 0; h < 2 * W; ++h) {
         const uint32_t a = (xi[h] & zj[h]) ^ (zi[h] & xj[h]);
-        if (REL == PICASSO_REL_ANTICOMMUTE) acc ^= a;
-        else acc |= a;
+        if (REL == PICASSO_REL_QWC) acc |= a;
+        else acc ^= a;
     }
     if (REL == PICASSO_REL_ANTICOMMUTE) return __popc(acc) & 1u;
+    if (REL == PICASSO_REL_COMMUTE) return (__popc(acc) & 1u) ^ 1u;
     return acc != 0u;
+}
+
+// Members of a 64-wide tile t below the bucket size: the bits a row word may
+// hold.  Padding members are zero strings, which commute with everything, so
+// the COMMUTE relation masks them (the other relations give 0 there).
+__device__ __forceinline__ uint64_t tile_mask(int64_t S, int64_t t)
+{
+    const int64_t k = S - t * 64;
+    return k >= 64 ? ~0ull : ((1ull << k) - 1ull);
 }
 
 // 64 x 64 bit transpose across a wave: lane l holds row l; afterwards lane
@@ -132,7 +142,8 @@ __global__ void __launch_bounds__(kWave * kRelWaves) relate_kernel(RelateArgs a)
         const uint64_t r = ((uint64_t)pair_bit<W, REL>(xi, zi, &cx[j32 * 2 * W], &cz[j32 * 2 * W]) << 32) | rl;
         const int rot = lane;
         const uint64_t placed = rot ? ((r << rot) | (r >> (64 - rot))) : r;
-        const uint64_t diag = placed | wave_transpose64(placed);
+        uint64_t diag = placed | wave_transpose64(placed);
+        if (REL == PICASSO_REL_COMMUTE) diag &= tile_mask(S, rt);
         if (i < S) Rm[i * nw + rt] = diag;
         // tiles to the right
         for (int64_t ct = rt + 1; ct < nw; ++ct) {
@@ -158,7 +169,9 @@ __global__ void __launch_bounds__(kWave * kRelWaves) relate_kernel(RelateArgs a)
                 }
                 row |= (uint64_t)bits8 << (b * 8);
             }
-            const uint64_t col = wave_transpose64(row);
+            if (REL == PICASSO_REL_COMMUTE) row &= tile_mask(S, ct);
+            uint64_t col = wave_transpose64(row);
+            if (REL == PICASSO_REL_COMMUTE) col &= tile_mask(S, rt);
             if (i < S) Rm[i * nw + ct] = row;
             if (j < S) Rm[j * nw + rt] = col;
         }
@@ -222,7 +235,7 @@ __global__ void __launch_bounds__(kMfmaThreads) relate_mfma_kernel(RelateArgs a,
                 const int w = q0 >> 6, b = q0 & 63;      // q0 % 4 == 0, so 4 bits stay in one word
                 if (w < a.W) {
                     const uint64_t xv = a.bx[(base + r) * a.W + w], zv = a.bz[(base + r) * a.W + w];
-                    if (REL == PICASSO_REL_ANTICOMMUTE) {
+                    if (REL != PICASSO_REL_QWC) {
                         val = spread4(blk == 0 ? xv : zv, b);
                     } else {
                         const uint64_t pick = blk == 0 ? (xv | zv) : blk == 1 ? (xv & ~zv) : blk == 2 ? (xv & zv) : (zv & ~xv);
@@ -246,7 +259,7 @@ __global__ void __launch_bounds__(kMfmaThreads) relate_mfma_kernel(RelateArgs a,
                 const int off = kk + 16 * half;
                 const v4i av = *reinterpret_cast<const v4i *>(ra + off);
                 v4i bv;
-                if (REL == PICASSO_REL_ANTICOMMUTE) {
+                if (REL != PICASSO_REL_QWC) {
                     const int boff = off < qpad ? off + qpad : off - qpad;  // [z | x]
                     bv = *reinterpret_cast<const v4i *>(rb + boff);
                 } else {
@@ -264,10 +277,18 @@ __global__ void __launch_bounds__(kMfmaThreads) relate_mfma_kernel(RelateArgs a,
             // lane holds D[i][j] for column j = ct*32 + l32 and rows
             // i = rt*32 + 8*(r/4) + 4*half + r%4
             uint32_t m = 0u;
+            const int64_t jcol = (int64_t)ct * 32 + l32;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const uint32_t bitv = REL == PICASSO_REL_ANTICOMMUTE ? ((uint32_t)acc[r] & 1u) : (acc[r] > 0 ? 1u : 0u);
-                m |= bitv << (8 * (r >> 2) + 4 * half + (r & 3));
+                const int sh = 8 * (r >> 2) + 4 * half + (r & 3);
+                uint32_t bitv;
+                if (REL == PICASSO_REL_ANTICOMMUTE) bitv = (uint32_t)acc[r] & 1u;
+                else if (REL == PICASSO_REL_QWC) bitv = acc[r] > 0 ? 1u : 0u;
+                else {  // COMMUTE: even parity, except for a member with itself and padding rows
+                    const int64_t irow = (int64_t)rt * 32 + sh;
+                    bitv = (((uint32_t)acc[r] & 1u) ^ 1u) & (irow < S && irow != jcol ? 1u : 0u);
+                }
+                m |= bitv << sh;
             }
             m |= (uint32_t)__shfl_xor((int)m, 32, 64);
             const int64_t j = (int64_t)ct * 32 + l32;
@@ -359,6 +380,8 @@ void launch_relate(const RelateArgs &a, hipStream_t st)
     case WW:                                                                                       \
         if (a.relation == PICASSO_REL_ANTICOMMUTE)                                                 \
             relate_kernel<WW, PICASSO_REL_ANTICOMMUTE><<<grid, kWave * kRelWaves, 0, st>>>(a);     \
+        else if (a.relation == PICASSO_REL_COMMUTE)                                                \
+            relate_kernel<WW, PICASSO_REL_COMMUTE><<<grid, kWave * kRelWaves, 0, st>>>(a);         \
         else                                                                                       \
             relate_kernel<WW, PICASSO_REL_QWC><<<grid, kWave * kRelWaves, 0, st>>>(a);             \
         break;
@@ -377,14 +400,14 @@ void launch_relate(const RelateArgs &a, hipStream_t st)
 bool mfma_supported(int32_t q, int32_t relation)
 {
     const int32_t qpad = (q + 15) / 16 * 16;
-    const int32_t kbytes = relation == PICASSO_REL_ANTICOMMUTE ? 2 * qpad : 4 * qpad;
+    const int32_t kbytes = relation == PICASSO_REL_QWC ? 4 * qpad : 2 * qpad;
     return kbytes % 32 == 0 && (int64_t)32 * kbytes <= kMfmaLds;
 }
 
 int64_t mfma_member_cap(int32_t q, int32_t relation)
 {
     const int32_t qpad = (q + 15) / 16 * 16;
-    const int32_t kbytes = relation == PICASSO_REL_ANTICOMMUTE ? 2 * qpad : 4 * qpad;
+    const int32_t kbytes = relation == PICASSO_REL_QWC ? 4 * qpad : 2 * qpad;
     const int64_t fit = (int64_t)kMfmaLds / kbytes / 32 * 32;
     return fit < kMfmaMembers ? fit : kMfmaMembers;
 }
@@ -393,12 +416,14 @@ void launch_relate_mfma(const RelateArgs &a, int32_t q, hipStream_t st)
 {
     if (a.P <= 0) return;
     const int32_t qpad = (q + 15) / 16 * 16;
-    const int32_t kbytes = a.relation == PICASSO_REL_ANTICOMMUTE ? 2 * qpad : 4 * qpad;
+    const int32_t kbytes = a.relation == PICASSO_REL_QWC ? 4 * qpad : 2 * qpad;
     const int64_t cap = mfma_member_cap(q, a.relation);
     const size_t lds = (size_t)((cap + 31) / 32 * 32) * kbytes;
     const unsigned grid = grid_cap(a.P, 1 << 20);
     if (a.relation == PICASSO_REL_ANTICOMMUTE)
         relate_mfma_kernel<PICASSO_REL_ANTICOMMUTE><<<grid, kMfmaThreads, lds, st>>>(a, qpad, kbytes);
+    else if (a.relation == PICASSO_REL_COMMUTE)
+        relate_mfma_kernel<PICASSO_REL_COMMUTE><<<grid, kMfmaThreads, lds, st>>>(a, qpad, kbytes);
     else
         relate_mfma_kernel<PICASSO_REL_QWC><<<grid, kMfmaThreads, lds, st>>>(a, qpad, kbytes);
     PCHECK_LAUNCH();

@@ -29,7 +29,9 @@ __device__ __forceinline__ bool tail_relation(const uint64_t *su, const uint64_t
         par ^= t;
         any |= t;
     }
-    return rel == PICASSO_REL_ANTICOMMUTE ? (__popcll(par) & 1) : (any != 0);
+    if (rel == PICASSO_REL_ANTICOMMUTE) return __popcll(par) & 1;
+    if (rel == PICASSO_REL_COMMUTE) return !(__popcll(par) & 1);
+    return any != 0;
 }
 
 __global__ void __launch_bounds__(kTailThreads) tail_kernel(const TailRec *__restrict__ recs,

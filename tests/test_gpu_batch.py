@@ -29,7 +29,7 @@ def say(*a):
 
 
 def mixed_instances(count, seed):
-    """Uneven instances: sizes 0..1500, q across one to four words, both
+    """Uneven instances: sizes 0..1500, q across one to four words, all three
     relations, per-instance seeds, palette fractions and list multipliers."""
     rng = np.random.default_rng(seed)
     sizes = [0, 1, 2, 3, 17] + [int(v) for v in np.exp(rng.uniform(np.log(20), np.log(1500), count - 5))]
@@ -44,7 +44,7 @@ def mixed_instances(count, seed):
         x, z = wl.pauli_strings(n, q, (pI, r, r, r), seed=1000 + i) if n else (
             np.zeros((0, (q + 63) // 64), np.uint64), np.zeros((0, (q + 63) // 64), np.uint64))
         out.append(dict(x=x, z=z, q=q, seed=int(rng.integers(0, 2**63)), frac=float(rng.choice([0.08, 0.125, 0.3])),
-                        alpha=float(rng.choice([1.0, 2.0, 3.0])), rel=int(rng.integers(0, 2))))
+                        alpha=float(rng.choice([1.0, 2.0, 3.0])), rel=int(rng.integers(0, 3))))
     rng.shuffle(out)
     return out
 

@@ -64,7 +64,7 @@ _ORACLE_EDGES = {}
 
 
 @pytest.mark.parametrize("path", [pk.PATH_VALU, pk.PATH_MFMA])
-@pytest.mark.parametrize("rel", [0, 1])
+@pytest.mark.parametrize("rel", [0, 1, 2])
 @pytest.mark.parametrize("n,q,probs,P,T", [
     (2000, 16, (0.25, 0.25, 0.25, 0.25), 250, 16),    # C1 iteration 1
     (1500, 48, (0.7, 0.1, 0.1, 0.1), 120, 20),
@@ -146,7 +146,7 @@ def test_c1_bit_exact(orc):
         run_both(orc, x, z, cfg.q, seed, cfg.frac, cfg.alpha, cfg.relation)
 
 
-@pytest.mark.parametrize("rel", [0, 1])
+@pytest.mark.parametrize("rel", [0, 1, 2])
 @pytest.mark.parametrize("n,q,probs,frac,alpha", [
     (5000, 48, (0.7, 0.1, 0.1, 0.1), 0.125, 2.0),
     (3000, 100, (0.8, 0.2 / 3, 0.2 / 3, 0.2 / 3), 0.05, 3.0),
@@ -159,6 +159,25 @@ def test_color_bit_exact(orc, rel, n, q, probs, frac, alpha):
     x, z = strings(n, q, probs, seed=n + rel)
     for path in (pk.PATH_VALU, pk.PATH_MFMA):
         run_both(orc, x, z, q, 5, frac, alpha, rel, path=path)
+
+
+@pytest.mark.parametrize("path", [pk.PATH_VALU, pk.PATH_MFMA])
+def test_commute_relation_special_cases(orc, path):
+    """COMMUTE (the paper's own orientation): Majorana strings pairwise
+    anticommute, so their graph is empty and one iteration gives every string
+    its first list colour; {I, Z} strings pairwise commute, so every string
+    needs its own colour; the aggressive preset (palette 3% of |V|, list
+    size 30 ln|V|) matches the oracle bit for bit."""
+    say("commute special cases", path)
+    for q in (9, 33, 100):
+        x, z = wl.majorana_strings(q)
+        nc, col, st = run_both(orc, x, z, q, 4, 0.125, 2.0, 2, path=path)
+        assert st["n_iters"] == 1 and st["iters"][0]["edges"] == 0
+    x, z = wl.iz_strings(300, 16, seed=9)
+    nc, _, _ = run_both(orc, x, z, 16, 2, 0.125, 2.0, 2, path=path)
+    assert nc == 300
+    x, z = strings(1200, 24, (0.6, 0.1, 0.2, 0.1), seed=77)  # buckets of every string: exact dedup path
+    run_both(orc, x, z, 24, 1, 0.03, 30.0, 2, path=path)
 
 
 def test_edge_cases(orc):

@@ -24,6 +24,8 @@ def brute_edges(strings, lists, rel):
             continue
         if rel == 0:
             r = np.allclose(mats[a] @ mats[b] + mats[b] @ mats[a], 0)
+        elif rel == 2:
+            r = np.allclose(mats[a] @ mats[b] - mats[b] @ mats[a], 0)
         else:
             r = not all(np.allclose(SIGMA[s] @ SIGMA[t], SIGMA[t] @ SIGMA[s]) for s, t in zip(strings[a], strings[b]))
         if r:
@@ -31,7 +33,7 @@ def brute_edges(strings, lists, rel):
     return np.array(out, dtype=np.int32).reshape(-1, 2)
 
 
-@pytest.mark.parametrize("rel", [0, 1])
+@pytest.mark.parametrize("rel", [0, 1, 2])
 @pytest.mark.parametrize("seed", [0, 1])
 def test_tiny_vs_brute_force(orc, rel, seed):
     q, n = 3, 36
@@ -50,7 +52,7 @@ def test_tiny_vs_brute_force(orc, rel, seed):
     assert tests == int((counts * (counts - 1) // 2).sum())
 
 
-@pytest.mark.parametrize("rel", [0, 1])
+@pytest.mark.parametrize("rel", [0, 1, 2])
 @pytest.mark.parametrize("n,q,P,T,probs", [
     (1200, 16, 150, 14, (0.25, 0.25, 0.25, 0.25)),
     (900, 70, 40, 12, (0.7, 0.1, 0.1, 0.1)),
@@ -69,7 +71,7 @@ def test_bucketed_equals_allpairs(orc, rel, n, q, P, T, probs):
     assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("rel", [0, 1])
+@pytest.mark.parametrize("rel", [0, 1, 2])
 def test_full_lists_give_relation_graph(orc, rel):
     # T = P: every pair shares the whole palette, so E_c = relation edges
     q, n, P = 10, 300, 4
@@ -91,6 +93,8 @@ def rho(probs, q, rel):
     p = sum(nonI[a] * nonI[b] for a in nonI for b in nonI if a != b)
     if rel == 0:
         return (1 - (1 - 2 * p) ** q) / 2
+    if rel == 2:  # commute: an even number of anticommuting positions
+        return (1 + (1 - 2 * p) ** q) / 2
     return 1 - (1 - p) ** q
 
 
@@ -98,6 +102,7 @@ def rho(probs, q, rel):
     (0, (0.25, 0.25, 0.25, 0.25), 16),
     (0, (0.7, 0.1, 0.1, 0.1), 48),
     (1, (0.85, 0.05, 0.05, 0.05), 48),  # q large enough that duplicate rejection is negligible
+    (2, (0.7, 0.1, 0.1, 0.1), 48),
 ])
 def test_expected_conflict_edges(orc, rel, probs, q):
     # E|E_c| = C(n,2) rho (1 - C(P-T,T)/C(P,T)) for i.i.d. positions

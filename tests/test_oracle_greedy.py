@@ -75,7 +75,7 @@ def iteration_of(stats, colour):
     raise AssertionError("colour outside every palette")
 
 
-@pytest.mark.parametrize("rel", [0, 1])
+@pytest.mark.parametrize("rel", [0, 1, 2])
 @pytest.mark.parametrize("n,q,probs,frac,alpha", [
     (400, 8, (0.25, 0.25, 0.25, 0.25), 0.125, 2.0),
     (600, 30, (0.7, 0.1, 0.1, 0.1), 0.05, 3.0),
@@ -109,7 +109,7 @@ def test_full_run_properties(orc, rel, n, q, probs, frac, alpha):
     assert col[v0] == orc.sample_list(7, 1, v0, st[0]["P"], st[0]["T"])[0]
 
 
-@pytest.mark.parametrize("rel", [0, 1])
+@pytest.mark.parametrize("rel", [0, 1, 2])
 def test_full_palette_is_textbook_greedy(orc, rel):
     # T = P = m >= Delta + 1: one iteration, and the list colouring is the
     # classical greedy colouring in the random order.
@@ -133,6 +133,55 @@ def test_complete_relation_needs_n_colours(orc, q):
     x, z = wl.majorana_strings(q)
     nc, col, st = orc.color(x, z, q, 1, 0.125, 2.0, 0)
     assert nc == 2 * q and len(np.unique(col)) == 2 * q
+
+
+@pytest.mark.parametrize("q", [4, 9, 33])
+def test_commute_relation_on_majorana_strings_is_empty(orc, q):
+    # the 2q Majorana strings pairwise anticommute: under COMMUTE no pair is
+    # an edge, so one iteration colours every string with its first list colour
+    x, z = wl.majorana_strings(q)
+    nc, col, st = orc.color(x, z, q, 4, 0.125, 2.0, 2)
+    assert len(st) == 1 and st[0]["edges"] == 0
+    P, T = st[0]["P"], st[0]["T"]
+    assert col.tolist() == [int(orc.sample_list(4, 1, v, P, T)[0]) for v in range(2 * q)]
+
+
+def test_commute_relation_on_iz_strings_is_complete(orc):
+    # strings over {I, Z} pairwise commute: under COMMUTE every pair is an
+    # edge and every string needs a colour of its own
+    n, q = 120, 12
+    x, z = wl.iz_strings(n, q, seed=9)
+    nc, col, st = orc.color(x, z, q, 2, 0.125, 2.0, 2)
+    assert nc == n and len(np.unique(col)) == n
+
+
+def test_commute_classes_pairwise_anticommute(orc):
+    # every colour class under COMMUTE is a set of mutually anticommuting
+    # strings, checked on the Pauli matrices themselves
+    from tests.test_oracle_relation import kron_string
+    q = 3
+    x, z = wl.pauli_strings(63, q, seed=4)  # all 63 non-identity strings
+    ch = orc.decode(x, z, q)
+    mats = [kron_string(bytes(r).decode()) for r in ch]
+    for cseed in range(3):
+        nc, col, _ = orc.color(x, z, q, cseed, 0.125, 2.0, 2)
+        for c in np.unique(col):
+            members = np.flatnonzero(col == c)
+            for a, b in itertools.combinations(members, 2):
+                assert np.allclose(mats[a] @ mats[b] + mats[b] @ mats[a], 0)
+
+
+def test_aggressive_preset_full_lists(orc):
+    # the paper's aggressive setting (palette 3% of |V|, list size 30 ln|V|)
+    # gives T = P at this size: every pair shares the palette, so the first
+    # iteration is the textbook greedy colouring over P colours
+    n, q = 400, 8
+    x, z = wl.pauli_strings(n, q, seed=12)
+    nc, col, st = orc.color(x, z, q, 1, 0.03, 30.0, 2)
+    assert st[0]["P"] == 12 and st[0]["T"] == 12
+    R = relation_matrix(orc, x, z, q, 2)
+    assert not np.any((col[:, None] == col[None, :]) & R)
+    assert np.all(col >= 0)
 
 
 def test_empty_relation_single_iteration(orc):
@@ -173,7 +222,7 @@ def chromatic_number(R):
 def test_chromatic_lower_bound_small(orc, seed):
     n, q = 11, 4
     x, z = wl.pauli_strings(n, q, seed=seed)
-    for rel in (0, 1):
+    for rel in (0, 1, 2):
         R = relation_matrix(orc, x, z, q, rel)
         chi = chromatic_number(R)
         for cseed in range(3):
@@ -199,7 +248,7 @@ def test_duplicates_accepted(orc):
     x, z = wl.pauli_strings(50, 6, seed=1)
     x2 = np.concatenate([x, x[:10]])
     z2 = np.concatenate([z, z[:10]])
-    for rel in (0, 1):
+    for rel in (0, 1, 2):
         nc, col, st = orc.color(x2, z2, 6, 2, 0.125, 2.0, rel)
         R = relation_matrix(orc, x2, z2, 6, rel)
         assert not np.any((col[:, None] == col[None, :]) & R)

@@ -82,6 +82,17 @@ def test_anticommute_all_pairs_vs_kronecker(orc, q):
             assert orc.relation_chars(a.encode(), b.encode(), 0) == anti
 
 
+@pytest.mark.parametrize("q", [1, 2, 3])
+def test_commute_all_pairs_vs_kronecker(orc, q):
+    # COMMUTE (the paper's own orientation): an edge iff the matrices commute
+    strings = ["".join(p) for p in itertools.product("IXYZ", repeat=q)]
+    mats = {s: kron_string(s) for s in strings}
+    for a in strings:
+        for b in strings:
+            A, B = mats[a], mats[b]
+            assert orc.relation_chars(a.encode(), b.encode(), 2) == np.allclose(A @ B - B @ A, 0)
+
+
 def test_anticommute_random_q4_vs_kronecker(orc):
     rng = np.random.default_rng(7)
     for _ in range(300):
