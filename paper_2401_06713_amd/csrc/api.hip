@@ -322,6 +322,9 @@ int64_t build_conflict_graph(picasso_ctx *h, const Batch &b, int64_t m, int64_t 
         if (mfma) {
             ra.mfma_max_members = mfma_member_cap(h->q, rel);
             if (h->mfma_cap >= 0 && h->mfma_cap < ra.mfma_max_members) ra.mfma_max_members = h->mfma_cap;
+            // no larger than the largest bucket: the kernel's LDS is sized by
+            // this bound, and a smaller one fits more workgroups per CU
+            ra.mfma_max_members = std::min<int64_t>(ra.mfma_max_members, std::max<int64_t>(bi.max_size, 1));
         }
         any_mfma |= mfma;
         if (mfma) launch_relate_mfma(ra, h->q, st);

@@ -417,7 +417,8 @@ void launch_relate_mfma(const RelateArgs &a, int32_t q, hipStream_t st)
     if (a.P <= 0) return;
     const int32_t qpad = (q + 15) / 16 * 16;
     const int32_t kbytes = a.relation == PICASSO_REL_QWC ? 4 * qpad : 2 * qpad;
-    const int64_t cap = mfma_member_cap(q, a.relation);
+    // member rows of the largest bucket this launch takes (at most the LDS cap)
+    const int64_t cap = std::min<int64_t>(mfma_member_cap(q, a.relation), std::max<int64_t>(a.mfma_max_members, 1));
     const size_t lds = (size_t)((cap + 31) / 32 * 32) * kbytes;
     const unsigned grid = grid_cap(a.P, 1 << 20);
     if (a.relation == PICASSO_REL_ANTICOMMUTE)
