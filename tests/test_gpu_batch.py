@@ -141,7 +141,7 @@ def test_batch_invalid_arguments():
         with pytest.raises(pk.PicassoError):
             h.color_batch([0, 0], [0.1, 1.5], [2.0, 2.0], [0, 0])  # palette fraction above 1
         with pytest.raises(pk.PicassoError):
-            h.color_batch([0, 0], [0.1, 0.1], [2.0, 2.0], [0, 2])  # unknown relation
+            h.color_batch([0, 0], [0.1, 0.1], [2.0, 2.0], [0, 3])  # unknown relation
 
 
 @pytest.mark.skipif(not os.path.exists(GOLDEN), reason="stored oracle results for the batch are not present")

@@ -23,7 +23,7 @@ def say(*a):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("rel", [0, 1])
+@pytest.mark.parametrize("rel", [0, 1, 2])
 @pytest.mark.parametrize("n,q,probs", [(3000, 40, (0.7, 0.1, 0.1, 0.1)), (1500, 130, (0.8, 0.2 / 3, 0.2 / 3, 0.2 / 3)),
                                        (1, 10, (0.5, 0.2, 0.2, 0.1))])
 def test_features_bit_exact(orc, rel, n, q, probs):
@@ -86,7 +86,7 @@ def test_adam_step_matches_fp64(orc):
     assert np.allclose(p1[sure], p[sure], atol=1e-5)
 
 
-@pytest.mark.parametrize("rel", [0, 1])
+@pytest.mark.parametrize("rel", [0, 1, 2])
 def test_learned_colouring_bit_exact(orc, rel):
     n, q = 4000, 48
     x, z = wl.pauli_strings(n, q, (0.7, 0.1, 0.1, 0.1), seed=11 + rel)
