@@ -24,26 +24,32 @@ MFMA_I8_PEAK_TOPS = 5000.0  # dense int8 MFMA, 5.0 POP/s
 HBM_PEAK_GBS = 8000.0
 
 
-# HBM bytes of the pair kernel's iteration-1 launch on the default workload,
-# from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; summary and commands
-# in profiles/pair_pass_c2_n200000_q48_counters.md), each scaled by what the
-# counter read for a 1 GiB device copy in the same runs.  Valid only for the
-# kernel source they were taken from (its SHA-256).
+# HBM bytes of the pair kernel's and the CSR fill's iteration-1 launches on
+# the default workload, from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE;
+# summary and commands in profiles/pair_and_fill_c2_n200000_q48_counters.md),
+# each scaled by what the counter read for a 1 GiB device copy in the same
+# runs.  Valid only for the kernel source they were taken from (its SHA-256).
 PAIR_TRAFFIC = {
     "workload": "C2 n=200000 q=48 pI=0.7",
     "path": "valu",
     "source": "paper_2401_06713_amd/csrc/relate.hip",
-    "sha256": "4b815f05c8c93ace88f28f30c59caa1a59e28ccf52c3ae237e00bc279199e50e",
-    "fetch_kib": 57593.875,
-    "fetch_scale": 1048576.0 / 524308.125,
-    "write_kib": 199404.1875,
+    "sha256": "a4eb31278c6673bdf4a234cbcec3ec625b313a2efa81133f8732b8622a2ac835",
+    "fetch_kib": 56653.5625,
+    "fetch_scale": 1048576.0 / 524308.5625,
+    "write_kib": 201274.6875,
     "write_scale": 1048576.0 / 1048576.0,
 }
 
-
-# The same two counter runs for the CSR fill kernel's iteration-1 launch
-# (edge compaction), valid for the source file of that kernel.
-FILL_TRAFFIC = None
+FILL_TRAFFIC = {
+    "workload": "C2 n=200000 q=48 pI=0.7",
+    "path": "valu",
+    "source": "paper_2401_06713_amd/csrc/pairs.hip",
+    "sha256": "b5a775ea1d384add96289e3e171f7c1fe3b71a0945432081158fd93f797870ca",
+    "fetch_kib": 485762.0625,
+    "fetch_scale": 1048576.0 / 524308.5625,
+    "write_kib": 2065046.21875,
+    "write_scale": 1048576.0 / 1048576.0,
+}
 
 
 def recorded_traffic(workload: str, path: str, rec):
