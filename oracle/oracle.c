@@ -17,9 +17,9 @@
  *                      Jordan-Wigner / {I,Z} special cases (tests).
  *   params          -- the list/palette sizes printed for the paper-scale
  *                      configurations (2 ln 2000 -> 16, 0.125*2000 -> 250).
- *   philox, sampler -- Philox4x32-10 values are parity unpinned (no published
- *                      known-answer vectors are available here); the sampler
- *                      is pinned by structure (T distinct sorted values in
+ *   philox          -- the generator's published known-answer vectors
+ *                      (Salmon et al., SC'11), stored as a test fixture.
+ *   sampler         -- pinned by structure (T distinct sorted values in
  *                      range, T = P gives the whole palette) and by statistics
  *                      (marginals T/P, pair-share probability, bucket pairs).
  *   conflict edges  -- brute force on tiny inputs, T = P special case, the

@@ -3,10 +3,11 @@
 Parameters (Alg. 1 estimate step, Table I, Sec. VII): the configuration sizes
 printed with the workloads fix the natural log and the ceilings.
 Lists (Sec. IV: T colours uniformly at random from the palette) are pinned
-by structure and by statistics; the Philox values themselves are parity
-unpinned (no published known-answer vectors are available here).
+by structure and by statistics; the Philox4x32-10 generator under them by its
+authors' published known-answer vectors (tests/golden/philox4x32_10_kat.txt).
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -131,3 +132,16 @@ def test_priorities_uniform_order(orc):
     assert len(counts) == 6
     chi2, pv = stats.chisquare(list(counts.values()))
     assert pv > 1e-4
+
+
+def test_philox_known_answer_vectors(orc):
+    """Philox4x32-10 against the known-answer vectors published with the
+    generator (Salmon et al., SC'11; Random123): counters and keys of all
+    zeros, all ones, and digits of pi."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "philox4x32_10_kat.txt")
+    rows = [line.split() for line in open(path) if line.strip() and not line.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        w = [int(t, 16) for t in r]
+        out = orc.philox4x32_10(np.array(w[:4], dtype=np.uint32), np.array(w[4:6], dtype=np.uint32))
+        assert [int(v) for v in out] == w[6:10]
