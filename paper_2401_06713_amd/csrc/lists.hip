@@ -129,13 +129,33 @@ __global__ void bucket_scatter_kernel(const uint32_t *__restrict__ lists, int64_
                                       const int64_t *__restrict__ bstart, uint32_t *__restrict__ bfill,
                                       uint32_t *__restrict__ bmem, uint8_t *__restrict__ bslot)
 {
+    // The position in the bucket comes back from an atomic add; eight of
+    // them are issued before the first result is used, so a thread waits
+    // for one atomic round trip per eight list entries, not per entry.
+    // (The order within a bucket is arbitrary: the sort that follows orders
+    // the members by their unique (priority, id) keys.)
+    constexpr int kGroup = 8;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < m; v += (int64_t)gridDim.x * blockDim.x) {
         const int64_t e0 = loff[v], T = loff[v + 1] - e0;
-        for (int64_t k = 0; k < T; ++k) {
-            const uint32_t c = lists[e0 + k];
-            const int64_t at = bstart[c] + atomicAdd(&bfill[c], 1u);
-            bmem[at] = (uint32_t)v;
-            bslot[at] = (uint8_t)k;
+        for (int64_t k0 = 0; k0 < T; k0 += kGroup) {
+            uint32_t c[kGroup], pos[kGroup];
+            int64_t base[kGroup];
+#pragma unroll
+            for (int j = 0; j < kGroup; ++j)
+                if (k0 + j < T) c[j] = lists[e0 + k0 + j];
+#pragma unroll
+            for (int j = 0; j < kGroup; ++j)
+                if (k0 + j < T) {
+                    base[j] = bstart[c[j]];
+                    pos[j] = atomicAdd(&bfill[c[j]], 1u);
+                }
+#pragma unroll
+            for (int j = 0; j < kGroup; ++j)
+                if (k0 + j < T) {
+                    const int64_t at = base[j] + pos[j];
+                    bmem[at] = (uint32_t)v;
+                    bslot[at] = (uint8_t)(k0 + j);
+                }
         }
     }
 }
