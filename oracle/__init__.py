@@ -87,6 +87,10 @@ def lib() -> ctypes.CDLL:
         L.orc_greedy_from_edges.restype = i32
         L.orc_color.argtypes = [i64, i32, p, p, u64, dbl, dbl, i32, i32, p, p, i32, p]
         L.orc_color.restype = i64
+        L.orc_color_dynamic.argtypes = [i64, i32, p, p, u64, dbl, dbl, i32, i32, p, p, i32, p]
+        L.orc_color_dynamic.restype = i64
+        L.orc_greedy_dynamic.argtypes = [i64, p, i32, p, i64, u64, u32, p, p]
+        L.orc_greedy_dynamic.restype = i64
         _lib = L
     return _lib
 
@@ -215,17 +219,33 @@ def greedy_from_edges(prio: np.ndarray, lists: np.ndarray, P: int, edges: np.nda
     return col
 
 
+def greedy_dynamic(lists: np.ndarray, edges: np.ndarray, seed: int, ell: int):
+    """Alg. 2 on a supplied graph.  Returns (colours[m] int32 with -1 for
+    vertices whose list emptied, order[m]: vertices in the order taken)."""
+    lists = np.ascontiguousarray(lists, dtype=np.uint32)
+    edges = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
+    m, T = lists.shape
+    col = np.zeros(max(m, 1), dtype=np.int32)
+    order = np.zeros(max(m, 1), dtype=np.int32)
+    rc = lib().orc_greedy_dynamic(m, _ptr(lists), T, _ptr(edges), edges.shape[0], seed, ell, _ptr(col), _ptr(order))
+    if rc < 0:
+        raise MemoryError("oracle: allocation failed")
+    return col[:m], order[:m]
+
+
 def color(x: np.ndarray, z: np.ndarray, q: int, seed: int, frac: float, alpha: float, rel: int,
-          fixed_T: int = 0, max_stats: int = 4096):
-    """Full Picasso iteration.  Returns (n_colors, colors[n] int32, stats list)."""
+          fixed_T: int = 0, max_stats: int = 4096, dynamic: bool = False):
+    """Full Picasso iteration.  Returns (n_colors, colors[n] int32, stats list).
+    dynamic: colour each conflict graph by Alg. 2 instead of the static
+    random order."""
     x = np.ascontiguousarray(x, dtype=np.uint64).reshape(-1, _words(q))
     z = np.ascontiguousarray(z, dtype=np.uint64).reshape(-1, _words(q))
     n = x.shape[0]
     out = np.zeros(max(n, 1), dtype=np.int32)
     stats = (IterStat * max_stats)()
     nit = ctypes.c_int32()
-    nc = lib().orc_color(n, q, _ptr(x), _ptr(z), seed, frac, alpha, rel, fixed_T, _ptr(out), stats, max_stats,
-                         ctypes.byref(nit))
+    fn = lib().orc_color_dynamic if dynamic else lib().orc_color
+    nc = fn(n, q, _ptr(x), _ptr(z), seed, frac, alpha, rel, fixed_T, _ptr(out), stats, max_stats, ctypes.byref(nit))
     if nc < 0:
         raise MemoryError("oracle: allocation failed")
     st = [

@@ -28,6 +28,9 @@
  *                      T = P, complete and empty relation graphs, chromatic
  *                      lower bound by subset DP for n <= 12.  Exact colour
  *                      values beyond these are parity unpinned by the paper.
+ *   dynamic colourer-- (Alg. 2) a pure-Python replay of its rules from the
+ *                      reported order and colours, uniform first choices,
+ *                      empty and complete graphs, full-run validity.
  *   schedule driver -- a constant schedule reproduces the fixed-parameter run.
  *   features        -- direct counts (weight), density 1 / 0 on complete and
  *                      empty relation graphs, closed-form density for i.i.d.
@@ -459,6 +462,108 @@ int32_t orc_greedy_from_edges(int64_t m, const uint64_t *prio, const uint32_t *l
 }
 
 /* ------------------------------------------------------------------------ */
+/* Dynamic-order list colouring (Alg. 2, Sec. IV-B): the vertex with the     */
+/* shortest remaining list goes next, and the colour it takes is removed     */
+/* from its uncoloured neighbours' lists.  A vertex whose list empties stays  */
+/* uncoloured for the next iteration.                                        */
+/* Readings where the algorithm leaves a choice open:                        */
+/*  - vertices sit in one array per remaining list size; the arrays start in */
+/*    ascending vertex order, a removal moves the array's last vertex into   */
+/*    the hole, and a vertex whose list shrinks is appended to its new array;*/
+/*  - step k (k = 0, 1, ...) draws r0 = H(seed; k, 0, ell, "DYNV") and picks  */
+/*    entry floor(r0 * count / 2^64) of the lowest non-empty array, then     */
+/*    r1 = H(seed; k, 1, ell, "DYNV") picks entry floor(r1 * size / 2^64) of */
+/*    that vertex's remaining list, kept in ascending colour order.          */
+/* ------------------------------------------------------------------------ */
+#define ORC_TAG_DYNV 0x44594E56u
+
+/* col[m] receives list colours or -1; order[m] (may be NULL) the vertices in
+ * the order they were taken (coloured or emptied), -1-terminated if fewer.
+ * Returns the number of coloured vertices, or -1 on allocation failure. */
+static int64_t greedy_dynamic_csr(int64_t m, const uint32_t *lists, int32_t T, const int64_t *rowptr,
+                                  const int32_t *adj, uint64_t seed, uint32_t ell, int32_t *col, int32_t *order)
+{
+    uint32_t *cl = (uint32_t *)malloc((size_t)(m * T > 0 ? m * T : 1) * sizeof(uint32_t));
+    int32_t *sz = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
+    int64_t *where = (int64_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+    int32_t *arr = (int32_t *)malloc((size_t)((T + 1) * (m > 0 ? m : 1)) * sizeof(int32_t));
+    int64_t *cnt = (int64_t *)calloc((size_t)(T + 1), sizeof(int64_t));
+    char *done = (char *)calloc((size_t)(m > 0 ? m : 1), 1);
+    if (!cl || !sz || !where || !arr || !cnt || !done) {
+        free(cl); free(sz); free(where); free(arr); free(cnt); free(done);
+        return -1;
+    }
+    memcpy(cl, lists, (size_t)(m * T) * sizeof(uint32_t));
+    for (int64_t v = 0; v < m; v++) {
+        col[v] = -1;
+        if (order) order[v] = -1;
+        sz[v] = T;
+        where[v] = cnt[T];
+        arr[(int64_t)T * m + cnt[T]++] = (int32_t)v;
+    }
+    int64_t taken = 0, colored = 0;
+    for (uint32_t step = 0; taken < m; step++) {
+        int32_t s = 1;
+        while (s <= T && cnt[s] == 0) s++;
+        if (s > T) break; /* every vertex is taken */
+        uint64_t r0 = orc_hash64(seed, step, 0, ell, ORC_TAG_DYNV);
+        int64_t at = (int64_t)mul_high64(r0, (uint64_t)cnt[s]);
+        int32_t v = arr[(int64_t)s * m + at];
+        /* remove v from its array */
+        int32_t last = arr[(int64_t)s * m + cnt[s] - 1];
+        arr[(int64_t)s * m + at] = last;
+        where[last] = at;
+        cnt[s]--;
+        done[v] = 1;
+        if (order) order[taken] = v;
+        taken++;
+        uint64_t r1 = orc_hash64(seed, step, 1, ell, ORC_TAG_DYNV);
+        uint32_t c = cl[v * T + (int64_t)mul_high64(r1, (uint64_t)sz[v])];
+        col[v] = (int32_t)c;
+        colored++;
+        for (int64_t e = rowptr[v]; e < rowptr[v + 1]; e++) {
+            int32_t u = adj[e];
+            if (done[u]) continue;
+            uint32_t *lu = cl + (int64_t)u * T;
+            int32_t k = 0;
+            while (k < sz[u] && lu[k] != c) k++;
+            if (k == sz[u]) continue; /* c is not (or no longer) in u's list */
+            for (int32_t j = k; j + 1 < sz[u]; j++) lu[j] = lu[j + 1];
+            /* move u from array sz[u] to array sz[u] - 1 (or take it out) */
+            int32_t su = sz[u];
+            int32_t lastu = arr[(int64_t)su * m + cnt[su] - 1];
+            arr[(int64_t)su * m + where[u]] = lastu;
+            where[lastu] = where[u];
+            cnt[su]--;
+            sz[u] = su - 1;
+            if (sz[u] == 0) {
+                done[u] = 1;
+                if (order) order[taken] = u;
+                taken++;
+            } else {
+                where[u] = cnt[sz[u]];
+                arr[(int64_t)sz[u] * m + cnt[sz[u]]++] = u;
+            }
+        }
+    }
+    free(cl); free(sz); free(where); free(arr); free(cnt); free(done);
+    return colored;
+}
+
+/* Exported: Alg. 2 on an edge list (for tests that supply their own graph). */
+int64_t orc_greedy_dynamic(int64_t m, const uint32_t *lists, int32_t T, const int32_t *uv, int64_t ne,
+                           uint64_t seed, uint32_t ell, int32_t *col, int32_t *order)
+{
+    int64_t *rowptr;
+    int32_t *adj;
+    if (build_csr(m, uv, ne, &rowptr, &adj)) return -1;
+    int64_t rc = greedy_dynamic_csr(m, lists, T, rowptr, adj, seed, ell, col, order);
+    free(rowptr);
+    free(adj);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
 /* The iteration (Alg. 1): estimate (P, T), draw lists, build the conflict    */
 /* graph, colour it, and recurse on the uncoloured vertices with a fresh      */
 /* palette.  Reading of the garbled palette indices: iteration ell uses the  */
@@ -471,9 +576,29 @@ typedef struct {
 /* Returns the number of distinct colours, or -1 on allocation failure.
  * out_colors[n] receives global colour ids.  stats (may be NULL) receives
  * up to max_stats per-iteration records; *n_iters the iteration count. */
+static int64_t color_driver(int64_t n, int32_t q, const uint64_t *x, const uint64_t *z, uint64_t seed,
+                            double frac, double alpha, int32_t rel, int32_t fixed_T, int32_t dynamic,
+                            int32_t *out_colors, orc_iter_stat *stats, int32_t max_stats, int32_t *n_iters);
+
 int64_t orc_color(int64_t n, int32_t q, const uint64_t *x, const uint64_t *z, uint64_t seed, double frac,
                   double alpha, int32_t rel, int32_t fixed_T, int32_t *out_colors, orc_iter_stat *stats,
                   int32_t max_stats, int32_t *n_iters)
+{
+    return color_driver(n, q, x, z, seed, frac, alpha, rel, fixed_T, 0, out_colors, stats, max_stats, n_iters);
+}
+
+/* Alg. 1 with the dynamic-order colourer of Alg. 2 in place of the static
+ * random order. */
+int64_t orc_color_dynamic(int64_t n, int32_t q, const uint64_t *x, const uint64_t *z, uint64_t seed, double frac,
+                          double alpha, int32_t rel, int32_t fixed_T, int32_t *out_colors, orc_iter_stat *stats,
+                          int32_t max_stats, int32_t *n_iters)
+{
+    return color_driver(n, q, x, z, seed, frac, alpha, rel, fixed_T, 1, out_colors, stats, max_stats, n_iters);
+}
+
+static int64_t color_driver(int64_t n, int32_t q, const uint64_t *x, const uint64_t *z, uint64_t seed,
+                            double frac, double alpha, int32_t rel, int32_t fixed_T, int32_t dynamic,
+                            int32_t *out_colors, orc_iter_stat *stats, int32_t max_stats, int32_t *n_iters)
 {
     char *chars = (char *)malloc((size_t)(n * q > 0 ? n * q : 1));
     int32_t *ids = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
@@ -506,7 +631,10 @@ int64_t orc_color(int64_t n, int32_t q, const uint64_t *x, const uint64_t *z, ui
         edge_buf eb = {0, 0, 0};
         int64_t tests = 0;
         int64_t ne = conflict_edges_by_colour(q, m, ids, chars, lists, T, P, rel, 0, P, &eb, &tests);
-        if (ne < 0 || orc_greedy_from_edges(m, prio, lists, T, P, eb.uv, ne, col)) {
+        int failed = ne < 0;
+        if (!failed && dynamic) failed = orc_greedy_dynamic(m, lists, T, eb.uv, ne, seed, ell, col, NULL) < 0;
+        else if (!failed) failed = orc_greedy_from_edges(m, prio, lists, T, P, eb.uv, ne, col) != 0;
+        if (failed) {
             free(eb.uv); free(lists); free(prio); free(col); free(used); free(chars); free(ids);
             return -1;
         }
