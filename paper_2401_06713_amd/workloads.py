@@ -153,6 +153,9 @@ C1 = Config("C1 n=2000 q=16 uniform", 2000, 16, (0.25, 0.25, 0.25, 0.25), 0, 0.1
 C2 = Config("C2 n=200000 q=48 pI=0.7", 200_000, 48, (0.7, 0.1, 0.1, 0.1), 0, 0.125, 2.0, 0)
 C4 = Config("C4 n=2000000 q=128 pI=0.8", 2_000_000, 128, (0.8, 0.2 / 3, 0.2 / 3, 0.2 / 3), 0, 0.125, 2.0, 0)
 LHELD_PROBS = (0.75, 0.25 / 3, 0.25 / 3, 0.25 / 3)
+# The first held-out instance of the learned-parameter evaluation (generator
+# and colouring seed 7,000,000), at the fixed parameters.
+LHELD0 = Config("L-held[0] n=500000 q=96 pI=0.75", 500_000, 96, LHELD_PROBS, 7_000_000, 0.125, 2.0, 0)
 
 
 def make(cfg: Config):

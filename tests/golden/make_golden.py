@@ -5,6 +5,7 @@ HIP path is never involved.  Each JSON file holds the colour count, the
 SHA-256 of the little-endian int32 colour array and the per-iteration sizes.
 
     python tests/golden/make_golden.py C2 [seed ...]
+    python tests/golden/make_golden.py L 7000000     # the first held-out instance
     python tests/golden/make_golden.py C3 [workers]   # the 512-instance batch
 """
 import hashlib
@@ -21,7 +22,7 @@ import numpy as np  # noqa: E402
 import oracle  # noqa: E402
 from paper_2401_06713_amd import workloads as wl  # noqa: E402
 
-CONFIGS = {"C1": wl.C1, "C2": wl.C2, "C4": wl.C4}
+CONFIGS = {"C1": wl.C1, "C2": wl.C2, "C4": wl.C4, "L": wl.LHELD0}
 
 
 def _batch_one(i):

@@ -1,7 +1,8 @@
 """Full-size workloads on the HIP path.
 
-C2 (n=200,000, q=48): bit-exact against stored oracle results written by
-tests/golden/make_golden.py (which calls only the CPU oracle), plus
+C2 (n=200,000, q=48) and the first held-out instance of the learned
+evaluation (n=500,000, q=96): bit-exact against stored oracle results written
+by tests/golden/make_golden.py (which calls only the CPU oracle), plus
 properties that hold at any size: every colour class is independent in the
 relation graph, colours lie in their iteration's palette, and each
 iteration's sizes match.
@@ -96,6 +97,28 @@ def test_c2_matches_oracle(seed, path):
     if path != pk.PATH_AUTO:
         assert st["iters"][0]["pair_path"] == path
     check_valid(x, z, col, cfg.relation)
+
+
+def test_heldout_instance_matches_oracle():
+    """The first held-out instance of the learned-parameter evaluation
+    (n = 500,000, q = 96, pI = 0.75) at the fixed parameters, bit-exact
+    against the stored oracle result."""
+    gpath = os.path.join(GOLDEN, "l_seed7000000.json")
+    if not os.path.exists(gpath):
+        pytest.skip("no stored oracle result for the held-out instance")
+    g = json.load(open(gpath))
+    cfg = wl.LHELD0
+    say("held-out instance 0")
+    x, z = wl.make(cfg)
+    with pk.Picasso(x, z, cfg.q) as h:
+        nc, col = h.color(g["seed"], cfg.frac, cfg.alpha, cfg.relation)
+        st = h.stats()
+    assert nc == g["n_colors"]
+    assert hashlib.sha256(np.ascontiguousarray(col, dtype="<i4").tobytes()).hexdigest() == g["colors_sha256"]
+    assert st["n_iters"] == len(g["iters"])
+    for a, b in zip(st["iters"], g["iters"]):
+        for k in ("m", "P", "T", "pair_tests", "edges", "colored", "offset"):
+            assert a[k] == b[k], (k, a[k], b[k])
 
 
 def test_c4_full_size_properties_and_samples(orc):
