@@ -67,6 +67,29 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def host_info() -> dict:
+    """The host the CPU baseline ran on: CPU model, logical CPUs, memory."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    ram = None
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal:"):
+                    ram = round(int(line.split()[1]) / 2**20, 1)  # GiB
+                    break
+    except OSError:
+        pass
+    return {"cpu": model, "logical_cpus": os.cpu_count(), "ram_gib": ram}
+
+
 def cpu_baseline(cfg, x, z, budget_s: float):
     """The oracle's conflict-graph build on a slice of iteration 1's colour
     buckets (single thread), scaled to pair tests per second."""
@@ -94,6 +117,7 @@ def cpu_baseline(cfg, x, z, budget_s: float):
         "value": tests / dt,
         "unit": "pair-tests/s",
         "cores": 1,
+        "host": host_info(),
         "kind": "oracle",
         "sample": f"{cfg.name}: iteration-1 conflict build over colour buckets [0,{hi}) of {P} "
                   f"({tests} pair tests, {edges} edges, {dt:.1f} s, single-threaded C oracle)",

@@ -44,3 +44,4 @@ def test_cpu_baseline_leg_on_a_small_sample():
     assert out["kind"] == "oracle" and out["cores"] == 1 and out["unit"] == "pair-tests/s"
     assert np.isfinite(out["value"]) and out["value"] > 0
     assert cfg.name in out["sample"]
+    assert set(out["host"]) == {"cpu", "logical_cpus", "ram_gib"} and out["host"]["logical_cpus"] >= 1
