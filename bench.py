@@ -289,6 +289,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "median_call_ms": sorted(s["ms_total"] for s in per_step)[len(per_step) // 2],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
