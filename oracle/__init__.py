@@ -280,6 +280,14 @@ def _bind_extra():
     L.orc_mlp_loss_grad.restype = dbl
     L.orc_adam_step.argtypes = [p, p, p, p, i32, dbl, dbl, dbl, dbl, i32]
     L.orc_adam_step.restype = None
+    L.orc_count_conflict_edges.argtypes = [i32, i64, p, p, p, i32, i64, i32, i64, i64, p]
+    L.orc_count_conflict_edges.restype = i64
+    L.orc_greedy_by_classes.argtypes = [i32, i64, p, p, p, i32, i64, p, i32, p]
+    L.orc_greedy_by_classes.restype = i32
+    L.orc_color_classes.argtypes = [i64, i32, p, p, u64, p, p, i32, i32, i32, i32, p, p, i32, p]
+    L.orc_color_classes.restype = i64
+    L.orc_color_learned.argtypes = [i64, i32, p, p, u64, p, i32, i32, p, p, i32, p, p, i32]
+    L.orc_color_learned.restype = i64
     L._extra_bound = True
     return L
 
@@ -352,3 +360,85 @@ def adam_step(params, grad, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         assert a.dtype == np.float64 and a.flags.c_contiguous
     g = np.ascontiguousarray(grad, dtype=np.float64)
     L.orc_adam_step(_ptr(params), _ptr(g), _ptr(m), _ptr(v), step, lr, b1, b2, eps, params.shape[0])
+
+
+# ---- runs without a stored conflict graph -----------------------------------
+
+def _stats_list(stats, nit, max_stats):
+    return [dict(m=s.m, P=s.P, T=s.T, pair_tests=s.pair_tests, edges=s.edges, colored=s.colored, offset=s.offset)
+            for s in stats[: min(nit, max_stats)]]
+
+
+def count_conflict_edges(chars, ids, lists, P: int, rel: int, c_lo: int = 0, c_hi: int | None = None):
+    """|E_c| over the colour slice [c_lo, c_hi) without storing edges.
+    Returns (count, pair_tests)."""
+    L = _bind_extra()
+    chars = np.ascontiguousarray(chars, dtype=np.uint8)
+    ids = np.ascontiguousarray(ids, dtype=np.int32)
+    lists = np.ascontiguousarray(lists, dtype=np.uint32)
+    q = chars.shape[1]
+    m, T = lists.shape
+    tests = ctypes.c_int64()
+    cnt = L.orc_count_conflict_edges(q, m, _ptr(ids), _ptr(chars), _ptr(lists), T, P, rel, c_lo,
+                                     P if c_hi is None else c_hi, ctypes.byref(tests))
+    if cnt < 0:
+        raise MemoryError("oracle: allocation failed")
+    return int(cnt), tests.value
+
+
+def greedy_by_classes(chars, ids, lists, P: int, prio, rel: int) -> np.ndarray:
+    """Static-order greedy of one iteration from the colour classes and the
+    relation (no conflict graph)."""
+    L = _bind_extra()
+    chars = np.ascontiguousarray(chars, dtype=np.uint8)
+    ids = np.ascontiguousarray(ids, dtype=np.int32)
+    lists = np.ascontiguousarray(lists, dtype=np.uint32)
+    prio = np.ascontiguousarray(prio, dtype=np.uint64)
+    m, T = lists.shape
+    col = np.zeros(max(m, 1), dtype=np.int32)
+    if L.orc_greedy_by_classes(chars.shape[1], m, _ptr(ids), _ptr(chars), _ptr(lists), T, P, _ptr(prio), rel,
+                               _ptr(col)):
+        raise MemoryError("oracle: allocation failed")
+    return col[:m]
+
+
+def color_classes(x, z, q, seed, fracs, alphas, rel, fixed_T: int = 0, count_edges: bool = True,
+                  max_stats: int = 4096):
+    """Alg. 1 colouring each iteration from its colour classes (no stored
+    conflict graph).  fracs/alphas: one value each (fixed parameters) or a
+    per-iteration schedule.  Without count_edges the stats' edges are -1."""
+    L = _bind_extra()
+    x = np.ascontiguousarray(x, dtype=np.uint64).reshape(-1, _words(q))
+    z = np.ascontiguousarray(z, dtype=np.uint64).reshape(-1, _words(q))
+    n = x.shape[0]
+    fr = np.ascontiguousarray(np.atleast_1d(fracs), dtype=np.float64)
+    al = np.ascontiguousarray(np.atleast_1d(alphas), dtype=np.float64)
+    out = np.zeros(max(n, 1), dtype=np.int32)
+    stats = (IterStat * max_stats)()
+    nit = ctypes.c_int32()
+    nc = L.orc_color_classes(n, q, _ptr(x), _ptr(z), seed, _ptr(fr), _ptr(al), len(fr), rel, fixed_T,
+                             int(count_edges), _ptr(out), stats, max_stats, ctypes.byref(nit))
+    if nc < 0:
+        raise MemoryError("oracle: allocation failed")
+    return int(nc), out[:n], _stats_list(stats, nit.value, max_stats)
+
+
+def color_learned(x, z, q, seed, params, rel, count_edges: bool = True, max_stats: int = 4096):
+    """Alg. 1 with each iteration's (f, alpha) from the FP64 predictor twin.
+    Returns (n_colors, colors, stats, schedule (iterations x 2 float64))."""
+    L = _bind_extra()
+    x = np.ascontiguousarray(x, dtype=np.uint64).reshape(-1, _words(q))
+    z = np.ascontiguousarray(z, dtype=np.uint64).reshape(-1, _words(q))
+    n = x.shape[0]
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    assert params.shape == (mlp_nparams(),)
+    out = np.zeros(max(n, 1), dtype=np.int32)
+    stats = (IterStat * max_stats)()
+    sched = np.zeros((max_stats, 2), dtype=np.float64)
+    nit = ctypes.c_int32()
+    nc = L.orc_color_learned(n, q, _ptr(x), _ptr(z), seed, _ptr(params), rel, int(count_edges), _ptr(out), stats,
+                             max_stats, ctypes.byref(nit), _ptr(sched), max_stats)
+    if nc < 0:
+        raise MemoryError("oracle: allocation failed")
+    k = min(nit.value, max_stats)
+    return int(nc), out[:n], _stats_list(stats, nit.value, max_stats), sched[:k].copy()

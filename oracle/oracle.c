@@ -302,7 +302,8 @@ int64_t orc_conflict_edges_allpairs(int32_t q, int64_t m, const int32_t *ids, co
  * c are the only candidates that conflict through c, and a pair sharing
  * several colours is recorded once, at the smallest shared colour.  Only
  * colours in [c_lo, c_hi) are visited (the whole palette by default), which
- * lets a caller time a bounded slice.  Edges are returned sorted.
+ * lets a caller time a bounded slice.  Edges are returned sorted; with
+ * eb == NULL they are only counted.
  * *pair_tests receives sum over visited colours of C(|B_c|, 2). */
 static int64_t conflict_edges_by_colour(int32_t q, int64_t m, const int32_t *ids, const char *chars,
                                         const uint32_t *lists, int32_t T, int64_t P, int32_t rel,
@@ -324,7 +325,7 @@ static int64_t conflict_edges_by_colour(int32_t q, int64_t m, const int32_t *ids
             members[start[c] + fill[c]++] = (int32_t)a;
         }
     free(fill);
-    int64_t tests = 0;
+    int64_t tests = 0, counted = 0;
     if (c_lo < 0) c_lo = 0;
     if (c_hi > P) c_hi = P;
     for (int64_t c = c_lo; c < c_hi; c++) {
@@ -336,6 +337,10 @@ static int64_t conflict_edges_by_colour(int32_t q, int64_t m, const int32_t *ids
                 if (!orc_relation_chars(q, chars + (int64_t)ids[a] * q, chars + (int64_t)ids[b] * q, rel))
                     continue;
                 if (min_shared(lists + (int64_t)a * T, lists + (int64_t)b * T, T) != (uint32_t)c) continue;
+                if (!eb) {
+                    counted++;
+                    continue;
+                }
                 if (edge_push(eb, a, b)) {
                     free(start); free(members);
                     return -1;
@@ -344,8 +349,9 @@ static int64_t conflict_edges_by_colour(int32_t q, int64_t m, const int32_t *ids
     }
     free(start);
     free(members);
-    qsort(eb->uv, (size_t)eb->count, 2 * sizeof(int32_t), cmp_edge);
     if (pair_tests) *pair_tests = tests;
+    if (!eb) return counted;
+    qsort(eb->uv, (size_t)eb->count, 2 * sizeof(int32_t), cmp_edge);
     return eb->count;
 }
 
@@ -364,6 +370,15 @@ int64_t orc_conflict_edges_bucketed(int32_t q, int64_t m, const int32_t *ids, co
     }
     free(eb.uv);
     return cnt;
+}
+
+/* Exported: |E_c| over the colour slice [c_lo, c_hi) without storing any
+ * edge (the same enumeration, counting only). */
+int64_t orc_count_conflict_edges(int32_t q, int64_t m, const int32_t *ids, const char *chars,
+                                 const uint32_t *lists, int32_t T, int64_t P, int32_t rel, int64_t c_lo,
+                                 int64_t c_hi, int64_t *pair_tests)
+{
+    return conflict_edges_by_colour(q, m, ids, chars, lists, T, P, rel, c_lo, c_hi, NULL, pair_tests);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -459,6 +474,53 @@ int32_t orc_greedy_from_edges(int64_t m, const uint64_t *prio, const uint32_t *l
     free(rowptr);
     free(adj);
     return rc;
+}
+
+/* The same static-order greedy without the conflict graph.  When v's turn
+ * comes, colour c of its list is forbidden exactly when an earlier vertex u
+ * with {u, v} in E_c already holds c.  Such a u took c from its own list, so
+ * c lies in both lists and the pair is in E_c iff the relation holds.  Hence
+ * c is forbidden iff some vertex already coloured c (all of them come
+ * earlier) is related to v: the test needs the colour classes built so far
+ * and the relation, nothing else.  chars holds the decoded strings of all
+ * vertices, ids maps local index -> original id, prio[m] the priorities.
+ * col[m] receives palette colours or -1.  Returns 0, or -1 on allocation
+ * failure. */
+int32_t orc_greedy_by_classes(int32_t q, int64_t m, const int32_t *ids, const char *chars, const uint32_t *lists,
+                              int32_t T, int64_t P, const uint64_t *prio, int32_t rel, int32_t *col)
+{
+    int64_t *order = (int64_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+    int64_t *head = (int64_t *)malloc((size_t)(P > 0 ? P : 1) * sizeof(int64_t));
+    int64_t *next = (int64_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+    if (!order || !head || !next) {
+        free(order); free(head); free(next);
+        return -1;
+    }
+    for (int64_t i = 0; i < m; i++) order[i] = i;
+    g_sort_prio = prio;
+    qsort(order, (size_t)m, sizeof(int64_t), cmp_order);
+    for (int64_t c = 0; c < P; c++) head[c] = -1; /* class of c: a linked list of its vertices */
+    for (int64_t i = 0; i < m; i++) col[i] = -1;
+    for (int64_t r = 0; r < m; r++) {
+        int64_t v = order[r];
+        const char *sv = chars + (int64_t)ids[v] * q;
+        for (int k = 0; k < T; k++) {
+            uint32_t c = lists[v * T + k];
+            int forbidden = 0;
+            for (int64_t u = head[c]; u >= 0 && !forbidden; u = next[u])
+                forbidden = orc_relation_chars(q, chars + (int64_t)ids[u] * q, sv, rel);
+            if (!forbidden) {
+                col[v] = (int32_t)c;
+                next[v] = head[c];
+                head[c] = v;
+                break;
+            }
+        }
+    }
+    free(order);
+    free(head);
+    free(next);
+    return 0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -747,6 +809,120 @@ int64_t orc_color_schedule(int64_t n, int32_t q, const uint64_t *x, const uint64
 }
 
 /* ------------------------------------------------------------------------ */
+/* Alg. 1 without storing any conflict graph: each iteration colours by the  */
+/* colour classes (orc_greedy_by_classes), so memory stays O(n q + m T) and  */
+/* the largest workloads fit a host.  Iteration ell uses (fracs[ell-1],      */
+/* alphas[ell-1]), the last entry after the end (n_sched = 1: fixed          */
+/* parameters).  With count_edges = 0 the per-iteration |E_c| is not counted */
+/* (stats carry -1); otherwise it is counted colour by colour, as above.    */
+/* ------------------------------------------------------------------------ */
+static int32_t learned_params(const double *mlp, const char *chars, int32_t q, int64_t m, const int32_t *ids,
+                              uint64_t seed, uint32_t ell, int32_t rel, double *frac, double *alpha);
+
+static int64_t classes_driver(int64_t n, int32_t q, const uint64_t *x, const uint64_t *z, uint64_t seed,
+                              const double *fracs, const double *alphas, int32_t n_sched, const double *mlp,
+                              int32_t rel, int32_t fixed_T, int32_t count_edges, int32_t *out_colors,
+                              orc_iter_stat *stats, int32_t max_stats, int32_t *n_iters, double *sched,
+                              int32_t max_sched)
+{
+    char *chars = (char *)malloc((size_t)(n * q > 0 ? n * q : 1));
+    int32_t *ids = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    if (!chars || !ids) {
+        free(chars); free(ids);
+        return -1;
+    }
+    orc_decode(n, q, x, z, chars);
+    for (int64_t i = 0; i < n; i++) {
+        ids[i] = (int32_t)i;
+        out_colors[i] = -1;
+    }
+    int64_t m = n, offset = 0, distinct = 0;
+    uint32_t ell = 1;
+    int32_t it = 0;
+    while (m > 0) {
+        double frac, alpha;
+        if (mlp) {
+            learned_params(mlp, chars, q, m, ids, seed, ell, rel, &frac, &alpha);
+        } else {
+            const int32_t si = (int32_t)ell - 1 < n_sched ? (int32_t)ell - 1 : n_sched - 1;
+            frac = fracs[si];
+            alpha = alphas[si];
+        }
+        if (sched && it < max_sched) {
+            sched[2 * it] = frac;
+            sched[2 * it + 1] = alpha;
+        }
+        int64_t P;
+        int32_t T;
+        orc_params(m, frac, alpha, fixed_T, &P, &T);
+        uint32_t *lists = (uint32_t *)malloc((size_t)(m * T) * sizeof(uint32_t));
+        uint64_t *prio = (uint64_t *)malloc((size_t)m * sizeof(uint64_t));
+        int32_t *col = (int32_t *)malloc((size_t)m * sizeof(int32_t));
+        char *used = (char *)calloc((size_t)P, 1);
+        if (!lists || !prio || !col || !used) {
+            free(lists); free(prio); free(col); free(used); free(chars); free(ids);
+            return -1;
+        }
+        orc_sample_lists(seed, ell, m, ids, P, T, lists);
+        for (int64_t i = 0; i < m; i++) prio[i] = orc_priority(seed, ell, (uint32_t)ids[i]);
+        int64_t ne = -1, tests = 0;
+        if (count_edges) {
+            ne = conflict_edges_by_colour(q, m, ids, chars, lists, T, P, rel, 0, P, NULL, &tests);
+        } else {
+            /* pair tests from the bucket sizes alone */
+            int64_t *cnt = (int64_t *)calloc((size_t)P, sizeof(int64_t));
+            if (cnt) {
+                for (int64_t e = 0; e < m * T; e++) cnt[lists[e]]++;
+                for (int64_t c = 0; c < P; c++) tests += cnt[c] * (cnt[c] - 1) / 2;
+            }
+            free(cnt);
+            if (!cnt) ne = -2;
+        }
+        if (ne == -2 || (count_edges && ne < 0) ||
+            orc_greedy_by_classes(q, m, ids, chars, lists, T, P, prio, rel, col)) {
+            free(lists); free(prio); free(col); free(used); free(chars); free(ids);
+            return -1;
+        }
+        int64_t next = 0, colored = 0;
+        for (int64_t i = 0; i < m; i++) {
+            if (col[i] >= 0) {
+                out_colors[ids[i]] = (int32_t)(offset + col[i]);
+                if (!used[col[i]]) {
+                    used[col[i]] = 1;
+                    distinct++;
+                }
+                colored++;
+            } else {
+                ids[next++] = ids[i];
+            }
+        }
+        if (stats && it < max_stats) {
+            orc_iter_stat s = {m, P, T, tests, ne, colored, offset};
+            stats[it] = s;
+        }
+        it++;
+        free(lists); free(prio); free(col); free(used);
+        offset += P;
+        m = next;
+        ell++;
+    }
+    if (n_iters) *n_iters = it;
+    free(chars);
+    free(ids);
+    return distinct;
+}
+
+int64_t orc_color_classes(int64_t n, int32_t q, const uint64_t *x, const uint64_t *z, uint64_t seed,
+                          const double *fracs, const double *alphas, int32_t n_sched, int32_t rel, int32_t fixed_T,
+                          int32_t count_edges, int32_t *out_colors, orc_iter_stat *stats, int32_t max_stats,
+                          int32_t *n_iters)
+{
+    if (n_sched < 1) return -1;
+    return classes_driver(n, q, x, z, seed, fracs, alphas, n_sched, NULL, rel, fixed_T, count_edges, out_colors,
+                          stats, max_stats, n_iters, NULL, 0);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Instance features for the parameter predictor (the paper's Sec. VI       */
 /* predicts (P', alpha) from the graph; here from five numbers per          */
 /* iteration):                                                              */
@@ -909,4 +1085,31 @@ void orc_adam_step(double *p, const double *g, double *m, double *v, int32_t ste
         v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
         p[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Alg. 1 with per-iteration parameters from the predictor (the FP64 twin): */
+/* each iteration computes the features of its vertex set, runs the network */
+/* and squashes its outputs to (f, alpha) in double, then proceeds as the   */
+/* fixed-parameter run does (Sec. VI uses a predictor's (P', alpha) the     */
+/* same way).  sched (may be NULL) receives the (f, alpha) of the first     */
+/* max_sched iterations.                                                    */
+/* ------------------------------------------------------------------------ */
+static int32_t learned_params(const double *mlp, const char *chars, int32_t q, int64_t m, const int32_t *ids,
+                              uint64_t seed, uint32_t ell, int32_t rel, double *frac, double *alpha)
+{
+    double feat[5], xin[ORC_IN], h1[ORC_H], h2[ORC_H], o[ORC_OUT];
+    orc_features(q, chars, m, ids, seed, ell, rel, 4096, feat);
+    mlp_row(mlp, feat, xin, h1, h2, o);
+    orc_mlp_squash(o, frac, alpha);
+    return 0;
+}
+
+int64_t orc_color_learned(int64_t n, int32_t q, const uint64_t *x, const uint64_t *z, uint64_t seed,
+                          const double *mlp, int32_t rel, int32_t count_edges, int32_t *out_colors,
+                          orc_iter_stat *stats, int32_t max_stats, int32_t *n_iters, double *sched, int32_t max_sched)
+{
+    if (!mlp) return -1;
+    return classes_driver(n, q, x, z, seed, NULL, NULL, 0, mlp, rel, 0, count_edges, out_colors, stats, max_stats,
+                          n_iters, sched, max_sched);
 }

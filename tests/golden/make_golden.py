@@ -7,6 +7,12 @@ SHA-256 of the little-endian int32 colour array and the per-iteration sizes.
     python tests/golden/make_golden.py C2 [seed ...]
     python tests/golden/make_golden.py L 7000000     # the first held-out instance
     python tests/golden/make_golden.py C3 [workers]   # the 512-instance batch
+    python tests/golden/make_golden.py C4 [workers]   # n = 2,000,000, q = 128, seed 0
+
+The C4 run colours each iteration from its colour classes (the oracle's
+edge-free mode: its conflict graph, 3.6e9 edges in iteration 1, does not fit
+a host), then counts each iteration's conflict edges colour slice by colour
+slice in worker processes.
 """
 import hashlib
 import json
@@ -66,10 +72,75 @@ def batch_main(workers):
     print(out, sum(r["n_colors"] for r in recs), flush=True)
 
 
+_SLICE = {}
+
+
+def _count_slice(bounds):
+    g = _SLICE
+    cnt, tests = oracle.count_conflict_edges(g["chars"], g["ids"], g["lists"], g["P"], g["rel"], *bounds)
+    return cnt, tests
+
+
+def c4_main(workers):
+    """Colours of the n = 2M workload (seed 0) and every iteration's sizes."""
+    import multiprocessing as mp
+
+    cfg = wl.C4
+    oracle.build(force=False)
+    x, z = wl.make(cfg)
+    seed = 0
+    t = time.time()
+    nc, col, st = oracle.color_classes(x, z, cfg.q, seed, cfg.frac, cfg.alpha, cfg.relation, count_edges=False)
+    t_color = time.time() - t
+    print(f"C4 colours: {nc} in {t_color:.0f} s, {len(st)} iterations", flush=True)
+    chars = oracle.decode(x, z, cfg.q)
+    t = time.time()
+    ctx = mp.get_context("fork")
+    for k, it in enumerate(st):
+        ell = k + 1
+        # iteration ell's vertex set: the vertices not coloured before it,
+        # i.e. whose colour id is at or above its palette offset
+        ids = np.nonzero(col >= it["offset"])[0].astype(np.int32)
+        assert ids.shape[0] == it["m"]
+        lists = oracle.sample_lists(seed, ell, ids, it["P"], it["T"])
+        _SLICE.update(chars=chars, ids=ids, lists=lists, P=it["P"], rel=cfg.relation)
+        nsl = max(1, min(8 * workers, it["P"]))
+        cuts = [it["P"] * j // nsl for j in range(nsl + 1)]
+        with ctx.Pool(workers) as pool:
+            parts = pool.map(_count_slice, list(zip(cuts[:-1], cuts[1:])))
+        it["edges"] = int(sum(c for c, _ in parts))
+        assert sum(tt for _, tt in parts) == it["pair_tests"]
+        print(f"  iteration {ell}: m={it['m']} edges={it['edges']} ({time.time() - t:.0f} s)", flush=True)
+    rec = {
+        "config": cfg.name,
+        "n": cfg.n,
+        "q": cfg.q,
+        "probs": list(cfg.probs),
+        "gen_seed": cfg.seed,
+        "seed": seed,
+        "frac": cfg.frac,
+        "alpha": cfg.alpha,
+        "relation": cfg.relation,
+        "n_colors": nc,
+        "colors_sha256": hashlib.sha256(np.ascontiguousarray(col, dtype="<i4").tobytes()).hexdigest(),
+        "colors_head": col[:32].tolist(),
+        "iters": st,
+        "oracle_seconds": round(t_color, 1),
+        "edge_count_seconds": round(time.time() - t, 1),
+        "method": "edge-free oracle colouring (colour classes); edges counted per colour slice",
+    }
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c4_seed0.json")
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(out, nc, flush=True)
+
+
 def main():
     name = sys.argv[1]
     if name == "C3":
         return batch_main(int(sys.argv[2]) if len(sys.argv) > 2 else 6)
+    if name == "C4":
+        return c4_main(int(sys.argv[2]) if len(sys.argv) > 2 else 6)
     seeds = [int(s) for s in sys.argv[2:]] or [0]
     cfg = CONFIGS[name]
     oracle.build(force=False)
