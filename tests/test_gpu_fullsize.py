@@ -7,11 +7,13 @@ properties that hold at any size: every colour class is independent in the
 relation graph, colours lie in their iteration's palette, and each
 iteration's sizes match.
 
-C4 (n=2,000,000, q=128): too large for a whole oracle run, so checked by
-properties at full size (validity of every colour class, iteration sizes
-from the parameter rule, both pair paths identical) and exactly at sampled
-vertices: iteration-1 degree and the sequential greedy choice, computed by
-the oracle from the vertex's bucket-mates.
+C4 (n=2,000,000, q=128): bit-exact against the oracle's whole run (its
+edge-free mode, which colours from the colour classes; every iteration's
+conflict-edge count comes from a count-only enumeration), plus properties at
+full size (validity of every colour class, iteration sizes from the
+parameter rule, both pair paths identical) and, at sampled vertices, the
+iteration-1 degree and the sequential greedy choice computed by the oracle
+from the vertex's bucket-mates.
 """
 import hashlib
 import json
@@ -114,6 +116,29 @@ def test_heldout_instance_matches_oracle():
         nc, col = h.color(g["seed"], cfg.frac, cfg.alpha, cfg.relation)
         st = h.stats()
     assert nc == g["n_colors"]
+    assert hashlib.sha256(np.ascontiguousarray(col, dtype="<i4").tobytes()).hexdigest() == g["colors_sha256"]
+    assert st["n_iters"] == len(g["iters"])
+    for a, b in zip(st["iters"], g["iters"]):
+        for k in ("m", "P", "T", "pair_tests", "edges", "colored", "offset"):
+            assert a[k] == b[k], (k, a[k], b[k])
+
+
+def test_c4_matches_oracle():
+    """n = 2,000,000, q = 128, seed 0: colour count, the SHA-256 of the colour
+    array and every iteration's sizes against the stored oracle run."""
+    gpath = os.path.join(GOLDEN, "c4_seed0.json")
+    if not os.path.exists(gpath):
+        pytest.skip("no stored oracle result for the n = 2,000,000 workload")
+    g = json.load(open(gpath))
+    cfg = wl.C4
+    say("C4 whole run against the oracle")
+    x, z = wl.make(cfg)
+    with pk.Picasso(x, z, cfg.q) as h:
+        nc, col = h.color(g["seed"], cfg.frac, cfg.alpha, cfg.relation)
+        st = h.stats()
+    say("C4", nc, "colours; oracle", g["n_colors"])
+    assert nc == g["n_colors"]
+    assert col[:32].tolist() == g["colors_head"]
     assert hashlib.sha256(np.ascontiguousarray(col, dtype="<i4").tobytes()).hexdigest() == g["colors_sha256"]
     assert st["n_iters"] == len(g["iters"])
     for a, b in zip(st["iters"], g["iters"]):
