@@ -129,7 +129,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="C2", choices=["C1", "C2", "C3", "C4"])
+    ap.add_argument("--config", default="C4", choices=["C1", "C2", "C3", "C4"])
     ap.add_argument("--path", default="valu", choices=["auto", "valu", "mfma"],
                     help="pair pass: popcount tile kernel (valu), int8 MFMA kernel with popcount for buckets "
                          "above its LDS cap (mfma), or the library's choice (auto)")
