@@ -256,7 +256,7 @@ def color(x: np.ndarray, z: np.ndarray, q: int, seed: int, frac: float, alpha: f
 
 
 # ---- parameter schedule, features, predictor twin ---------------------------
-MLP_IN, MLP_HIDDEN, MLP_OUT = 5, 64, 2
+MLP_IN, MLP_HIDDEN, MLP_OUT = 6, 64, 2
 FEATURE_PAIRS = 4096
 
 
@@ -286,7 +286,7 @@ def _bind_extra():
     L.orc_greedy_by_classes.restype = i32
     L.orc_color_classes.argtypes = [i64, i32, p, p, u64, p, p, i32, i32, i32, i32, p, p, i32, p]
     L.orc_color_classes.restype = i64
-    L.orc_color_learned.argtypes = [i64, i32, p, p, u64, p, i32, i32, p, p, i32, p, p, i32]
+    L.orc_color_learned.argtypes = [i64, i32, p, p, u64, p, dbl, i32, i32, p, p, i32, p, p, i32]
     L.orc_color_learned.restype = i64
     L._extra_bound = True
     return L
@@ -423,8 +423,9 @@ def color_classes(x, z, q, seed, fracs, alphas, rel, fixed_T: int = 0, count_edg
     return int(nc), out[:n], _stats_list(stats, nit.value, max_stats)
 
 
-def color_learned(x, z, q, seed, params, rel, count_edges: bool = True, max_stats: int = 4096):
-    """Alg. 1 with each iteration's (f, alpha) from the FP64 predictor twin.
+def color_learned(x, z, q, seed, params, rel, beta: float, count_edges: bool = True, max_stats: int = 4096):
+    """Alg. 1 with each iteration's (f, alpha) from the FP64 predictor twin
+    given the iteration's features and the trade-off weight beta.
     Returns (n_colors, colors, stats, schedule (iterations x 2 float64))."""
     L = _bind_extra()
     x = np.ascontiguousarray(x, dtype=np.uint64).reshape(-1, _words(q))
@@ -436,7 +437,7 @@ def color_learned(x, z, q, seed, params, rel, count_edges: bool = True, max_stat
     stats = (IterStat * max_stats)()
     sched = np.zeros((max_stats, 2), dtype=np.float64)
     nit = ctypes.c_int32()
-    nc = L.orc_color_learned(n, q, _ptr(x), _ptr(z), seed, _ptr(params), rel, int(count_edges), _ptr(out), stats,
+    nc = L.orc_color_learned(n, q, _ptr(x), _ptr(z), seed, _ptr(params), float(beta), rel, int(count_edges), _ptr(out), stats,
                              max_stats, ctypes.byref(nit), _ptr(sched), max_stats)
     if nc < 0:
         raise MemoryError("oracle: allocation failed")

@@ -816,12 +816,13 @@ int64_t orc_color_schedule(int64_t n, int32_t q, const uint64_t *x, const uint64
 /* parameters).  With count_edges = 0 the per-iteration |E_c| is not counted */
 /* (stats carry -1); otherwise it is counted colour by colour, as above.    */
 /* ------------------------------------------------------------------------ */
-static int32_t learned_params(const double *mlp, const char *chars, int32_t q, int64_t m, const int32_t *ids,
-                              uint64_t seed, uint32_t ell, int32_t rel, double *frac, double *alpha);
+static int32_t learned_params(const double *mlp, double beta, const char *chars, int32_t q, int64_t m,
+                              const int32_t *ids, uint64_t seed, uint32_t ell, int32_t rel, double *frac,
+                              double *alpha);
 
 static int64_t classes_driver(int64_t n, int32_t q, const uint64_t *x, const uint64_t *z, uint64_t seed,
                               const double *fracs, const double *alphas, int32_t n_sched, const double *mlp,
-                              int32_t rel, int32_t fixed_T, int32_t count_edges, int32_t *out_colors,
+                              double beta, int32_t rel, int32_t fixed_T, int32_t count_edges, int32_t *out_colors,
                               orc_iter_stat *stats, int32_t max_stats, int32_t *n_iters, double *sched,
                               int32_t max_sched)
 {
@@ -842,7 +843,7 @@ static int64_t classes_driver(int64_t n, int32_t q, const uint64_t *x, const uin
     while (m > 0) {
         double frac, alpha;
         if (mlp) {
-            learned_params(mlp, chars, q, m, ids, seed, ell, rel, &frac, &alpha);
+            learned_params(mlp, beta, chars, q, m, ids, seed, ell, rel, &frac, &alpha);
         } else {
             const int32_t si = (int32_t)ell - 1 < n_sched ? (int32_t)ell - 1 : n_sched - 1;
             frac = fracs[si];
@@ -918,7 +919,7 @@ int64_t orc_color_classes(int64_t n, int32_t q, const uint64_t *x, const uint64_
                           int32_t *n_iters)
 {
     if (n_sched < 1) return -1;
-    return classes_driver(n, q, x, z, seed, fracs, alphas, n_sched, NULL, rel, fixed_T, count_edges, out_colors,
+    return classes_driver(n, q, x, z, seed, fracs, alphas, n_sched, NULL, 0.0, rel, fixed_T, count_edges, out_colors,
                           stats, max_stats, n_iters, NULL, 0);
 }
 
@@ -971,18 +972,21 @@ void orc_features_bits(int64_t n, int32_t q, const uint64_t *x, const uint64_t *
 }
 
 /* ------------------------------------------------------------------------ */
-/* The parameter predictor: a 3-layer perceptron 5 -> 64 -> 64 -> 2 with    */
-/* ReLU hidden layers (FP64 twin of the GPU network).                       */
-/* Parameter vector layout (4674 values):                                   */
-/*   W1[64][5], b1[64], W2[64][64], b2[64], W3[2][64], b3[2]                */
+/* The parameter predictor: a 3-layer perceptron 6 -> 64 -> 64 -> 2 with    */
+/* ReLU hidden layers (FP64 twin of the GPU network).  Its inputs are the   */
+/* five features of the iteration's vertex set and the trade-off weight     */
+/* beta of the bi-objective (Sec. VI, Eq. 7: the regressor is given the     */
+/* graph and beta and predicts (P', alpha)).                                */
+/* Parameter vector layout (4738 values):                                   */
+/*   W1[64][6], b1[64], W2[64][64], b2[64], W3[2][64], b3[2]                */
 /* Inputs are scaled before the first layer:                                */
-/*   (ln m / 16, q / 128, weight / 128, density, ell / 16).                 */
+/*   (ln m / 16, q / 128, weight / 128, density, ell / 16, beta).           */
 /* Outputs o (2 values) map to parameters by                                */
 /*   f = 0.01 + 0.24 sigmoid(o0), alpha = 1 + 3 sigmoid(o1).                */
 /* Training loss over a batch of B rows: (1/(2B)) sum (o - t)^2.            */
 /* ------------------------------------------------------------------------ */
 #define ORC_H 64
-#define ORC_IN 5
+#define ORC_IN 6
 #define ORC_OUT 2
 #define ORC_NPARAM (ORC_H * ORC_IN + ORC_H + ORC_H * ORC_H + ORC_H + ORC_OUT * ORC_H + ORC_OUT)
 
@@ -995,6 +999,7 @@ static void mlp_scale(const double *raw, double *xin)
     xin[2] = raw[2] / 128.0;
     xin[3] = raw[3];
     xin[4] = raw[4] / 16.0;
+    xin[5] = raw[5];
 }
 
 /* Forward pass of one row; keeps the activations for the gradient. */
@@ -1095,21 +1100,23 @@ void orc_adam_step(double *p, const double *g, double *m, double *v, int32_t ste
 /* same way).  sched (may be NULL) receives the (f, alpha) of the first     */
 /* max_sched iterations.                                                    */
 /* ------------------------------------------------------------------------ */
-static int32_t learned_params(const double *mlp, const char *chars, int32_t q, int64_t m, const int32_t *ids,
-                              uint64_t seed, uint32_t ell, int32_t rel, double *frac, double *alpha)
+static int32_t learned_params(const double *mlp, double beta, const char *chars, int32_t q, int64_t m,
+                              const int32_t *ids, uint64_t seed, uint32_t ell, int32_t rel, double *frac,
+                              double *alpha)
 {
-    double feat[5], xin[ORC_IN], h1[ORC_H], h2[ORC_H], o[ORC_OUT];
+    double feat[ORC_IN], xin[ORC_IN], h1[ORC_H], h2[ORC_H], o[ORC_OUT];
     orc_features(q, chars, m, ids, seed, ell, rel, 4096, feat);
+    feat[5] = beta;
     mlp_row(mlp, feat, xin, h1, h2, o);
     orc_mlp_squash(o, frac, alpha);
     return 0;
 }
 
 int64_t orc_color_learned(int64_t n, int32_t q, const uint64_t *x, const uint64_t *z, uint64_t seed,
-                          const double *mlp, int32_t rel, int32_t count_edges, int32_t *out_colors,
+                          const double *mlp, double beta, int32_t rel, int32_t count_edges, int32_t *out_colors,
                           orc_iter_stat *stats, int32_t max_stats, int32_t *n_iters, double *sched, int32_t max_sched)
 {
     if (!mlp) return -1;
-    return classes_driver(n, q, x, z, seed, NULL, NULL, 0, mlp, rel, 0, count_edges, out_colors, stats, max_stats,
+    return classes_driver(n, q, x, z, seed, NULL, NULL, 0, mlp, beta, rel, 0, count_edges, out_colors, stats, max_stats,
                           n_iters, sched, max_sched);
 }

@@ -102,13 +102,14 @@ def test_learned_driver_uses_the_fp64_network(orc):
     x, z = _instance(3000, 32, (0.7, 0.1, 0.1, 0.1), 13)
     rng = np.random.default_rng(0)
     params = rng.normal(0, 0.3, orc.mlp_nparams())
-    nc, col, st, sched = orc.color_learned(x, z, 32, 5, params, 0)
+    beta = 0.3
+    nc, col, st, sched = orc.color_learned(x, z, 32, 5, params, 0, beta)
     assert sched.shape == (len(st), 2)
     n = x.shape[0]
     for k, s in enumerate(st):
         ids = np.nonzero(col >= s["offset"])[0].astype(np.int32)
         assert ids.shape[0] == s["m"]
-        feat = orc.features(x, z, 32, ids, 5, k + 1, 0)
+        feat = np.r_[orc.features(x, z, 32, ids, 5, k + 1, 0), beta]
         f, a = orc.mlp_squash(orc.mlp_forward(params, feat)[0])
         assert sched[k, 0] == f and sched[k, 1] == a
         assert (s["P"], s["T"]) == orc.params(s["m"], f, a)

@@ -1,7 +1,8 @@
 """Pins for the oracle's parameter predictor, features and schedule driver.
 
 The predictor stands in for the paper's regressor (Sec. VI); it maps five
-instance features to (palette fraction, list multiplier).  Pins: gradients
+instance features and the trade-off weight beta of Eq. 7 to (palette
+fraction, list multiplier).  Pins: gradients
 against central finite differences, the forward pass against the collapsed
 affine map when every ReLU is active, Adam's first step in closed form,
 feature values against direct counts and special cases.
@@ -26,24 +27,24 @@ def split(orc, p):
 
 
 def scaled(raw):
-    return raw / np.array([16.0, 128.0, 128.0, 1.0, 16.0])
+    return raw / np.array([16.0, 128.0, 128.0, 1.0, 16.0, 1.0])
 
 
 def test_param_count(orc):
-    assert orc.mlp_nparams() == 64 * 5 + 64 + 64 * 64 + 64 + 2 * 64 + 2
+    assert orc.mlp_nparams() == 64 * 6 + 64 + 64 * 64 + 64 + 2 * 64 + 2
 
 
 def test_forward_zero_weights_gives_bias(orc):
     p = np.zeros(orc.mlp_nparams())
     p[-2:] = [0.7, -1.3]
-    out = orc.mlp_forward(p, np.random.default_rng(0).random((5, 5)))
+    out = orc.mlp_forward(p, np.random.default_rng(0).random((5, 6)))
     assert np.allclose(out, [[0.7, -1.3]] * 5)
 
 
 def test_forward_matches_affine_map_when_all_units_active(orc):
     rng = np.random.default_rng(1)
     p = np.abs(rng.normal(0, 0.2, orc.mlp_nparams()))  # positive weights, positive inputs: every ReLU passes
-    raw = rng.random((7, 5)) * np.array([16, 128, 128, 1, 16])
+    raw = rng.random((7, 6)) * np.array([16, 128, 128, 1, 16, 1])
     W1, b1, W2, b2, W3, b3 = split(orc, p)
     expect = (W3 @ (W2 @ (W1 @ scaled(raw).T + b1[:, None]) + b2[:, None]) + b3[:, None]).T
     assert np.allclose(orc.mlp_forward(p, raw), expect, rtol=1e-12)
@@ -52,7 +53,7 @@ def test_forward_matches_affine_map_when_all_units_active(orc):
 def test_gradient_matches_finite_differences(orc):
     rng = np.random.default_rng(2)
     p = rand_params(orc, 3)
-    raw = rng.random((6, 5)) * np.array([16, 128, 60, 1, 8])
+    raw = rng.random((6, 6)) * np.array([16, 128, 60, 1, 8, 1])
     t = rng.normal(0, 1, (6, 2))
     _, g = orc.mlp_loss_grad(p, raw, t)
     idx = rng.choice(p.shape[0], 60, replace=False)
@@ -67,7 +68,7 @@ def test_gradient_matches_finite_differences(orc):
 
 def test_loss_value(orc):
     p = np.zeros(orc.mlp_nparams())
-    raw = np.ones((4, 5))
+    raw = np.ones((4, 6))
     t = np.array([[1.0, 2.0]] * 4)
     loss, _ = orc.mlp_loss_grad(p, raw, t)
     assert math.isclose(loss, 0.5 * (1 + 4))  # mean over rows of half squared error
