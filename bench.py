@@ -137,6 +137,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-fixed comparison")
+    ap.add_argument("--beta", type=float, default=0.3,
+                    help="trade-off input of the learned parameters (weight of the colour count)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the timed steps, copy MIB MiB device to device once (a plain copy of known size "
                          "that calibrates the HBM byte counters of a profiler run)")
@@ -312,18 +314,21 @@ def main():
     if seeds_nc:
         line["n_colors_seeds_0_4"] = {"n_colors": seeds_nc, "mean": sum(seeds_nc) / len(seeds_nc)}
     h.close()
-    if not batch and not args.no_learned and os.path.exists(learn.PREDICTOR):
+    params = np.load(learn.PREDICTOR) if os.path.exists(learn.PREDICTOR) else None
+    if params is not None and params.shape != (pk.MLP_NPARAMS,):
+        params = None  # stored for another network shape
+    if not batch and not args.no_learned and params is not None:
         # learned parameters (the stored network) against the fixed ones, each
         # on a fresh handle so that peak device bytes count only its own run
         log("bench: learned vs fixed parameters")
-        mlp = pk.Mlp(np.load(learn.PREDICTOR))
+        mlp = pk.Mlp(params)
         cmp = {}
         for name in ("fixed", "learned"):
             hh = pk.Picasso(xd, zd, cfg.q)
             hh.set_option(pk.OPT_PAIR_PATH, pk.PATH_VALU)
             hh.set_option(pk.OPT_TAIL, 0)  # the learned run consults the network every iteration
             run = (lambda: hh.color(args.seed, cfg.frac, cfg.alpha, cfg.relation)[0]) if name == "fixed" else \
-                (lambda: hh.color_learned(mlp, args.seed, cfg.relation)[0])
+                (lambda: hh.color_learned(mlp, args.seed, cfg.relation, args.beta)[0])
             run()
             torch.cuda.synchronize()
             t1 = time.perf_counter()

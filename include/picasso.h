@@ -85,13 +85,35 @@ enum {
                                    members take the MFMA kernel, larger ones the
                                    popcount tile kernel; -1 (default) = as many
                                    as the kernel's LDS rows hold for this q      */
-    PICASSO_OPT_TAIL = 9        /* 1 (default): an instance with at most 256
+    PICASSO_OPT_TAIL = 9,       /* 1 (default): an instance with at most 256
                                    vertices left (and lists within the kernel's
                                    LDS) finishes its iterations in one device
                                    workgroup; 0: every iteration takes the full
                                    path.  Results are identical.  Iterations
                                    run there report pair_path 0 and no times.  */
+    PICASSO_OPT_LEARNED_JUDGE = 10, /* picasso_color_learned: 1 = also colour with
+                                   the fixed parameters (f = 0.125, alpha = 2)
+                                   and return whichever result has fewer
+                                   colours (the network's on a tie); stats
+                                   record which (picasso_stats.judged) and the
+                                   time of both runs.  0 (default): the
+                                   network's result only.                     */
+    PICASSO_OPT_CSR_SIZING = 11 /* colouring calls: 1 (default) = each iteration's
+                                   CSR buffer is sized by the predicted bound on
+                                   |E_c| (picasso_iter_stats.edges_bound) and
+                                   filled without waiting for the exact size;
+                                   an iteration above the bound is filled again
+                                   at its exact size (picasso_stats.csr_refills).
+                                   0 = the exact size is read back before the
+                                   fill.  2 = the bound taken as zero, so every
+                                   iteration refills (tests that path).
+                                   Results are identical.                     */
 };
+
+/* picasso_stats.judged */
+#define PICASSO_JUDGE_NONE 0    /* no judge run                               */
+#define PICASSO_JUDGE_LEARNED 1 /* the network's colouring was kept          */
+#define PICASSO_JUDGE_FIXED 2   /* the fixed-parameter colouring was kept    */
 
 #define PICASSO_PATH_AUTO 0
 #define PICASSO_PATH_VALU 1
@@ -107,6 +129,10 @@ typedef struct {
     int64_t T;          /* list size                                          */
     int64_t pair_tests; /* sum over colours c of C(|B_c|, 2)                   */
     int64_t edges;      /* |E_c|, undirected conflict edges                    */
+    int64_t edges_bound; /* upper bound on |E_c| predicted before the pair pass
+                           from the sampled relation density (sizes the CSR;
+                           iterations run in the tail kernel count |E_c|
+                           exactly and report it here)                       */
     int64_t colored;    /* vertices coloured in this iteration                 */
     int64_t offset;     /* first global colour id of this iteration's palette
                            (single-instance handles; 0 for batches)           */
@@ -131,6 +157,9 @@ typedef struct {
     int64_t max_edges;     /* largest single-iteration |E_c|                   */
     int64_t peak_device_bytes;
     int32_t n_iters;
+    int32_t judged;  /* PICASSO_JUDGE_* (picasso_color_learned)           */
+    int32_t csr_refills; /* iterations whose |E_c| exceeded the predicted bound
+                            (their CSR was written again at the exact size) */
     int32_t reserved;
     double ms_total; /* wall time of the call                                */
     picasso_iter_stats iters[PICASSO_MAX_ITER_STATS];
@@ -263,7 +292,8 @@ int64_t picasso_list_color_csr(picasso_handle h, int64_t m, const uint64_t *prio
 
 typedef struct picasso_mlp_ctx *picasso_mlp;
 
-#define PICASSO_MLP_NPARAMS 4674 /* W1[64][5] b1[64] W2[64][64] b2[64] W3[2][64] b3[2] */
+#define PICASSO_MLP_NPARAMS 4738 /* W1[64][6] b1[64] W2[64][64] b2[64] W3[2][64] b3[2] */
+#define PICASSO_MLP_INPUTS 6      /* five features (picasso_features) and beta          */
 #define PICASSO_FEATURE_PAIRS 4096
 
 /* Features of an iteration's vertex set: out[5] = (ln m, q, mean Pauli
@@ -273,8 +303,10 @@ typedef struct picasso_mlp_ctx *picasso_mlp;
 int32_t picasso_features(picasso_handle h, uint64_t seed, int32_t ell, int64_t m, const int32_t *ids,
                          int32_t relation, double *out);
 
-/* A 5 -> 64 -> 64 -> 2 perceptron (ReLU hidden layers, FP32) on the device
- * of the calling thread.  params: host, PICASSO_MLP_NPARAMS floats in the
+/* A 6 -> 64 -> 64 -> 2 perceptron (ReLU hidden layers, FP32) whose inputs are an iteration's five features and the trade-off weight
+ * beta of the bi-objective beta * colours + (1 - beta) * |E_c| (Sec. VI,
+ * Eq. 7: the regressor predicts (P', alpha) for a given graph and beta), on
+ * the device of the calling thread.  params: host, PICASSO_MLP_NPARAMS floats in the
  * layout above, or NULL for a deterministic initialisation from seed
  * (scaled normal weights, zero biases).  Returns NULL on error. */
 picasso_mlp picasso_mlp_create(const float *params, uint64_t seed);
@@ -282,7 +314,8 @@ void picasso_mlp_destroy(picasso_mlp mlp);
 int32_t picasso_mlp_get_params(picasso_mlp mlp, float *out);      /* host, NPARAMS floats */
 int32_t picasso_mlp_set_params(picasso_mlp mlp, const float *in);  /* resets the Adam state */
 
-/* Raw outputs o (B x 2, host) for B feature rows (B x 5, host); the
+/* Raw outputs o (B x 2, host) for B input rows (B x 6, host: the five
+ * features of picasso_features, then beta); the
  * parameters are f = 0.01 + 0.24 sigmoid(o0), alpha = 1 + 3 sigmoid(o1). */
 int32_t picasso_mlp_forward(picasso_mlp mlp, const float *features, int32_t B, float *out);
 
@@ -297,11 +330,26 @@ int32_t picasso_mlp_train_step(picasso_mlp mlp, const float *features, const flo
                                float *loss);
 
 /* Colour with per-iteration parameters from the network: each iteration
- * computes its features on the device, runs the network, and uses the FP32
- * (f, alpha) it returns.  out_schedule (host, 2 * max_sched floats, may be
- * NULL) receives the (f, alpha) of the first max_sched iterations.  Returns
- * n_colors or an error. */
-int64_t picasso_color_learned(picasso_handle h, uint64_t seed, picasso_mlp mlp, int32_t relation,
+ * computes its features on the device, runs the network on them and beta
+ * (in [0, 1], the weight of the colour count in Eq. 7), and uses the FP32
+ * (f, alpha) it returns (Sec. VI: parameters predicted from the graph and
+ * beta).  Fallback: an iteration whose outputs are not finite or fall
+ * outside f in (0, 1], alpha > 0 uses the fixed parameters f = 0.125,
+ * alpha = 2 (the paper's evaluation default).  Judge: with
+ * PICASSO_OPT_LEARNED_JUDGE = 1 the fixed-parameter colouring runs as well
+ * and the result with fewer colours is returned.  out_schedule (host,
+ * 2 * max_sched floats, may be NULL) receives the network's (f, alpha) of
+ * the first max_sched iterations.  Returns n_colors or an error. */
+/* Colour with an explicit schedule of parameters (Alg. 1 with the
+ * per-iteration palette and list size chosen by the caller, as the learned
+ * predictor of Sec. VI chooses them): iteration l (from 1) uses
+ * palette_fracs[k] and list_sizes[k] with k = min(l, count) - 1, so the last
+ * entry repeats.  palette_fracs, list_sizes: host, count >= 1 entries, each
+ * valid as in picasso_color.  Output and errors as picasso_color. */
+int64_t picasso_color_schedule(picasso_handle h, uint64_t seed, const double *palette_fracs, const double *list_sizes,
+                               int32_t count, int32_t relation, int32_t *out_colors);
+
+int64_t picasso_color_learned(picasso_handle h, uint64_t seed, picasso_mlp mlp, double beta, int32_t relation,
                               int32_t *out_colors, float *out_schedule, int32_t max_sched);
 
 #ifdef __cplusplus

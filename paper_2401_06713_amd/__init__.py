@@ -21,7 +21,8 @@ REL_QWC = 1
 REL_COMMUTE = 2
 PATH_AUTO, PATH_VALU, PATH_MFMA = 0, 1, 2
 (OPT_MEM_BUDGET, OPT_PAIR_PATH, OPT_FIXED_T, OPT_STREAM, OPT_TIMING, OPT_JP_BATCH, OPT_GRAPH,
- OPT_MFMA_CAP, OPT_TAIL) = 1, 2, 3, 4, 5, 6, 7, 8, 9
+ OPT_MFMA_CAP, OPT_TAIL, OPT_LEARNED_JUDGE, OPT_CSR_SIZING) = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11
+JUDGE_NONE, JUDGE_LEARNED, JUDGE_FIXED = 0, 1, 2
 MAX_T = 256
 MAX_ITER_STATS = 256
 
@@ -52,9 +53,11 @@ EXPORTS = (
     "picasso_mlp_forward",
     "picasso_mlp_gradient",
     "picasso_mlp_train_step",
+    "picasso_color_schedule",
     "picasso_color_learned",
 )
-MLP_NPARAMS = 4674
+MLP_NPARAMS = 4738
+MLP_INPUTS = 6
 FEATURE_PAIRS = 4096
 
 
@@ -65,6 +68,7 @@ class IterStats(ctypes.Structure):
         ("T", ctypes.c_int64),
         ("pair_tests", ctypes.c_int64),
         ("edges", ctypes.c_int64),
+        ("edges_bound", ctypes.c_int64),
         ("colored", ctypes.c_int64),
         ("offset", ctypes.c_int64),
         ("pair_path", ctypes.c_int32),
@@ -88,6 +92,8 @@ class Stats(ctypes.Structure):
         ("max_edges", ctypes.c_int64),
         ("peak_device_bytes", ctypes.c_int64),
         ("n_iters", ctypes.c_int32),
+        ("judged", ctypes.c_int32),
+        ("csr_refills", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
         ("ms_total", ctypes.c_double),
         ("iters", IterStats * MAX_ITER_STATS),
@@ -190,8 +196,10 @@ def lib() -> ctypes.CDLL:
     L.picasso_mlp_gradient.argtypes = [p, p, p, i32, p, ctypes.POINTER(f32)]
     L.picasso_mlp_train_step.restype = i32
     L.picasso_mlp_train_step.argtypes = [p, p, p, i32, f32, ctypes.POINTER(f32)]
+    L.picasso_color_schedule.restype = i64
+    L.picasso_color_schedule.argtypes = [p, u64, p, p, i32, i32, p]
     L.picasso_color_learned.restype = i64
-    L.picasso_color_learned.argtypes = [p, u64, p, i32, p, p, i32]
+    L.picasso_color_learned.argtypes = [p, u64, p, dbl, i32, p, p, i32]
     _lib = L
     return L
 
@@ -324,13 +332,28 @@ class Picasso:
         _check(lib().picasso_features(self._h, seed, ell, ids.shape[0], _ptr(ids), relation, _ptr(out)))
         return out
 
-    def color_learned(self, mlp: "Mlp", seed: int = 0, relation: int = REL_ANTICOMMUTE, max_sched: int = 256):
-        """Colours with per-iteration (f, alpha) from the network.
+    def color_schedule(self, seed: int, palette_fracs, list_sizes, relation: int = REL_ANTICOMMUTE):
+        """Colours with iteration l using entry min(l, len) - 1 of the
+        schedule; returns (n_colors, colors int32[n])."""
+        fr = np.ascontiguousarray(np.atleast_1d(palette_fracs), dtype=np.float64)
+        al = np.ascontiguousarray(np.atleast_1d(list_sizes), dtype=np.float64)
+        if fr.shape != al.shape:
+            raise PicassoError(EINVAL, "schedule arrays differ in length")
+        out = np.empty(max(self.n, 1), dtype=np.int32)
+        nc = _check(lib().picasso_color_schedule(self._h, seed, _ptr(fr), _ptr(al), fr.shape[0], relation,
+                                                 _ptr(out)))
+        return nc, out[: self.n]
+
+    def color_learned(self, mlp: "Mlp", seed: int = 0, relation: int = REL_ANTICOMMUTE, beta: float = 0.5,
+                      max_sched: int = 256):
+        """Colours with per-iteration (f, alpha) from the network given the
+        iteration's features and beta.
 
         Returns (n_colors, colors, schedule) with schedule (iterations, 2) float32."""
         out = np.empty(max(self.n, 1), dtype=np.int32)
         sched = np.zeros((max_sched, 2), dtype=np.float32)
-        nc = _check(lib().picasso_color_learned(self._h, seed, mlp._m, relation, _ptr(out), _ptr(sched), max_sched))
+        nc = _check(lib().picasso_color_learned(self._h, seed, mlp._m, beta, relation, _ptr(out), _ptr(sched),
+                                                max_sched))
         n_it = min(self.stats()["n_iters"], max_sched)
         return nc, out[: self.n], sched[:n_it].copy()
 
@@ -441,13 +464,13 @@ class Mlp:
         _check(lib().picasso_mlp_set_params(self._m, _ptr(params)))
 
     def forward(self, feats) -> np.ndarray:
-        feats = np.ascontiguousarray(feats, dtype=np.float32).reshape(-1, 5)
+        feats = np.ascontiguousarray(feats, dtype=np.float32).reshape(-1, MLP_INPUTS)
         out = np.zeros((feats.shape[0], 2), dtype=np.float32)
         _check(lib().picasso_mlp_forward(self._m, _ptr(feats), feats.shape[0], _ptr(out)))
         return out
 
     def gradient(self, feats, target):
-        feats = np.ascontiguousarray(feats, dtype=np.float32).reshape(-1, 5)
+        feats = np.ascontiguousarray(feats, dtype=np.float32).reshape(-1, MLP_INPUTS)
         target = np.ascontiguousarray(target, dtype=np.float32).reshape(-1, 2)
         grad = np.zeros(MLP_NPARAMS, dtype=np.float32)
         loss = ctypes.c_float()
@@ -456,7 +479,7 @@ class Mlp:
         return loss.value, grad
 
     def train_step(self, feats, target, lr: float = 1e-3) -> float:
-        feats = np.ascontiguousarray(feats, dtype=np.float32).reshape(-1, 5)
+        feats = np.ascontiguousarray(feats, dtype=np.float32).reshape(-1, MLP_INPUTS)
         target = np.ascontiguousarray(target, dtype=np.float32).reshape(-1, 2)
         loss = ctypes.c_float()
         _check(lib().picasso_mlp_train_step(self._m, _ptr(feats), _ptr(target), feats.shape[0], lr,

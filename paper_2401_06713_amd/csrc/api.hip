@@ -78,13 +78,16 @@ struct picasso_ctx {
     int32_t use_graph = 1;   // replay colouring rounds from a captured graph
     int64_t mfma_cap = -1;   // largest bucket for the MFMA kernel (-1: as large as LDS allows)
     int32_t use_tail = 1;    // finish instances with few vertices left in the tail kernel
+    int32_t judge = 0;       // learned colouring: also run the fixed parameters, keep the better
+    int32_t csr_sizing = 1;  // colouring calls: 1 CSR sized by the predicted bound, 0 by the exact
+                             // size, 2 bound forced to zero (every iteration refills; for tests)
     Arena arena;
     DevBuf x, z, xz;  // bit-planes, and the interleaved copy the member gather reads
     // iteration buffers
     DevBuf ids, next_ids, lists, prio, bcnt, bstart, bmem, bslot, pos_of, bent, tmp_mem, tmp_slot, tiles, words, tile_off,
         rb_off, R, D, bx, bz, tile_bucket, nslow, slow, slot_cnt, slot_off, rowptr, adj, col, blk, fre, nblk, st,
-        dirty, wake_at, wl, flags, pos, used, scan_tmp, scalars, out_colors, inst, vinst, loff, binst, inst_out, tail_recs,
-        tail_table, tail_outs, tail_iters, tail_ranges;
+        dirty, wake_at, wl, flags, pos, used, scan_tmp, scalars, out_colors, judge_out, inst, vinst, loff, binst,
+        inst_out, tail_recs, tail_table, tail_outs, tail_iters, tail_ranges, hits, csr_flag;
     std::vector<InstRec> h_inst;  // table of the active instances (kept until the copy has completed)
     picasso_stats stats;
     std::vector<picasso_instance_stats> istats;
@@ -99,6 +102,10 @@ struct picasso_mlp_ctx {
 };
 
 namespace {
+
+// The fixed parameters of the paper's evaluation (palette 12.5% of the
+// vertices, alpha = 2): the learned colouring's fallback and judge.
+constexpr double kFixedFrac = 0.125, kFixedAlpha = 2.0;
 
 template <typename T>
 T *mbuf(picasso_mlp_ctx *c, DevBuf &b, size_t count)
@@ -218,7 +225,8 @@ struct BucketInfo {
 // of batch b, P colours): count, scan, scatter, sort by priority (h->prio),
 // the shapes of the per-bucket bit matrices and the bucket -> instance
 // table (b.binst is set).
-BucketInfo buckets_from_lists(picasso_ctx *h, Batch &b, int64_t m, int64_t E, int64_t P)
+BucketInfo buckets_from_lists(picasso_ctx *h, Batch &b, int64_t m, int64_t E, int64_t P,
+                              const uint32_t *d_hits = nullptr, uint32_t *h_hits = nullptr)
 {
     hipStream_t st = h->stream;
     const uint32_t *lists = static_cast<const uint32_t *>(h->lists.p);
@@ -253,6 +261,8 @@ BucketInfo buckets_from_lists(picasso_ctx *h, Batch &b, int64_t m, int64_t E, in
     PCHECK_HIP(hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, st));
     PCHECK_HIP(hipMemcpyAsync(&t2[0], tile_off + P, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     PCHECK_HIP(hipMemcpyAsync(&t2[1], rb_off + P, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    if (d_hits)
+        PCHECK_HIP(hipMemcpyAsync(h_hits, d_hits, sizeof(uint32_t) * (size_t)b.nb, hipMemcpyDeviceToHost, st));
     PCHECK_HIP(hipStreamSynchronize(st));
     BucketInfo bi;
     bi.pair_tests = (int64_t)hs[0];
@@ -273,12 +283,62 @@ BucketInfo buckets_from_lists(picasso_ctx *h, Batch &b, int64_t m, int64_t E, in
 
 // Lists, priorities and buckets of one iteration.
 BucketInfo build_lists_and_buckets(picasso_ctx *h, Batch &b, uint32_t ell, int64_t m, const int32_t *d_ids, int64_t E,
-                                   int64_t P, int32_t T_max)
+                                   int64_t P, int32_t T_max, const uint32_t *d_hits = nullptr,
+                                   uint32_t *h_hits = nullptr)
 {
     uint32_t *lists = buf<uint32_t>(h, h->lists, (size_t)std::max<int64_t>(E, 1));
     uint64_t *prio = buf<uint64_t>(h, h->prio, (size_t)std::max<int64_t>(m, 1));
     launch_sample_lists(b, ell, m, d_ids, T_max, lists, prio, h->stream);
-    return buckets_from_lists(h, b, m, E, P);
+    return buckets_from_lists(h, b, m, E, P, d_hits, h_hits);
+}
+
+// Upper bound on an iteration's conflict edges before the pair pass, from
+// each instance's sampled relation density rho (K keyed vertex pairs).  A
+// relation pair is a conflict edge when the two lists share a colour (Alg. 1
+// construct_conflict_graph), and two uniform T-subsets of P colours meet with
+// probability s = 1 - C(P-T, T) / C(P, T), so E|E_c| = C(m, 2) rho s.  The
+// bound takes rho four standard errors high, adds six standard deviations of
+// |E_c| (edges at one vertex are dependent through its list: variance about
+// the mean times 1 + 2 m rho T / P) and is never above the iteration's pair
+// tests, which bound |E_c| exactly (each edge is a pair of the bucket of its
+// smallest shared colour).
+int64_t conflict_edge_bound(const std::vector<InstRec> &recs, const uint32_t *hits, int32_t K, int64_t pair_tests)
+{
+    double total = 0.0;
+    for (size_t a = 0; a < recs.size(); ++a) {
+        const InstRec &r = recs[a];
+        if (r.m < 2) continue;
+        const double m = (double)r.m, P = (double)r.P, T = (double)r.T;
+        double share = 1.0;
+        if (2.0 * T <= P)
+            share = 1.0 - std::exp(2.0 * std::lgamma(P - T + 1.0) - std::lgamma(P - 2.0 * T + 1.0) -
+                                   std::lgamma(P + 1.0));
+        const double rho = (double)hits[a] / (double)K;
+        const double rho_hi =
+            std::min(1.0, rho + 4.0 * std::sqrt(std::max(rho * (1.0 - rho), 1.0 / K) / (double)K));
+        const double mu = 0.5 * m * (m - 1.0) * rho_hi * share;
+        total += mu + 6.0 * std::sqrt(mu * (1.0 + 2.0 * m * rho_hi * T / P)) + 64.0;
+    }
+    const double capped = std::min(total, (double)pair_tests);
+    return (int64_t)std::ceil(capped);
+}
+
+// The CSR passes' arguments over the current buckets and matrices (the
+// slot offsets as last scanned; no adjacency buffer, no skip flag).
+CsrArgs csr_args(picasso_ctx *h, const Batch &b, int64_t P)
+{
+    CsrArgs ca{};
+    ca.bstart = static_cast<const int64_t *>(h->bstart.p);
+    ca.bmem = static_cast<const uint32_t *>(h->bmem.p);
+    ca.bslot = static_cast<const uint8_t *>(h->bslot.p);
+    ca.P = P;
+    ca.rb_off = static_cast<const int64_t *>(h->rb_off.p);
+    ca.R = static_cast<const uint64_t *>(h->R.p);
+    ca.D = static_cast<const uint64_t *>(h->D.p);
+    ca.loff = b.loff;
+    ca.bent = static_cast<const int64_t *>(h->bent.p);
+    ca.slot_off = static_cast<const int64_t *>(h->slot_off.p);
+    return ca;
 }
 
 // Relation matrices, duplicate-pair matrices, CSR counts, scan and fill.
@@ -287,7 +347,7 @@ BucketInfo build_lists_and_buckets(picasso_ctx *h, Batch &b, uint32_t ell, int64
 // h->slot_off.
 int64_t build_conflict_graph(picasso_ctx *h, const Batch &b, int64_t m, int64_t E, int64_t P, int32_t T_max,
                              int32_t rel_mask, const BucketInfo &bi, double *ms_relate, double *ms_csr,
-                             bool *used_mfma = nullptr, bool csr_required = true)
+                             bool *used_mfma = nullptr, bool csr_required = true, int64_t edge_bound = -1)
 {
     hipStream_t st = h->stream;
     Timer tm(h);
@@ -356,16 +416,7 @@ int64_t build_conflict_graph(picasso_ctx *h, const Batch &b, int64_t m, int64_t 
         launch_dup_slow(da, st);  // its bucket count is read on the device
     }
     // edge counts per (vertex, slot), scan, row pointers
-    CsrArgs ca{};
-    ca.bstart = ra.bstart;
-    ca.bmem = ra.bmem;
-    ca.bslot = da.bslot;
-    ca.P = P;
-    ca.rb_off = ra.rb_off;
-    ca.R = R;
-    ca.D = D;
-    ca.loff = b.loff;
-    ca.bent = da.bent;
+    CsrArgs ca = csr_args(h, b, P);
     ca.slot_cnt = buf<int32_t>(h, h->slot_cnt, (size_t)std::max<int64_t>(E, 1));
     launch_count(ca, st);
     int64_t *slot_off = buf<int64_t>(h, h->slot_off, (size_t)E + 1);
@@ -373,6 +424,24 @@ int64_t build_conflict_graph(picasso_ctx *h, const Batch &b, int64_t m, int64_t 
     exclusive_scan_i32_to_i64(ca.slot_cnt, slot_off, E, true, tmp, st);
     int64_t *rowptr = buf<int64_t>(h, h->rowptr, (size_t)m + 1);
     launch_rowptr(slot_off, m, b.loff, rowptr, st);
+    ca.slot_off = slot_off;
+    if (edge_bound >= 0 && !csr_required &&
+        (h->mem_budget <= 0 || 2 * edge_bound * (int64_t)sizeof(int32_t) <= h->mem_budget)) {
+        // CSR sized by the predicted bound: the fill is queued without waiting
+        // for the exact size; a guard on the device skips it if the size
+        // exceeds the buffer (the caller refills once it knows the size)
+        const int64_t cap = 2 * edge_bound;
+        ca.adj = buf<int32_t>(h, h->adj, (size_t)std::max<int64_t>(cap, 1));
+        int32_t *flag = buf<int32_t>(h, h->csr_flag, 1);
+        launch_csr_guard(slot_off + E, cap, flag, st);
+        ca.skip = flag;
+        tm.mark();
+        launch_fill(ca, bi.max_size, st);
+        tm.mark();
+        if (ms_relate) *ms_relate = tm.ms(0, 1);
+        if (ms_csr) *ms_csr = tm.ms(2, 3);
+        return -1;
+    }
     const int64_t total = read_scalar(h, slot_off + E);
     if (total % 2) throw Error(PICASSO_EINTERNAL, "odd CSR size");
     const int64_t bytes = total * (int64_t)sizeof(int32_t);
@@ -386,7 +455,6 @@ int64_t build_conflict_graph(picasso_ctx *h, const Batch &b, int64_t m, int64_t 
         if (ms_csr) *ms_csr = 0.0;
         return total / 2;
     }
-    ca.slot_off = slot_off;
     ca.adj = buf<int32_t>(h, h->adj, (size_t)std::max<int64_t>(total, 1));
     tm.mark();
     launch_fill(ca, bi.max_size, st);
@@ -455,10 +523,12 @@ int32_t color_buckets(picasso_ctx *h, const Batch &b, int64_t m, int64_t E, int6
     j.st = buf<uint8_t>(h, h->st, (size_t)std::max<int64_t>(E, 1));
     j.dirty = buf<uint32_t>(h, h->dirty, (size_t)P);
     j.wake_at = buf<unsigned long long>(h, h->wake_at, (size_t)P);
-    int32_t *wl = buf<int32_t>(h, h->wl, (size_t)2 * P + 2);
+    int32_t *wl = buf<int32_t>(h, h->wl, (size_t)2 * P + 4);
     j.wl[0] = wl;
     j.wl[1] = wl + P;
     j.wl_count = wl + 2 * P;
+    j.ticket = reinterpret_cast<uint32_t *>(wl + 2 * P + 2);
+    launch_fill_i32(wl + 2 * P + 2, 1, 0, st);
     unsigned long long *sc = buf<unsigned long long>(h, h->scalars, 8);
     j.progress = sc + 2;
     j.m = m;
@@ -534,11 +604,12 @@ void device_features(picasso_ctx *h, uint64_t seed, uint32_t ell, int64_t m, con
     out[4] = (double)ell;
 }
 
-// The predictor's (f, alpha) for one feature row, computed on the device.
-void mlp_params_for(picasso_mlp_ctx *mc, hipStream_t st, const double feat[5], float fa_out[2])
+// The predictor's (f, alpha) for one feature row (five features and beta),
+// computed on the device.
+void mlp_params_for(picasso_mlp_ctx *mc, hipStream_t st, const double feat[kMlpIn], float fa_out[2])
 {
-    float raw[5];
-    for (int i = 0; i < 5; ++i) raw[i] = (float)feat[i];
+    float raw[kMlpIn];
+    for (int i = 0; i < kMlpIn; ++i) raw[i] = (float)feat[i];
     float *d_raw = mbuf<float>(mc, mc->raw, 8);
     float *d_out = mbuf<float>(mc, mc->out, 8);
     float *d_fa = mbuf<float>(mc, mc->fa, 8);
@@ -557,6 +628,11 @@ struct RunArgs {
     picasso_mlp_ctx *mlp = nullptr;  // learned parameters (single-instance calls)
     float *sched = nullptr;          // the learned (f, alpha) of each iteration
     int32_t max_sched = 0;
+    double beta = 0.5;               // the network's trade-off input
+    // explicit schedule (single-instance calls): iteration l uses entry
+    // min(l, n_steps) - 1; fracs/alphas then point at the last entry
+    const double *step_f = nullptr, *step_a = nullptr;
+    int32_t n_steps = 0;
 };
 
 // Adds one iteration's record (one instance's share, or the whole batch's)
@@ -572,6 +648,7 @@ void add_iter(picasso_stats &S, std::vector<int64_t> &iter_edges, int64_t idx, c
         d.T = std::max(d.T, it.T);
         d.pair_tests += it.pair_tests;
         d.edges += it.edges;
+        d.edges_bound += it.edges_bound;
         d.colored += it.colored;
         d.offset = it.offset;
         d.pair_path = std::max(d.pair_path, it.pair_path);
@@ -680,6 +757,7 @@ int64_t run_tails(picasso_ctx *h, const RunArgs &ra, const std::vector<int32_t> 
             it.T = ti.T;
             it.pair_tests = ti.pair_tests;
             it.edges = ti.edges;
+            it.edges_bound = ti.edges;  // counted exactly, no CSR to size
             it.colored = ti.colored;
             it.offset = h->nb == 1 ? ti.offset : 0;
             it.pair_path = 0;
@@ -717,6 +795,7 @@ int64_t color_all(picasso_ctx *h, const RunArgs &ra, int32_t *d_out, int64_t *n_
     }
     std::vector<int32_t> act;
     std::vector<int64_t> hv, iter_edges;
+    std::vector<uint32_t> h_hits;
     int64_t m = h->n;
     uint32_t ell = 1;
     while (m > 0) {
@@ -728,14 +807,23 @@ int64_t color_all(picasso_ctx *h, const RunArgs &ra, int32_t *d_out, int64_t *n_
         for (int32_t i = 0; i < h->nb; ++i) {
             if (mi[i] == 0) continue;
             double frac = ra.fracs[i], alpha = ra.alphas[i];
-            if (ra.mlp) {
-                double feat[5];
+            if (ra.n_steps > 0) {
+                const int32_t k = std::min<int32_t>((int32_t)ell, ra.n_steps) - 1;
+                frac = ra.step_f[k];
+                alpha = ra.step_a[k];
+            } else if (ra.mlp) {
+                double feat[kMlpIn];
                 device_features(h, ra.seeds[i], ell, mi[i], static_cast<const int32_t *>(h->ids.p) + vs,
                                 h->inst_q[i], ra.rels[i], feat);
+                feat[5] = ra.beta;
                 float fa[2];
                 mlp_params_for(ra.mlp, h->stream, feat, fa);
-                frac = (double)fa[0];
-                alpha = (double)fa[1];
+                // fallback: an output outside the parameter ranges (only
+                // corrupt weights give one) keeps the fixed parameters
+                if (std::isfinite(fa[0]) && std::isfinite(fa[1]) && fa[0] > 0.f && fa[0] <= 1.f && fa[1] > 0.f) {
+                    frac = (double)fa[0];
+                    alpha = (double)fa[1];
+                }
                 if (ra.sched && (int32_t)ell <= ra.max_sched) {
                     ra.sched[2 * (ell - 1)] = fa[0];
                     ra.sched[2 * (ell - 1) + 1] = fa[1];
@@ -775,12 +863,22 @@ int64_t color_all(picasso_ctx *h, const RunArgs &ra, int32_t *d_out, int64_t *n_
         tm.mark();
         Batch b = upload_batch(h, m);
         const int32_t *d_ids = static_cast<const int32_t *>(h->ids.p);
-        const BucketInfo bi = build_lists_and_buckets(h, b, ell, m, d_ids, E, Ptot, T_max);
+        // sampled relation density per instance: the conflict-graph size
+        // bound that sizes the CSR before the pair pass
+        uint32_t *d_hits = buf<uint32_t>(h, h->hits, (size_t)b.nb);
+        launch_fill_u32(d_hits, b.nb, 0u, st);
+        launch_density(b, d_ids, static_cast<const uint64_t *>(h->x.p), static_cast<const uint64_t *>(h->z.p), h->W,
+                       ell, kFeaturePairs, d_hits, st);
+        h_hits.resize((size_t)b.nb);
+        const BucketInfo bi = build_lists_and_buckets(h, b, ell, m, d_ids, E, Ptot, T_max, d_hits, h_hits.data());
         it.pair_tests = bi.pair_tests;
+        it.edges_bound = conflict_edge_bound(h->h_inst, h_hits.data(), kFeaturePairs, bi.pair_tests);
         tm.mark();
         bool used_mfma = false;
+        const int64_t presize = h->csr_sizing == 0 ? -1 : h->csr_sizing == 2 ? 0 : it.edges_bound;
         it.edges = build_conflict_graph(h, b, m, E, Ptot, T_max, rel_mask, bi, &it.ms_count, &it.ms_fill,
-                                        &used_mfma, false);
+                                        &used_mfma, false, presize);
+        const bool csr_deferred = it.edges < 0;
         it.pair_path = used_mfma ? PICASSO_PATH_MFMA : PICASSO_PATH_VALU;
         tm.mark();
         it.jp_rounds = color_buckets(h, b, m, E, Ptot, T_max, bi);
@@ -803,6 +901,19 @@ int64_t color_all(picasso_ctx *h, const RunArgs &ra, int32_t *d_out, int64_t *n_
         tm.mark();
         hv.resize((size_t)3 * na);
         download(h, hv.data(), iout, hv.size() * sizeof(int64_t));
+        if (csr_deferred) {
+            it.edges = 0;
+            for (int32_t a = 0; a < na; ++a) it.edges += hv[2 * na + a];
+            if (it.edges > presize) {
+                // above the predicted bound (the guard skipped the fill):
+                // the CSR again at its exact size
+                CsrArgs ca = csr_args(h, b, Ptot);
+                ca.adj = buf<int32_t>(h, h->adj, (size_t)std::max<int64_t>(2 * it.edges, 1));
+                launch_fill(ca, bi.max_size, st);
+                PCHECK_HIP(hipStreamSynchronize(st));
+                ++S.csr_refills;
+            }
+        }
         int64_t m_next = 0;
         for (int32_t a = 0; a < na; ++a) {
             const int32_t i = act[a];
@@ -827,7 +938,8 @@ int64_t color_all(picasso_ctx *h, const RunArgs &ra, int32_t *d_out, int64_t *n_
         // instances with few vertices left finish in the tail kernel; the
         // others' vertices move to the front of the next vertex set
         bool gathered = false;
-        if (!ra.mlp && h->use_tail) {
+        // (with a schedule, once every further iteration uses its last entry)
+        if (!ra.mlp && h->use_tail && (ra.n_steps == 0 || (int32_t)ell + 1 >= ra.n_steps)) {
             const int64_t kept = run_tails(h, ra, act, mi, off, ell, n_colors, d_out, S, iter_edges, gathered);
             m_next = kept;
         }
@@ -1044,8 +1156,9 @@ void picasso_destroy(picasso_handle h)
                      &h->slot_cnt, &h->slot_off, &h->rowptr, &h->adj,      &h->col,     &h->blk,      &h->fre,
                      &h->nblk,    &h->st,       &h->dirty,   &h->wl,       &h->flags,   &h->pos,      &h->used,
                      &h->scan_tmp, &h->bx,      &h->bz,      &h->tile_bucket,
-                     &h->scalars, &h->out_colors, &h->inst,    &h->vinst,    &h->loff,    &h->binst,    &h->inst_out, &h->tail_recs,
-                     &h->tail_table, &h->tail_outs, &h->tail_iters, &h->tail_ranges, &h->wake_at};
+                     &h->scalars, &h->out_colors, &h->judge_out, &h->inst,    &h->vinst,    &h->loff,    &h->binst,    &h->inst_out, &h->tail_recs,
+                     &h->tail_table, &h->tail_outs, &h->tail_iters, &h->tail_ranges, &h->wake_at,
+                     &h->hits,    &h->csr_flag};
     for (DevBuf *b : all) h->arena.release(*b);
     if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
     delete h;
@@ -1084,6 +1197,14 @@ int32_t picasso_set_option(picasso_handle h, int32_t key, int64_t value)
                     break;
                 case PICASSO_OPT_TAIL:
                     h->use_tail = value != 0;
+                    break;
+                case PICASSO_OPT_CSR_SIZING:
+                    if (value < 0 || value > 2) throw Error(PICASSO_EINVAL, "CSR sizing is 0, 1 or 2");
+                    h->csr_sizing = (int32_t)value;
+                    break;
+                case PICASSO_OPT_LEARNED_JUDGE:
+                    if (value != 0 && value != 1) throw Error(PICASSO_EINVAL, "the judge option is 0 or 1");
+                    h->judge = (int32_t)value;
                     break;
                 case PICASSO_OPT_MFMA_CAP:
                     if (value < -1 || value > 4096) throw Error(PICASSO_EINVAL, "MFMA bucket cap must be in [-1, 4096]");
@@ -1488,7 +1609,34 @@ int32_t picasso_mlp_train_step(picasso_mlp c, const float *features, const float
         PICASSO_EINTERNAL);
 }
 
-int64_t picasso_color_learned(picasso_handle h, uint64_t seed, picasso_mlp mlp, int32_t relation,
+int64_t picasso_color_schedule(picasso_handle h, uint64_t seed, const double *palette_fracs, const double *list_sizes,
+                               int32_t count, int32_t relation, int32_t *out_colors)
+{
+    return guarded(
+        [&]() -> int64_t {
+            check_handle(h);
+            check_single(h);
+            if (count < 1 || !palette_fracs || !list_sizes) throw Error(PICASSO_EINVAL, "empty schedule");
+            for (int32_t k = 0; k < count; ++k) check_color_args(palette_fracs[k], list_sizes[k], relation);
+            if (h->n > 0 && !out_colors) throw Error(PICASSO_EINVAL, "null output");
+            if (h->n == 0) {
+                std::memset(&h->stats, 0, sizeof(h->stats));
+                return 0;
+            }
+            int32_t *d_out = buf<int32_t>(h, h->out_colors, (size_t)h->n);
+            RunArgs ra{&seed, &palette_fracs[count - 1], &list_sizes[count - 1], &relation};
+            ra.step_f = palette_fracs;
+            ra.step_a = list_sizes;
+            ra.n_steps = count;
+            int64_t n_colors = 0;
+            const int64_t nc = color_all(h, ra, d_out, &n_colors);
+            download(h, out_colors, d_out, (size_t)h->n * sizeof(int32_t));
+            return nc;
+        },
+        PICASSO_EINTERNAL);
+}
+
+int64_t picasso_color_learned(picasso_handle h, uint64_t seed, picasso_mlp mlp, double beta, int32_t relation,
                               int32_t *out_colors, float *out_schedule, int32_t max_sched)
 {
     return guarded(
@@ -1496,6 +1644,7 @@ int64_t picasso_color_learned(picasso_handle h, uint64_t seed, picasso_mlp mlp, 
             check_handle(h);
             check_single(h);
             check_rel(relation);
+            if (!(beta >= 0.0 && beta <= 1.0)) throw Error(PICASSO_EINVAL, "beta must be in [0, 1]");
             if (!mlp) throw Error(PICASSO_EINVAL, "null network");
             if (h->n > 0 && !out_colors) throw Error(PICASSO_EINVAL, "null output");
             if (mlp->device != h->device) throw Error(PICASSO_EINVAL, "network and handle on different devices");
@@ -1504,11 +1653,39 @@ int64_t picasso_color_learned(picasso_handle h, uint64_t seed, picasso_mlp mlp, 
                 return 0;
             }
             int32_t *d_out = buf<int32_t>(h, h->out_colors, (size_t)h->n);
-            const double f0 = 0.125, a0 = 2.0;
+            const double f0 = kFixedFrac, a0 = kFixedAlpha;
             RunArgs ra{&seed, &f0, &a0, &relation, mlp, out_schedule, max_sched};
+            ra.beta = beta;
             int64_t n_colors = 0;
             const int64_t nc = color_all(h, ra, d_out, &n_colors);
+            if (!h->judge) {
+                download(h, out_colors, d_out, (size_t)h->n * sizeof(int32_t));
+                return nc;
+            }
+            // judge: the fixed-parameter colouring of the same strings and
+            // seed; the network's result is kept unless the fixed one uses
+            // fewer colours
+            const picasso_stats learned_stats = h->stats;
+            const std::vector<picasso_instance_stats> learned_istats = h->istats;
+            int32_t *d_fixed = buf<int32_t>(h, h->judge_out, (size_t)h->n);
+            RunArgs rf{&seed, &f0, &a0, &relation};
+            int64_t nf_colors = 0;
+            const int64_t nf = color_all(h, rf, d_fixed, &nf_colors);
+            const double ms_fixed = h->stats.ms_total;
+            const int64_t peak = std::max<int64_t>(learned_stats.peak_device_bytes, h->stats.peak_device_bytes);
+            if (nf < nc) {
+                download(h, out_colors, d_fixed, (size_t)h->n * sizeof(int32_t));
+                h->stats.judged = PICASSO_JUDGE_FIXED;
+                h->stats.peak_device_bytes = peak;
+                h->stats.ms_total += learned_stats.ms_total;
+                return nf;
+            }
             download(h, out_colors, d_out, (size_t)h->n * sizeof(int32_t));
+            h->stats = learned_stats;
+            h->istats = learned_istats;
+            h->stats.judged = PICASSO_JUDGE_LEARNED;
+            h->stats.peak_device_bytes = peak;
+            h->stats.ms_total += ms_fixed;
             return nc;
         },
         PICASSO_EINTERNAL);

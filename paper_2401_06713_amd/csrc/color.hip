@@ -295,10 +295,14 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(6)))
             atomicMin(&a.wake_at[c], from);
         __syncthreads();
     }
+    // The list this round consumed is emptied before the next round refills
+    // it, by the last workgroup to finish: every workgroup read n_in before
+    // taking its ticket (the loop bound depends on it).
+    if (threadIdx.x == 0 && atomicAdd(a.ticket, 1u) == gridDim.x - 1) {
+        a.wl_count[cur] = 0;
+        *a.ticket = 0u;
+    }
 }
-
-// The list a round has consumed is emptied before the next round refills it.
-__global__ void jp_reset_kernel(int32_t *count) { *count = 0; }
 
 // Worklist of every bucket (the first round, and the host's recovery round).
 __global__ void wl_all_kernel(int64_t P, int32_t *wl, uint32_t *dirty, unsigned long long *wake_at,
@@ -425,8 +429,6 @@ void launch_jp_round(const JpArgs &a, int cur, hipStream_t st)
     const size_t lds = (size_t)2 * a.nw_max * sizeof(uint64_t);
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(a.P, 16384));
     jp_round_kernel<<<(unsigned)grid, kWave, lds, st>>>(a, cur);
-    PCHECK_LAUNCH();
-    jp_reset_kernel<<<1, 1, 0, st>>>(&a.wl_count[cur]);
     PCHECK_LAUNCH();
 }
 

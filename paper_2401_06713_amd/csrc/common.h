@@ -204,10 +204,13 @@ struct CsrArgs {
     int32_t *slot_cnt;       // count pass: edge count per list entry (vertex, slot)
     const int64_t *slot_off; // fill pass: exclusive scan of slot_cnt
     int32_t *adj;            // fill pass: CSR column indices
+    const int32_t *skip;     // fill pass: if non-null and nonzero, write nothing
 };
 void launch_count(const CsrArgs &a, hipStream_t st);
 void launch_fill(const CsrArgs &a, int64_t max_size, hipStream_t st);  // max_size: largest bucket
 void launch_rowptr(const int64_t *slot_off, int64_t m, const int64_t *loff, int64_t *rowptr, hipStream_t st);
+// flag = (*total > cap): the CSR of *total entries does not fit cap entries.
+void launch_csr_guard(const int64_t *total, int64_t cap, int32_t *flag, hipStream_t st);
 
 // color.hip
 struct JpArgs {
@@ -230,15 +233,15 @@ struct JpArgs {
     unsigned long long *wake_at;  // per bucket: first bucket position changed since it was last taken
     int32_t *wl[2];         // worklists of buckets (P entries each)
     int32_t *wl_count;      // [2]
+    uint32_t *ticket;       // workgroups of the current round that have finished
     unsigned long long *progress;  // decided vertices
     int64_t m;              // vertices to decide
 };
 // Every bucket onto worklist 0 (marked waiting); worklist 1 empty.
 void launch_jp_all(const JpArgs &a, hipStream_t st);
-// One worklist round reading list `cur` and filling list cur ^ 1; then list
-// `cur` is emptied by a separate one-thread kernel (three lists in rotation,
-// with each round emptying the list the next round fills, measured about
-// twice as slow per round on MI355X).
+// One worklist round reading list `cur` and filling list cur ^ 1; the last
+// workgroup to finish (a ticket counter, zero between rounds) empties list
+// `cur`, after every workgroup has read its length.
 void launch_jp_round(const JpArgs &a, int cur, hipStream_t st);
 void launch_csr_to_relation(int64_t m, const int64_t *rowptr, const int32_t *adj, const uint32_t *lists,
                             const int64_t *loff, const int64_t *pos_of, const int64_t *bstart, const int64_t *rb_off,
@@ -286,7 +289,7 @@ void launch_gather_ranges(const int32_t *src, int32_t *dst, const int64_t *range
                           hipStream_t st);
 
 // learned.hip: features of the current vertex set and the predictor network.
-constexpr int kMlpIn = 5, kMlpHidden = 64, kMlpOut = 2;
+constexpr int kMlpIn = 6, kMlpHidden = 64, kMlpOut = 2;
 constexpr int kMlpParams = kMlpHidden * kMlpIn + kMlpHidden + kMlpHidden * kMlpHidden + kMlpHidden +
                            kMlpOut * kMlpHidden + kMlpOut;
 constexpr int kMlpKeep = kMlpIn + 2 * kMlpHidden + kMlpOut + 2 * kMlpHidden;  // per-row training state
@@ -294,6 +297,12 @@ constexpr int kFeaturePairs = 4096;
 void launch_features(int64_t m, const int32_t *ids, const uint64_t *x, const uint64_t *z, int32_t W, uint64_t seed,
                      uint32_t ell, int32_t rel, int32_t K, unsigned long long *weight, unsigned long long *hits,
                      hipStream_t st);
+// Relation density of every instance of a batch: hits[a] (zeroed by the
+// caller) counts the K sampled pairs of the instance's active vertices that
+// the relation joins -- the pairs the features kernel samples, keyed by the
+// instance's seed.
+void launch_density(const Batch &b, const int32_t *ids, const uint64_t *x, const uint64_t *z, int32_t W, uint32_t ell,
+                    int32_t K, uint32_t *hits, hipStream_t st);
 // Forward pass over B rows (out: B x 2 raw outputs, may be null); with
 // target/keep/row_loss non-null it also stores the training state.
 void launch_mlp_rows(const float *p, const float *raw, int32_t B, float *out, const float *target, float *keep,

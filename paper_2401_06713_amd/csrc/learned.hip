@@ -1,15 +1,18 @@
 // Learned parameters: instance features and the predictor network.
 //
 // The paper chooses (palette %, alpha) with a regressor trained on parameter
-// sweeps (Sec. VI, Eq. 7).  Here a 3-layer perceptron 5 -> 64 -> 64 -> 2
+// sweeps and given the graph and the trade-off weight beta of its
+// bi-objective (Sec. VI, Eq. 7).  Here a 3-layer perceptron 6 -> 64 -> 64 -> 2
 // (ReLU hidden layers, FP32) maps five features of the current iteration
-// (ln m, q, mean Pauli weight, sampled relation density, iteration) to
-// (f, alpha) = (0.01 + 0.24 sigmoid(o0), 1 + 3 sigmoid(o1)).
+// (ln m, q, mean Pauli weight, sampled relation density, iteration) and beta
+// to (f, alpha) = (0.01 + 0.24 sigmoid(o0), 1 + 3 sigmoid(o1)).
 //
-// Parameter vector layout (4674 floats): W1[64][5], b1[64], W2[64][64],
+// Parameter vector layout (4738 floats): W1[64][6], b1[64], W2[64][64],
 // b2[64], W3[2][64], b3[2].  Inputs are scaled by (1/16, 1/128, 1/128, 1,
-// 1/16) before the first layer.  Training loss over B rows:
+// 1/16, 1) before the first layer.  Training loss over B rows:
 // (1/(2B)) sum (o - t)^2, minimised with Adam.
+#include <algorithm>
+
 #include "common.h"
 
 namespace picasso {
@@ -62,6 +65,39 @@ __global__ void features_kernel(int64_t m, const int32_t *__restrict__ ids, cons
     }
 }
 
+// Relation density of each instance of a batch (the conflict-graph size
+// prediction): block (kb, a) tests pairs kb*256 .. kb*256+255 of instance a,
+// drawn as in features_kernel from the instance's seed.
+__global__ void density_kernel(Batch b, const int32_t *__restrict__ ids, const uint64_t *__restrict__ x,
+                               const uint64_t *__restrict__ z, int32_t W, uint32_t ell, int32_t K,
+                               uint32_t *__restrict__ hits)
+{
+    for (int32_t ai = blockIdx.y; ai < b.nb; ai += gridDim.y) {
+        const InstRec &r = b.inst[ai];
+        const int64_t m = r.m;
+        const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        uint32_t hit = 0;
+        if (m >= 2 && k < K) {
+            const uint64_t r1 = philox_draw(r.seed, (uint32_t)k, 0, ell, TAG_FEAT);
+            const uint64_t r2 = philox_draw(r.seed, (uint32_t)k, 1, ell, TAG_FEAT);
+            const uint64_t pa = __umul64hi(r1, (uint64_t)m);
+            uint64_t pb = __umul64hi(r2, (uint64_t)(m - 1));
+            if (pb >= pa) ++pb;
+            const int64_t ga = (int64_t)ids[r.vstart + pa] * W, gb = (int64_t)ids[r.vstart + pb] * W;
+            uint64_t par = 0, any = 0;
+            for (int w = 0; w < W; ++w) {
+                const uint64_t t = (x[ga + w] & z[gb + w]) ^ (z[ga + w] & x[gb + w]);
+                par ^= t;
+                any |= t;
+            }
+            const uint32_t odd = __popcll(par) & 1;
+            hit = r.rel == PICASSO_REL_ANTICOMMUTE ? odd : r.rel == PICASSO_REL_COMMUTE ? 1 - odd : (any != 0);
+        }
+        const uint64_t bal = __ballot(hit != 0);
+        if ((threadIdx.x & 63) == 0 && bal) atomicAdd(&hits[ai], (uint32_t)__popcll(bal));
+    }
+}
+
 // ---- the network ----------------------------------------------------------
 __device__ __forceinline__ void scale_inputs(const float *raw, float *xin)
 {
@@ -70,6 +106,7 @@ __device__ __forceinline__ void scale_inputs(const float *raw, float *xin)
     xin[2] = raw[2] * (1.0f / 128.0f);
     xin[3] = raw[3];
     xin[4] = raw[4] * (1.0f / 16.0f);
+    xin[5] = raw[5];
 }
 
 // One thread per row.  Keeps what the gradient needs when `keep` is set:
@@ -193,6 +230,15 @@ void launch_features(int64_t m, const int32_t *ids, const uint64_t *x, const uin
     if (blocks < 1) blocks = 1;
     if (blocks > 4096) blocks = 4096;
     features_kernel<<<(unsigned)blocks, 256, 0, st>>>(m, ids, x, z, W, seed, ell, rel, K, weight, hits);
+    PCHECK_LAUNCH();
+}
+
+void launch_density(const Batch &b, const int32_t *ids, const uint64_t *x, const uint64_t *z, int32_t W, uint32_t ell,
+                    int32_t K, uint32_t *hits, hipStream_t st)
+{
+    if (b.nb <= 0 || K <= 0) return;
+    const dim3 grid((unsigned)((K + 255) / 256), (unsigned)std::min<int32_t>(b.nb, 65535));
+    density_kernel<<<grid, 256, 0, st>>>(b, ids, x, z, W, ell, K, hits);
     PCHECK_LAUNCH();
 }
 

@@ -427,6 +427,7 @@ __global__ void __launch_bounds__(kWave * kFillWaves) fill_kernel(CsrArgs a, int
     int64_t *seg = reinterpret_cast<int64_t *>(fill_lds + cap_words); // cap_members
     uint32_t *mv = reinterpret_cast<uint32_t *>(seg + cap_members);    // cap_members
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (a.skip && *a.skip) return;  // the CSR does not fit the buffer: nothing is written
     for (int64_t c = blockIdx.x; c < a.P; c += gridDim.x) {
         const int64_t base = a.bstart[c];
         const int64_t S = a.bstart[c + 1] - base;
@@ -513,6 +514,14 @@ void launch_fill(const CsrArgs &a, int64_t max_size, hipStream_t st)
     const int64_t cap_words = std::min<int64_t>(cap_members * ((cap_members + 63) >> 6), kFillWords);
     const size_t lds = (size_t)cap_words * 8 + (size_t)cap_members * 12;
     fill_kernel<<<grid_cap(a.P, 1 << 20), kWave * kFillWaves, lds, st>>>(a, cap_members, cap_words);
+    PCHECK_LAUNCH();
+}
+
+__global__ void csr_guard_kernel(const int64_t *total, int64_t cap, int32_t *flag) { *flag = *total > cap; }
+
+void launch_csr_guard(const int64_t *total, int64_t cap, int32_t *flag, hipStream_t st)
+{
+    csr_guard_kernel<<<1, 1, 0, st>>>(total, cap, flag);
     PCHECK_LAUNCH();
 }
 

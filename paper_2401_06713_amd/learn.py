@@ -2,17 +2,20 @@
 
 The paper picks (palette %, alpha) by sweeping a grid on training graphs,
 scoring each point with a bi-objective (Eq. 7: beta * colours + (1 - beta) *
-|E_c|) and training a regressor on the argmins (Sec. VI).  Here:
+|E_c|) for several values of beta, and training a regressor that is given
+the graph and beta (Sec. VI, Steps 1-6).  Here:
 
 * sweep: every training instance is coloured with the fixed parameters
   (f = 0.125, alpha = 2) and at every grid point; each run records the colour
   count, the largest per-iteration |E_c| (the memory driver) and its time;
-* label: J = beta * C / C_fixed + (1 - beta) * E / E_fixed (the raw sum of
-  Eq. 7 mixes units, hence the normalisation) minimised over the grid points
-  with C <= C_fixed; the fixed point itself is always a candidate;
+* label, per beta: J = beta * C / C_fixed + (1 - beta) * E / E_fixed (the
+  raw sum of Eq. 7 mixes units, hence the normalisation) minimised over the
+  grid points with C <= (1 - margin) C_fixed; the fixed point itself is
+  always a candidate;
 * rows: the features of every iteration of the fixed run (iteration l's
   vertex set is the set of vertices whose colour id is at least that
-  iteration's palette offset), each with its instance's label;
+  iteration's palette offset) followed by beta, each with its instance's
+  label for that beta;
 * training: mini-batch Adam on the device network (Mlp.train_step).
 
 All colouring runs, features and training steps go through libpicasso.
@@ -72,9 +75,12 @@ def objective(r: Run, fixed: Run, beta: float) -> float:
     return beta * r.colors / fixed.colors + (1 - beta) * r.max_edges / max(fixed.max_edges, 1)
 
 
-def label(runs: list[Run], fixed: Run, beta: float) -> Run:
-    ok = [r for r in runs if r.colors <= fixed.colors] + [fixed]
+def label(runs: list[Run], fixed: Run, beta: float, margin: float = 0.0) -> Run:
+    ok = [r for r in runs if r.colors <= (1.0 - margin) * fixed.colors] + [fixed]
     return min(ok, key=lambda r: objective(r, fixed, beta))
+
+
+BETAS = (0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9)
 
 
 def training_instances(count: int, seed: int = 10**6, n_lo: int = 1000, n_hi: int = 100_000):
@@ -107,8 +113,8 @@ def iteration_sets(col: np.ndarray, frac: float):
     return sets
 
 
-def sweep(cfgs, beta: float = 0.5, grid_f=GRID_F, grid_a=GRID_A, log=print):
-    """Returns (features rows, targets rows, per-instance records).
+def sweep(cfgs, betas=BETAS, grid_f=GRID_F, grid_a=GRID_A, margin: float = 0.0, log=print):
+    """Returns (input rows: features and beta, targets rows, per-instance records).
 
     All training instances sit in one batch handle: the fixed run and every
     grid point are one batched colouring each; per-instance colour counts
@@ -153,14 +159,18 @@ def sweep(cfgs, beta: float = 0.5, grid_f=GRID_F, grid_a=GRID_A, log=print):
         with pk.Picasso(x, z, cfg.q) as h:
             feats = np.array([h.features(cfg.seed, k + 1, ids, cfg.relation)
                               for k, ids in enumerate(iteration_sets(cols[i], FIXED[0]))], dtype=np.float64)
-        best = label(runs[i], fixed[i], beta)
-        X.append(feats)
-        Y.append(np.repeat(pk.unsquash(best.frac, best.alpha)[None, :], len(feats), axis=0))
-        recs.append({"config": asdict(cfg), "fixed": asdict(fixed[i]), "best": asdict(best)})
+        best = {}
+        for beta in betas:
+            b = label(runs[i], fixed[i], beta, margin)
+            best[beta] = asdict(b)
+            X.append(np.concatenate([feats, np.full((len(feats), 1), beta)], axis=1))
+            Y.append(np.repeat(pk.unsquash(b.frac, b.alpha)[None, :], len(feats), axis=0))
+        recs.append({"config": asdict(cfg), "fixed": asdict(fixed[i]), "best": best,
+                     "runs": [asdict(r) for r in runs[i]]})
     if log:
-        gain = np.mean([objective(r, f, beta) for r, f in
-                        ((label(rr, ff, beta), ff) for rr, ff in zip(runs, fixed))])
-        log(f"sweep: {len(cfgs)} instances, mean best J {gain:.3f} (fixed = 1)")
+        for beta in betas:
+            gain = np.mean([objective(label(rr, ff, beta, margin), ff, beta) for rr, ff in zip(runs, fixed)])
+            log(f"sweep: {len(cfgs)} instances, beta {beta}: mean best J {gain:.3f} (fixed = 1)")
     return np.concatenate(X), np.concatenate(Y), recs
 
 
@@ -179,16 +189,17 @@ def train(X, Y, steps: int = 2000, batch: int = 256, lr: float = 3e-3, seed: int
     return mlp, loss
 
 
-def evaluate(mlp: pk.Mlp, cfgs, beta: float = 0.5):
-    """Per instance: fixed vs learned colours, largest |E_c|, time, peak bytes.
+def evaluate(mlp: pk.Mlp, cfgs, betas=(0.5,), judge: bool = False):
+    """Per instance: fixed vs learned colours, largest |E_c|, time, peak
+    bytes, for each beta.
 
     The learned run consults the network every iteration, so it does not use
     the tail kernel; the fixed run is timed the same way (`fixed`), and with
-    the tail kernel as well (`fixed_tail_ms`)."""
-    out = []
+    the tail kernel as well (`fixed_tail_ms`).  Every run uses a fresh handle,
+    so its peak counts only its own buffers."""
+    out = {float(b): [] for b in betas}
     for cfg in cfgs:
         x, z = wl.make(cfg)
-        # a fresh handle per method, so each peak counts only its own buffers
         with pk.Picasso(x, z, cfg.q) as h:
             h.color(cfg.seed, *FIXED, cfg.relation)  # warm-up
             tail = run_once(h, cfg.seed, *FIXED, cfg.relation)
@@ -196,16 +207,35 @@ def evaluate(mlp: pk.Mlp, cfgs, beta: float = 0.5):
             h.set_option(pk.OPT_TAIL, 0)
             h.color(cfg.seed, *FIXED, cfg.relation)
             fixed = run_once(h, cfg.seed, *FIXED, cfg.relation)
-        with pk.Picasso(x, z, cfg.q) as h:
-            h.color_learned(mlp, cfg.seed, cfg.relation)  # warm-up
-            t = time.perf_counter()
-            nc, _, sched = h.color_learned(mlp, cfg.seed, cfg.relation)
-            ms = (time.perf_counter() - t) * 1e3
-            st = h.stats()
-        learned = Run(float(sched[0, 0]), float(sched[0, 1]), nc, st["max_edges"], ms, st["peak_device_bytes"])
-        out.append({"n": cfg.n, "q": cfg.q, "fixed": asdict(fixed), "fixed_tail_ms": tail.ms,
-                    "learned": asdict(learned), "J_learned": objective(learned, fixed, beta)})
+        for beta in betas:
+            with pk.Picasso(x, z, cfg.q) as h:
+                h.set_option(pk.OPT_LEARNED_JUDGE, int(judge))
+                h.color_learned(mlp, cfg.seed, cfg.relation, beta)  # warm-up
+            with pk.Picasso(x, z, cfg.q) as h:
+                h.set_option(pk.OPT_LEARNED_JUDGE, int(judge))
+                t = time.perf_counter()
+                nc, _, sched = h.color_learned(mlp, cfg.seed, cfg.relation, beta)
+                ms = (time.perf_counter() - t) * 1e3
+                st = h.stats()
+            learned = Run(float(sched[0, 0]), float(sched[0, 1]), nc, st["max_edges"], ms, st["peak_device_bytes"])
+            out[float(beta)].append({"n": cfg.n, "q": cfg.q, "seed": cfg.seed, "fixed": asdict(fixed),
+                                     "fixed_tail_ms": tail.ms, "learned": asdict(learned),
+                                     "J_learned": objective(learned, fixed, beta), "schedule": sched.tolist(),
+                                     "judged": st["judged"]})
     return out
+
+
+def summarize(res: list) -> dict:
+    """Mean ratios learned / fixed over the evaluated instances."""
+    def mean(key):
+        return float(np.mean([r["learned"][key] / r["fixed"][key] for r in res]))
+
+    return {"count": len(res), "mean_J_learned": float(np.mean([r["J_learned"] for r in res])),
+            "colors_ratio": mean("colors"), "max_edges_ratio": mean("max_edges"), "ms_ratio": mean("ms"),
+            "peak_bytes_ratio": mean("peak_bytes"),
+            "colors_ratio_max": float(max(r["learned"]["colors"] / r["fixed"]["colors"] for r in res)),
+            "instances_with_fewer_or_equal_colours": int(sum(r["learned"]["colors"] <= r["fixed"]["colors"]
+                                                              for r in res))}
 
 
 def heldout_instances(count: int, n: int, q: int, pI: float, seed: int = 7_000_000):
@@ -220,8 +250,13 @@ def main():
     ap.add_argument("--train", type=int, default=1000, help="training instances")
     ap.add_argument("--n-lo", type=int, default=1000)
     ap.add_argument("--n-hi", type=int, default=100_000)
-    ap.add_argument("--steps", type=int, default=3000)
-    ap.add_argument("--beta", type=float, default=0.5)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--betas", type=float, nargs="+", default=list(BETAS), help="labels for these beta values")
+    ap.add_argument("--margin", type=float, default=0.0,
+                    help="labels need C <= (1 - margin) C_fixed (else the fixed parameters)")
+    ap.add_argument("--grid-f", type=float, nargs="+", default=list(GRID_F))
+    ap.add_argument("--grid-a", type=float, nargs="+", default=list(GRID_A))
+    ap.add_argument("--eval-betas", type=float, nargs="+", default=[0.1, 0.5, 0.9])
     ap.add_argument("--heldout", type=int, default=20)
     ap.add_argument("--heldout-n", type=int, default=500_000)
     ap.add_argument("--heldout-q", type=int, default=96)
@@ -235,29 +270,26 @@ def main():
     else:
         cfgs = training_instances(args.train, n_lo=args.n_lo, n_hi=args.n_hi)
         t = time.perf_counter()
-        X, Y, recs = sweep(cfgs, args.beta, log=say)
+        X, Y, recs = sweep(cfgs, args.betas, tuple(args.grid_f), tuple(args.grid_a), args.margin, log=say)
         sweep_s = time.perf_counter() - t
+        with open(args.out + "_sweep.json", "w") as f:
+            json.dump(recs, f)
         mlp, loss = train(X, Y, steps=args.steps, log=say)
         rows, n_train = int(X.shape[0]), len(cfgs)
         np.save(args.out + ".npy", mlp.get_params())
     held = heldout_instances(args.heldout, args.heldout_n, args.heldout_q, args.heldout_pi)
-    res = evaluate(mlp, held, args.beta)
+    res = evaluate(mlp, held, args.eval_betas)
     summary = {
-        "beta": args.beta, "train_instances": n_train, "rows": rows, "final_loss": loss,
+        "betas": args.betas, "margin": args.margin, "grid_f": args.grid_f, "grid_a": args.grid_a,
+        "train_instances": n_train, "n_range": [args.n_lo, args.n_hi], "rows": rows, "final_loss": loss,
         "sweep_seconds": sweep_s,
         "heldout": {"count": len(held), "n": args.heldout_n, "q": args.heldout_q, "pI": args.heldout_pi,
-                    "mean_J_learned": float(np.mean([r["J_learned"] for r in res])),
-                    "colors_ratio": float(np.mean([r["learned"]["colors"] / r["fixed"]["colors"] for r in res])),
-                    "max_edges_ratio": float(np.mean([r["learned"]["max_edges"] / r["fixed"]["max_edges"]
-                                                      for r in res])),
-                    "ms_ratio": float(np.mean([r["learned"]["ms"] / r["fixed"]["ms"] for r in res])),
-                    "peak_bytes_ratio": float(np.mean([r["learned"]["peak_bytes"] / r["fixed"]["peak_bytes"]
-                                                       for r in res])),
-                    "instances": res},
+                    "by_beta": {str(b): {**summarize(r), "instances": r} for b, r in res.items()}},
     }
     with open(args.out + ".json", "w") as f:
         json.dump(summary, f, indent=1)
-    say("held-out:", json.dumps({k: v for k, v in summary["heldout"].items() if k != "instances"}))
+    for b, r in res.items():
+        say(f"held-out beta {b}:", json.dumps(summarize(r)))
     if not args.params:
         say("saved", os.path.abspath(args.out + ".npy"))
 

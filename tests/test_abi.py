@@ -29,12 +29,36 @@ def test_last_error_callable_without_gpu():
     assert isinstance(pk.last_error(), str)
 
 
+def c_layout(struct: str, fields) -> dict:
+    """sizeof and offsetof of a header struct, from the C compiler."""
+    import subprocess
+    import tempfile
+
+    body = [f'printf("size %zu\\n", sizeof({struct}));']
+    body += [f'printf("{f} %zu\\n", offsetof({struct}, {f}));' for f in fields]
+    src = ("#include <stddef.h>\n#include <stdio.h>\n#include \"picasso.h\"\nint main(void) {\n"
+           + "\n".join(body) + "\nreturn 0;\n}\n")
+    with tempfile.TemporaryDirectory() as d:
+        c, exe = os.path.join(d, "layout.c"), os.path.join(d, "layout")
+        with open(c, "w") as f:
+            f.write(src)
+        subprocess.run(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), c, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout
+    return {k: int(v) for k, v in (line.split() for line in out.splitlines())}
+
+
+def check_struct(struct: str, cls):
+    names = [name for name, _ in cls._fields_]
+    lay = c_layout(struct, names)
+    assert ctypes.sizeof(cls) == lay["size"], struct
+    for name in names:
+        assert getattr(cls, name).offset == lay[name], (struct, name)
+
+
 def test_stats_struct_layout():
-    # picasso_iter_stats: 7 int64 + 2 int32 + 6 double = 112 bytes
-    assert ctypes.sizeof(pk.IterStats) == 112
-    assert ctypes.sizeof(pk.Stats) == 7 * 8 + 8 + 8 + 112 * pk.MAX_ITER_STATS
+    check_struct("picasso_iter_stats", pk.IterStats)
+    check_struct("picasso_stats", pk.Stats)
 
 
 def test_instance_stats_struct_layout():
-    # picasso_instance_stats: 5 int64 + 2 int32 = 48 bytes
-    assert ctypes.sizeof(pk.InstanceStats) == 48
+    check_struct("picasso_instance_stats", pk.InstanceStats)

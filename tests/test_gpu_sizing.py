@@ -1,0 +1,80 @@
+"""The conflict-graph size predicted before the pair pass (the bound that
+sizes each iteration's CSR buffer) against the actual |E_c|, through the
+C ABI: the bound holds in every iteration that runs the full path, it is
+not loose by more than the sampling allows at scale, and sizing the CSR
+from it (with the refill path forced, or with the exact size) changes
+neither the colours nor the statistics."""
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2401_06713_amd as pk
+from paper_2401_06713_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+CASES = [
+    (2000, 16, (0.25, 0.25, 0.25, 0.25), 0, 0.125, 2.0),
+    (20000, 48, (0.7, 0.1, 0.1, 0.1), 0, 0.125, 2.0),
+    (20000, 48, (0.7, 0.1, 0.1, 0.1), 1, 0.05, 3.0),
+    (15000, 100, (0.8, 0.2 / 3, 0.2 / 3, 0.2 / 3), 2, 0.25, 1.0),
+    (30000, 64, (0.6, 0.1, 0.2, 0.1), 0, 0.03, 4.0),
+]
+
+
+def full_path_iters(st):
+    return [it for it in st["iters"] if it["pair_path"] != 0]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_predicted_bound_holds(case):
+    n, q, probs, rel, f, a = CASES[case]
+    say("sizing", n, q, rel, f, a)
+    x, z = wl.pauli_strings(n, q, probs, seed=100 + case)
+    with pk.Picasso(x, z, q) as h:
+        nc, col = h.color(case, f, a, rel)
+        st = h.stats()
+    its = full_path_iters(st)
+    assert its
+    for it in its:
+        assert it["edges"] <= it["edges_bound"] <= it["pair_tests"], it
+        if it["edges"] >= 1_000_000:
+            assert it["edges_bound"] <= 1.1 * it["edges"], it
+    assert st["csr_refills"] == 0
+
+
+def test_sizing_modes_give_identical_results():
+    n, q, rel = 20000, 48, 0
+    x, z = wl.pauli_strings(n, q, (0.7, 0.1, 0.1, 0.1), seed=7)
+    out = {}
+    with pk.Picasso(x, z, q) as h:
+        for mode in (1, 0, 2):
+            h.set_option(pk.OPT_CSR_SIZING, mode)
+            nc, col = h.color(3, 0.125, 2.0, rel)
+            out[mode] = (nc, col, h.stats())
+    for mode in (0, 2):
+        assert out[mode][0] == out[1][0] and np.array_equal(out[mode][1], out[1][1])
+        for a, b in zip(out[mode][2]["iters"], out[1][2]["iters"]):
+            for k in ("m", "P", "T", "pair_tests", "edges", "edges_bound", "colored", "offset"):
+                assert a[k] == b[k], (mode, k)
+    n_full = len(full_path_iters(out[2][2]))
+    assert out[1][2]["csr_refills"] == 0 and out[0][2]["csr_refills"] == 0
+    assert out[2][2]["csr_refills"] == n_full
+
+
+def test_batch_bound_sums_instances():
+    cfgs = wl.batch_instances(24, seed=5)
+    insts = [wl.make(c) for c in cfgs]
+    with pk.PicassoBatch([(x, z, c.q) for (x, z), c in zip(insts, cfgs)]) as hb:
+        hb.color_batch([c.seed for c in cfgs], 0.125, 2.0, [c.relation for c in cfgs])
+        st = hb.stats()
+    for it in full_path_iters(st):
+        assert it["edges"] <= it["edges_bound"] <= it["pair_tests"], it
+    assert st["csr_refills"] == 0
