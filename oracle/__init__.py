@@ -91,6 +91,10 @@ def lib() -> ctypes.CDLL:
         L.orc_color_dynamic.restype = i64
         L.orc_greedy_dynamic.argtypes = [i64, p, i32, p, i64, u64, u32, p, p]
         L.orc_greedy_dynamic.restype = i64
+        L.orc_greedy_dynamic_rounds.argtypes = [i64, p, p, i32, p, i64, u64, u32, i32, p, p]
+        L.orc_greedy_dynamic_rounds.restype = i64
+        L.orc_color_dynamic_rounds.argtypes = [i64, i32, p, p, u64, dbl, dbl, i32, i32, i32, p, p, i32, p]
+        L.orc_color_dynamic_rounds.restype = i64
         _lib = L
     return _lib
 
@@ -233,19 +237,43 @@ def greedy_dynamic(lists: np.ndarray, edges: np.ndarray, seed: int, ell: int):
     return col[:m], order[:m]
 
 
+def greedy_dynamic_rounds(ids: np.ndarray, lists: np.ndarray, edges: np.ndarray, seed: int, ell: int,
+                          divisor: int):
+    """The round form of Alg. 2 on a supplied graph (ids: original ids, which
+    key the draws).  Returns (colours[m] int32, -1 where the list emptied;
+    rounds)."""
+    ids = np.ascontiguousarray(ids, dtype=np.int32)
+    lists = np.ascontiguousarray(lists, dtype=np.uint32)
+    edges = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
+    m, T = lists.shape
+    col = np.zeros(max(m, 1), dtype=np.int32)
+    nr = ctypes.c_int32()
+    rc = lib().orc_greedy_dynamic_rounds(m, _ptr(ids), _ptr(lists), T, _ptr(edges), edges.shape[0], seed, ell,
+                                         divisor, _ptr(col), ctypes.byref(nr))
+    if rc < 0:
+        raise MemoryError("oracle: allocation failed")
+    return col[:m], nr.value
+
+
 def color(x: np.ndarray, z: np.ndarray, q: int, seed: int, frac: float, alpha: float, rel: int,
-          fixed_T: int = 0, max_stats: int = 4096, dynamic: bool = False):
+          fixed_T: int = 0, max_stats: int = 4096, dynamic: bool = False, rounds_divisor: int = 0):
     """Full Picasso iteration.  Returns (n_colors, colors[n] int32, stats list).
     dynamic: colour each conflict graph by Alg. 2 instead of the static
-    random order."""
+    random order; rounds_divisor > 0 (with dynamic): by the round form of
+    Alg. 2 with that divisor."""
     x = np.ascontiguousarray(x, dtype=np.uint64).reshape(-1, _words(q))
     z = np.ascontiguousarray(z, dtype=np.uint64).reshape(-1, _words(q))
     n = x.shape[0]
     out = np.zeros(max(n, 1), dtype=np.int32)
     stats = (IterStat * max_stats)()
     nit = ctypes.c_int32()
-    fn = lib().orc_color_dynamic if dynamic else lib().orc_color
-    nc = fn(n, q, _ptr(x), _ptr(z), seed, frac, alpha, rel, fixed_T, _ptr(out), stats, max_stats, ctypes.byref(nit))
+    if dynamic and rounds_divisor > 0:
+        nc = lib().orc_color_dynamic_rounds(n, q, _ptr(x), _ptr(z), seed, frac, alpha, rel, fixed_T, rounds_divisor,
+                                            _ptr(out), stats, max_stats, ctypes.byref(nit))
+    else:
+        fn = lib().orc_color_dynamic if dynamic else lib().orc_color
+        nc = fn(n, q, _ptr(x), _ptr(z), seed, frac, alpha, rel, fixed_T, _ptr(out), stats, max_stats,
+                ctypes.byref(nit))
     if nc < 0:
         raise MemoryError("oracle: allocation failed")
     st = [

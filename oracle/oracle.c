@@ -626,6 +626,165 @@ int64_t orc_greedy_dynamic(int64_t m, const uint32_t *lists, int32_t T, const in
 }
 
 /* ------------------------------------------------------------------------ */
+/* A round form of Alg. 2 for parallel execution.  Alg. 2 takes one vertex   */
+/* at a time, the one with the shortest remaining list, gives it a random    */
+/* colour of its list and removes that colour from its neighbours' lists.   */
+/* Here many vertices move per round (a reading for parallel hardware; the  */
+/* result differs from the sequential order, so it has its own oracle):     */
+/*  1. active vertices: uncoloured and not failed; one whose list is empty   */
+/*     fails (stays uncoloured for the next iteration of Alg. 1);           */
+/*  2. R = max(ceil(A / divisor), min(A, 64)) of the A active vertices      */
+/*     request a colour: those with the shortest lists, by the smallest     */
+/*     size s* whose cumulative count reaches R; of the vertices with       */
+/*     exactly s* colours left, those whose key h = high 32 bits of         */
+/*     H(seed; id, round, ell, "DYNK") is below cut = floor(need 2^32 / eq) */
+/*     (need = R minus the vertices with fewer colours, eq = the vertices   */
+/*     with exactly s*; need = eq takes all of them);                       */
+/*  3. a requester asks for entry floor(r size / 2^64) of its remaining     */
+/*     list in ascending colour order, r = H(seed; id, round, ell, "DYNC");  */
+/*  4. each colour's requesters, in ascending (size, h, vertex) order, take */
+/*     the colour unless a conflict neighbour took it earlier in this       */
+/*     order (requesters of one colour share it, so conflict = relation);  */
+/*  5. every conflict neighbour of a vertex that took colour c loses c from */
+/*     its list.                                                            */
+/* id is the vertex's original id, so the result does not depend on where  */
+/* the vertex sits in the iteration's vertex set.                          */
+/* ------------------------------------------------------------------------ */
+#define ORC_TAG_DYNK 0x44594E4Bu
+#define ORC_TAG_DYNC 0x44594E43u
+
+typedef struct {
+    uint32_t colour;
+    uint64_t key;
+    int32_t v;
+} orc_request;
+
+static int cmp_request(const void *a, const void *b)
+{
+    const orc_request *x = (const orc_request *)a, *y = (const orc_request *)b;
+    if (x->colour != y->colour) return x->colour < y->colour ? -1 : 1;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    return (x->v > y->v) - (x->v < y->v);
+}
+
+static int64_t greedy_rounds_csr(int64_t m, const int32_t *ids, const uint32_t *lists, int32_t T,
+                                 const int64_t *rowptr, const int32_t *adj, uint64_t seed, uint32_t ell,
+                                 int32_t divisor, int32_t *col, int32_t *n_rounds)
+{
+    char *alive = (char *)malloc((size_t)(m * T > 0 ? m * T : 1));
+    int32_t *size = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
+    char *failed = (char *)calloc((size_t)(m > 0 ? m : 1), 1);
+    int32_t *took = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t)); /* round it took its colour */
+    int64_t *hist = (int64_t *)malloc((size_t)(T + 1) * sizeof(int64_t));
+    orc_request *req = (orc_request *)malloc((size_t)(m > 0 ? m : 1) * sizeof(orc_request));
+    if (!alive || !size || !failed || !took || !hist || !req) {
+        free(alive); free(size); free(failed); free(took); free(hist); free(req);
+        return -1;
+    }
+    for (int64_t i = 0; i < m * T; i++) alive[i] = 1;
+    for (int64_t v = 0; v < m; v++) {
+        size[v] = T;
+        col[v] = -1;
+        took[v] = -1;
+    }
+    int64_t colored = 0;
+    int32_t round = 0;
+    for (;; round++) {
+        int64_t A = 0;
+        for (int32_t s = 0; s <= T; s++) hist[s] = 0;
+        for (int64_t v = 0; v < m; v++) {
+            if (col[v] >= 0 || failed[v]) continue;
+            if (size[v] == 0) {
+                failed[v] = 1;
+                continue;
+            }
+            hist[size[v]]++;
+            A++;
+        }
+        if (A == 0) break;
+        int64_t R = (A + divisor - 1) / divisor;
+        const int64_t floor_r = A < 64 ? A : 64;
+        if (R < floor_r) R = floor_r;
+        int64_t below = 0, eq = 0;
+        int32_t sstar = T;
+        for (int32_t s = 1; s <= T; s++) {
+            if (below + hist[s] >= R) {
+                sstar = s;
+                eq = hist[s];
+                break;
+            }
+            below += hist[s];
+        }
+        const int64_t need = R - below;
+        const uint64_t cut = need >= eq ? ((uint64_t)1 << 32) : ((uint64_t)need << 32) / (uint64_t)eq;
+        int64_t nreq = 0;
+        for (int64_t v = 0; v < m; v++) {
+            if (col[v] >= 0 || failed[v]) continue;
+            const uint64_t h = orc_hash64(seed, (uint32_t)ids[v], (uint32_t)round, ell, ORC_TAG_DYNK) >> 32;
+            if (!(size[v] < sstar || (size[v] == sstar && h < cut))) continue;
+            const uint64_t r = orc_hash64(seed, (uint32_t)ids[v], (uint32_t)round, ell, ORC_TAG_DYNC);
+            int64_t j = (int64_t)mul_high64(r, (uint64_t)size[v]);
+            int32_t k = 0;
+            for (; k < T; k++)
+                if (alive[v * T + k] && j-- == 0) break;
+            req[nreq].colour = lists[v * T + k];
+            req[nreq].key = ((uint64_t)size[v] << 32) | h;
+            req[nreq].v = (int32_t)v;
+            nreq++;
+        }
+        qsort(req, (size_t)nreq, sizeof(orc_request), cmp_request);
+        for (int64_t i = 0; i < nreq; i++) {
+            const int32_t u = req[i].v;
+            const uint32_t c = req[i].colour;
+            int ok = 1;
+            for (int64_t e = rowptr[u]; e < rowptr[u + 1] && ok; e++) {
+                const int32_t w = adj[e];
+                if (took[w] == round && col[w] == (int32_t)c) ok = 0;
+            }
+            if (ok) {
+                col[u] = (int32_t)c;
+                took[u] = round;
+                colored++;
+            }
+        }
+        for (int64_t i = 0; i < nreq; i++) {
+            const int32_t u = req[i].v;
+            if (took[u] != round) continue;
+            const uint32_t c = (uint32_t)col[u];
+            for (int64_t e = rowptr[u]; e < rowptr[u + 1]; e++) {
+                const int32_t w = adj[e];
+                for (int32_t k = 0; k < T; k++)
+                    if (lists[(int64_t)w * T + k] == c) {
+                        if (alive[(int64_t)w * T + k]) {
+                            alive[(int64_t)w * T + k] = 0;
+                            size[w]--;
+                        }
+                        break;
+                    }
+            }
+        }
+    }
+    if (n_rounds) *n_rounds = round;
+    free(alive); free(size); free(failed); free(took); free(hist); free(req);
+    return colored;
+}
+
+/* Exported: the round form on an edge list (for tests that supply their own
+ * graph).  ids[m]: the vertices' original ids (they key the draws). */
+int64_t orc_greedy_dynamic_rounds(int64_t m, const int32_t *ids, const uint32_t *lists, int32_t T, const int32_t *uv,
+                                  int64_t ne, uint64_t seed, uint32_t ell, int32_t divisor, int32_t *col,
+                                  int32_t *n_rounds)
+{
+    int64_t *rowptr;
+    int32_t *adj;
+    if (divisor < 1 || build_csr(m, uv, ne, &rowptr, &adj)) return -1;
+    int64_t rc = greedy_rounds_csr(m, ids, lists, T, rowptr, adj, seed, ell, divisor, col, n_rounds);
+    free(rowptr);
+    free(adj);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
 /* The iteration (Alg. 1): estimate (P, T), draw lists, build the conflict    */
 /* graph, colour it, and recurse on the uncoloured vertices with a fresh      */
 /* palette.  Reading of the garbled palette indices: iteration ell uses the  */
@@ -640,13 +799,14 @@ typedef struct {
  * up to max_stats per-iteration records; *n_iters the iteration count. */
 static int64_t color_driver(int64_t n, int32_t q, const uint64_t *x, const uint64_t *z, uint64_t seed,
                             double frac, double alpha, int32_t rel, int32_t fixed_T, int32_t dynamic,
-                            int32_t *out_colors, orc_iter_stat *stats, int32_t max_stats, int32_t *n_iters);
+                            int32_t divisor, int32_t *out_colors, orc_iter_stat *stats, int32_t max_stats,
+                            int32_t *n_iters);
 
 int64_t orc_color(int64_t n, int32_t q, const uint64_t *x, const uint64_t *z, uint64_t seed, double frac,
                   double alpha, int32_t rel, int32_t fixed_T, int32_t *out_colors, orc_iter_stat *stats,
                   int32_t max_stats, int32_t *n_iters)
 {
-    return color_driver(n, q, x, z, seed, frac, alpha, rel, fixed_T, 0, out_colors, stats, max_stats, n_iters);
+    return color_driver(n, q, x, z, seed, frac, alpha, rel, fixed_T, 0, 0, out_colors, stats, max_stats, n_iters);
 }
 
 /* Alg. 1 with the dynamic-order colourer of Alg. 2 in place of the static
@@ -655,12 +815,24 @@ int64_t orc_color_dynamic(int64_t n, int32_t q, const uint64_t *x, const uint64_
                           double alpha, int32_t rel, int32_t fixed_T, int32_t *out_colors, orc_iter_stat *stats,
                           int32_t max_stats, int32_t *n_iters)
 {
-    return color_driver(n, q, x, z, seed, frac, alpha, rel, fixed_T, 1, out_colors, stats, max_stats, n_iters);
+    return color_driver(n, q, x, z, seed, frac, alpha, rel, fixed_T, 1, 0, out_colors, stats, max_stats, n_iters);
+}
+
+/* Alg. 1 with the round form of Alg. 2 (divisor >= 1: about one active
+ * vertex in `divisor` requests a colour per round). */
+int64_t orc_color_dynamic_rounds(int64_t n, int32_t q, const uint64_t *x, const uint64_t *z, uint64_t seed,
+                                 double frac, double alpha, int32_t rel, int32_t fixed_T, int32_t divisor,
+                                 int32_t *out_colors, orc_iter_stat *stats, int32_t max_stats, int32_t *n_iters)
+{
+    if (divisor < 1) return -1;
+    return color_driver(n, q, x, z, seed, frac, alpha, rel, fixed_T, 2, divisor, out_colors, stats, max_stats,
+                        n_iters);
 }
 
 static int64_t color_driver(int64_t n, int32_t q, const uint64_t *x, const uint64_t *z, uint64_t seed,
                             double frac, double alpha, int32_t rel, int32_t fixed_T, int32_t dynamic,
-                            int32_t *out_colors, orc_iter_stat *stats, int32_t max_stats, int32_t *n_iters)
+                            int32_t divisor, int32_t *out_colors, orc_iter_stat *stats, int32_t max_stats,
+                            int32_t *n_iters)
 {
     char *chars = (char *)malloc((size_t)(n * q > 0 ? n * q : 1));
     int32_t *ids = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
@@ -694,7 +866,9 @@ static int64_t color_driver(int64_t n, int32_t q, const uint64_t *x, const uint6
         int64_t tests = 0;
         int64_t ne = conflict_edges_by_colour(q, m, ids, chars, lists, T, P, rel, 0, P, &eb, &tests);
         int failed = ne < 0;
-        if (!failed && dynamic) failed = orc_greedy_dynamic(m, lists, T, eb.uv, ne, seed, ell, col, NULL) < 0;
+        if (!failed && dynamic == 2)
+            failed = orc_greedy_dynamic_rounds(m, ids, lists, T, eb.uv, ne, seed, ell, divisor, col, NULL) < 0;
+        else if (!failed && dynamic) failed = orc_greedy_dynamic(m, lists, T, eb.uv, ne, seed, ell, col, NULL) < 0;
         else if (!failed) failed = orc_greedy_from_edges(m, prio, lists, T, P, eb.uv, ne, col) != 0;
         if (failed) {
             free(eb.uv); free(lists); free(prio); free(col); free(used); free(chars); free(ids);

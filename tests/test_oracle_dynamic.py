@@ -121,3 +121,111 @@ def test_full_run_with_dynamic_colourer(orc, rel):
         k = iteration_of(st, int(col[v]))
         L = orc.sample_list(6, k + 1, v, st[k]["P"], st[k]["T"])
         assert col[v] - st[k]["offset"] in L.tolist()
+
+
+# ---------------------------------------------------------------- round form
+TAG_DYNK, TAG_DYNC = 0x44594E4B, 0x44594E43
+
+
+def rounds_replay(orc, ids, lists, edges, seed, ell, divisor):
+    """The round form's rules, restated in plain Python (tiny graphs)."""
+    m, T = lists.shape
+    nbr = [set() for _ in range(m)]
+    for a, b in edges:
+        nbr[a].add(int(b))
+        nbr[b].add(int(a))
+    alive = [list(int(c) for c in row) for row in lists]  # ascending remaining colours
+    col = [-1] * m
+    failed = [False] * m
+    rnd = 0
+    while True:
+        for v in range(m):
+            if col[v] < 0 and not failed[v] and not alive[v]:
+                failed[v] = True
+        act = [v for v in range(m) if col[v] < 0 and not failed[v]]
+        if not act:
+            return np.array(col, dtype=np.int32), rnd
+        A = len(act)
+        R = max(-(-A // divisor), min(A, 64))
+        sizes = sorted(len(alive[v]) for v in act)
+        sstar = sizes[R - 1]
+        below = sum(1 for s in sizes if s < sstar)
+        eq = sum(1 for s in sizes if s == sstar)
+        need = R - below
+        cut = 1 << 32 if need >= eq else (need << 32) // eq
+        reqs = []
+        for v in act:
+            s = len(alive[v])
+            h = orc.hash64(seed, int(ids[v]), rnd, ell, TAG_DYNK) >> 32
+            if s < sstar or (s == sstar and h < cut):
+                j = (orc.hash64(seed, int(ids[v]), rnd, ell, TAG_DYNC) * s) >> 64
+                reqs.append((alive[v][j], (s << 32) | h, v))
+        winners = {}
+        for c, key, v in sorted(reqs):
+            if not any(winners.get(u) == c for u in nbr[v]):
+                winners[v] = c
+        for v, c in winners.items():
+            col[v] = c
+        for v, c in winners.items():
+            for u in nbr[v]:
+                if c in alive[u]:
+                    alive[u].remove(c)
+        rnd += 1
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_round_form_follows_its_rules(orc, seed):
+    rng = np.random.default_rng(300 + seed)
+    m, P, T = int(rng.integers(20, 90)), int(rng.integers(4, 20)), 0
+    T = int(rng.integers(1, min(P, 8) + 1))
+    lists, edges = random_instance(rng, m, P, T, float(rng.uniform(0.1, 0.6)))
+    ids = np.sort(rng.choice(10_000, m, replace=False)).astype(np.int32)
+    divisor = int(rng.choice([1, 2, 4, 16]))
+    col, rounds = orc.greedy_dynamic_rounds(ids, lists, edges, seed, 2, divisor)
+    ref, ref_rounds = rounds_replay(orc, ids, lists, edges, seed, 2, divisor)
+    assert np.array_equal(col, ref) and rounds == ref_rounds
+
+
+def test_round_form_valid_and_respects_lists(orc):
+    rng = np.random.default_rng(7)
+    for _ in range(5):
+        m, P, T = 400, 60, 6
+        lists, edges = random_instance(rng, m, P, T, 0.3)
+        ids = np.arange(m, dtype=np.int32)
+        col, _ = orc.greedy_dynamic_rounds(ids, lists, edges, 11, 1, 16)
+        for a, b in edges:
+            assert not (col[a] >= 0 and col[a] == col[b])
+        for v in range(m):
+            assert col[v] == -1 or col[v] in lists[v]
+
+
+def test_round_form_special_graphs(orc):
+    rng = np.random.default_rng(8)
+    m, P, T = 150, 40, 5
+    lists = np.sort(np.array([rng.choice(P, T, replace=False) for _ in range(m)]), axis=1).astype(np.uint32)
+    ids = np.arange(m, dtype=np.int32)
+    # no edges: every vertex takes a colour of its list
+    col, _ = orc.greedy_dynamic_rounds(ids, lists, np.zeros((0, 2), np.int32), 3, 1, 16)
+    assert (col >= 0).all() and all(col[v] in lists[v] for v in range(m))
+    # complete graph, whole palette as every list: each colour at most once,
+    # min(m, P) vertices coloured
+    full = np.tile(np.arange(P, dtype=np.uint32), (m, 1))
+    edges = np.array([(a, b) for a in range(m) for b in range(a + 1, m)], np.int32)
+    col, _ = orc.greedy_dynamic_rounds(ids, full, edges, 3, 1, 4)
+    c = col[col >= 0]
+    assert c.size == min(m, P) and np.unique(c).size == c.size
+
+
+def test_round_form_keeps_most_of_alg2s_gain(orc):
+    """C1, colouring seeds 0-2: whole runs with the round form (divisor 16)
+    use fewer colours than the static order and at most 3% more than the
+    sequential Alg. 2."""
+    cfg = wl.C1
+    x, z = wl.make(cfg)
+    rf, seq, st = [], [], []
+    for seed in range(3):
+        rf.append(orc.color(x, z, cfg.q, seed, cfg.frac, cfg.alpha, 0, dynamic=True, rounds_divisor=16)[0])
+        seq.append(orc.color(x, z, cfg.q, seed, cfg.frac, cfg.alpha, 0, dynamic=True)[0])
+        st.append(orc.color(x, z, cfg.q, seed, cfg.frac, cfg.alpha, 0)[0])
+    assert np.mean(rf) < np.mean(st)
+    assert np.mean(rf) <= 1.03 * np.mean(seq)
