@@ -8,6 +8,8 @@ SHA-256 of the little-endian int32 colour array and the per-iteration sizes.
     python tests/golden/make_golden.py L 7000000     # the first held-out instance
     python tests/golden/make_golden.py C3 [workers]   # the 512-instance batch
     python tests/golden/make_golden.py C4 [workers]   # n = 2,000,000, q = 128, seed 0
+    python tests/golden/make_golden.py C2dyn [divisor] # C2 seed 0, dynamic colourer (round form),
+                                                     # with the sequential Alg. 2 colour count beside it
 
 The C4 run colours each iteration from its colour classes (the oracle's
 edge-free mode: its conflict graph, 3.6e9 edges in iteration 1, does not fit
@@ -135,8 +137,39 @@ def c4_main(workers):
     print(out, nc, flush=True)
 
 
+def c2_dynamic_main(divisor):
+    """C2, seed 0, coloured by the round form of Alg. 2 (the stored result)
+    and by the sequential Alg. 2 and the static order (colour counts)."""
+    cfg = wl.C2
+    oracle.build(force=False)
+    x, z = wl.make(cfg)
+    seed = 0
+    t = time.time()
+    nc, col, st = oracle.color(x, z, cfg.q, seed, cfg.frac, cfg.alpha, cfg.relation, dynamic=True,
+                               rounds_divisor=divisor)
+    secs = round(time.time() - t, 1)
+    print(f"C2 round form (divisor {divisor}): {nc} colours in {secs} s", flush=True)
+    nseq, _, stseq = oracle.color(x, z, cfg.q, seed, cfg.frac, cfg.alpha, cfg.relation, dynamic=True)
+    print(f"C2 sequential Alg. 2: {nseq} colours", flush=True)
+    nst, _, _ = oracle.color(x, z, cfg.q, seed, cfg.frac, cfg.alpha, cfg.relation)
+    rec = {
+        "config": cfg.name, "n": cfg.n, "q": cfg.q, "probs": list(cfg.probs), "gen_seed": cfg.seed, "seed": seed,
+        "frac": cfg.frac, "alpha": cfg.alpha, "relation": cfg.relation, "colourer": "dynamic rounds",
+        "divisor": divisor, "n_colors": nc,
+        "colors_sha256": hashlib.sha256(np.ascontiguousarray(col, dtype="<i4").tobytes()).hexdigest(),
+        "colors_head": col[:32].tolist(), "iters": st, "oracle_seconds": secs,
+        "n_colors_sequential_alg2": nseq, "iterations_sequential_alg2": len(stseq), "n_colors_static": nst,
+    }
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c2_dynamic_seed0.json")
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(out, nc, nseq, nst, flush=True)
+
+
 def main():
     name = sys.argv[1]
+    if name == "C2dyn":
+        return c2_dynamic_main(int(sys.argv[2]) if len(sys.argv) > 2 else 16)
     if name == "C3":
         return batch_main(int(sys.argv[2]) if len(sys.argv) > 2 else 6)
     if name == "C4":
