@@ -277,8 +277,22 @@ def main():
 
     # colour counts over colouring seeds 0-4 (untimed)
     seeds_nc = None
+    dyn = None
     if not batch:
         seeds_nc = [int(h.color_device(out, sd, cfg.frac, cfg.alpha, cfg.relation)) for sd in range(5)]
+        # the dynamic-order colourer (Alg. 2 in rounds) on the same workload:
+        # colours and end-to-end time beside the static order's
+        h.set_option(pk.OPT_COLOURER, pk.COLOURER_DYNAMIC)
+        h.color_device(out, *run_args)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ncd = int(h.color_device(out, *run_args))
+        torch.cuda.synchronize()
+        sd_ = h.stats()
+        dyn = {"n_colors": ncd, "ms": (time.perf_counter() - t1) * 1e3, "iterations": sd_["n_iters"],
+               "rounds": sum(it["jp_rounds"] for it in sd_["iters"]), "divisor": 16,
+               "ms_color": sum(it["ms_color"] for it in sd_["iters"])}
+        h.set_option(pk.OPT_COLOURER, pk.COLOURER_STATIC)
 
     workload["pair_path"] = args.path
     if tuned:
@@ -313,6 +327,8 @@ def main():
     }
     if seeds_nc:
         line["n_colors_seeds_0_4"] = {"n_colors": seeds_nc, "mean": sum(seeds_nc) / len(seeds_nc)}
+    if dyn:
+        line["dynamic_colourer"] = dyn
     h.close()
     params = np.load(learn.PREDICTOR) if os.path.exists(learn.PREDICTOR) else None
     if params is not None and params.shape != (pk.MLP_NPARAMS,):

@@ -98,7 +98,7 @@ enum {
                                    record which (picasso_stats.judged) and the
                                    time of both runs.  0 (default): the
                                    network's result only.                     */
-    PICASSO_OPT_CSR_SIZING = 11 /* colouring calls: 1 (default) = each iteration's
+    PICASSO_OPT_CSR_SIZING = 11, /* colouring calls: 1 (default) = each iteration's
                                    CSR buffer is sized by the predicted bound on
                                    |E_c| (picasso_iter_stats.edges_bound) and
                                    filled without waiting for the exact size;
@@ -108,7 +108,48 @@ enum {
                                    fill.  2 = the bound taken as zero, so every
                                    iteration refills (tests that path).
                                    Results are identical.                     */
+    PICASSO_OPT_COLOURER = 12,  /* list colouring of each iteration:
+                                   PICASSO_COLOURER_STATIC (default) or
+                                   PICASSO_COLOURER_DYNAMIC                   */
+    PICASSO_OPT_DYN_DIVISOR = 13, /* dynamic colourer: about one active vertex in
+                                   this many requests a colour per round
+                                   (1..2^20; 16).  Larger: closer to the
+                                   sequential order, more rounds.             */
+    PICASSO_OPT_BUCKET_BUILD = 15, /* colour buckets: 0 (default) auto, 1 = an
+                                   atomic count and scatter per list entry,
+                                   then a sort of each bucket by priority;
+                                   2 = a stable radix sort (vertices by
+                                   priority, then their entries by colour).
+                                   Auto takes the radix sort from 2^20 list
+                                   entries.  Results are identical.           */
+    PICASSO_OPT_EDGES = 14      /* colouring calls: 1 (default) = each iteration
+                                   also counts its conflict edges and writes its
+                                   CSR (min-shared-colour dedup, counts, fill);
+                                   0 = only the per-bucket relation matrices the
+                                   colouring reads are built, and the edge
+                                   statistics of those iterations are -1.  The
+                                   colours are identical.  For long lists over
+                                   small palettes (buckets of thousands of
+                                   members, e.g. palette 3%, alpha 30) the dedup
+                                   dominates the run time.                    */
 };
+
+/* Colourers (PICASSO_OPT_COLOURER). */
+#define PICASSO_COLOURER_STATIC 0  /* random static order, smallest free list
+                                      colour (Sec. IV-B, static order schemes):
+                                      equals the sequential greedy in
+                                      (priority, id) order                    */
+#define PICASSO_COLOURER_DYNAMIC 1 /* dynamic order, Alg. 2 (Sec. IV-B): the
+                                      shortest remaining lists first, a random
+                                      colour of the list, the colour removed
+                                      from the neighbours' lists; run in rounds
+                                      in which about one active vertex in
+                                      PICASSO_OPT_DYN_DIVISOR (those with the
+                                      shortest lists) requests a colour, each
+                                      colour's requesters settled in (size,
+                                      draw, vertex) order.  Deterministic for a
+                                      seed; not the sequential Alg. 2 order.
+                                      Instances do not use the tail kernel.   */
 
 /* picasso_stats.judged */
 #define PICASSO_JUDGE_NONE 0    /* no judge run                               */
@@ -119,7 +160,7 @@ enum {
 #define PICASSO_PATH_VALU 1
 #define PICASSO_PATH_MFMA 2
 
-#define PICASSO_MAX_T 256          /* largest list size the kernels accept   */
+#define PICASSO_MAX_T 1024         /* largest list size the kernels accept   */
 #define PICASSO_MAX_ITER_STATS 256 /* per-iteration records kept in stats    */
 
 /* Per-iteration record. Times are milliseconds (0 unless PICASSO_OPT_TIMING). */
@@ -128,7 +169,8 @@ typedef struct {
     int64_t P;          /* palette size                                       */
     int64_t T;          /* list size                                          */
     int64_t pair_tests; /* sum over colours c of C(|B_c|, 2)                   */
-    int64_t edges;      /* |E_c|, undirected conflict edges                    */
+    int64_t edges;      /* |E_c|, undirected conflict edges (-1: not counted,
+                           PICASSO_OPT_EDGES = 0)                             */
     int64_t edges_bound; /* upper bound on |E_c| predicted before the pair pass
                            from the sampled relation density (sizes the CSR;
                            iterations run in the tail kernel count |E_c|

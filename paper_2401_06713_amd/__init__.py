@@ -21,9 +21,11 @@ REL_QWC = 1
 REL_COMMUTE = 2
 PATH_AUTO, PATH_VALU, PATH_MFMA = 0, 1, 2
 (OPT_MEM_BUDGET, OPT_PAIR_PATH, OPT_FIXED_T, OPT_STREAM, OPT_TIMING, OPT_JP_BATCH, OPT_GRAPH,
- OPT_MFMA_CAP, OPT_TAIL, OPT_LEARNED_JUDGE, OPT_CSR_SIZING) = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11
+ OPT_MFMA_CAP, OPT_TAIL, OPT_LEARNED_JUDGE, OPT_CSR_SIZING, OPT_COLOURER, OPT_DYN_DIVISOR, OPT_EDGES,
+ OPT_BUCKET_BUILD) = range(1, 16)
+COLOURER_STATIC, COLOURER_DYNAMIC = 0, 1
 JUDGE_NONE, JUDGE_LEARNED, JUDGE_FIXED = 0, 1, 2
-MAX_T = 256
+MAX_T = 1024
 MAX_ITER_STATS = 256
 
 EINVAL, ENOMEM, EDEVICE, EINTERNAL = -1, -2, -3, -4

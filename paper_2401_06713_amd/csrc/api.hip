@@ -79,6 +79,10 @@ struct picasso_ctx {
     int64_t mfma_cap = -1;   // largest bucket for the MFMA kernel (-1: as large as LDS allows)
     int32_t use_tail = 1;    // finish instances with few vertices left in the tail kernel
     int32_t judge = 0;       // learned colouring: also run the fixed parameters, keep the better
+    int32_t edges_on = 1;    // colouring calls: count the conflict edges and write the CSR
+    int32_t bucket_build = 0;  // 0 auto, 1 atomics + per-bucket sort, 2 radix sort
+    int32_t colourer = PICASSO_COLOURER_STATIC;
+    int32_t dyn_divisor = 16;  // dynamic colourer: about one active vertex in this many requests per round
     int32_t csr_sizing = 1;  // colouring calls: 1 CSR sized by the predicted bound, 0 by the exact
                              // size, 2 bound forced to zero (every iteration refills; for tests)
     Arena arena;
@@ -87,7 +91,8 @@ struct picasso_ctx {
     DevBuf ids, next_ids, lists, prio, bcnt, bstart, bmem, bslot, pos_of, bent, tmp_mem, tmp_slot, tiles, words, tile_off,
         rb_off, R, D, bx, bz, tile_bucket, nslow, slow, slot_cnt, slot_off, rowptr, adj, col, blk, fre, nblk, st,
         dirty, wake_at, wl, flags, pos, used, scan_tmp, scalars, out_colors, judge_out, inst, vinst, loff, binst,
-        inst_out, tail_recs, tail_table, tail_outs, tail_iters, tail_ranges, hits, csr_flag;
+        inst_out, tail_recs, tail_table, tail_outs, tail_iters, tail_ranges, hits, csr_flag, rkey, dyn_hist, dyn_sstar,
+        dyn_cut, rx_k64a, rx_k64b, rx_va, rx_vb, rx_tmp, rx_tr, rx_at, rx_cka, rx_ckb, rx_cva, rx_cvb;
     std::vector<InstRec> h_inst;  // table of the active instances (kept until the copy has completed)
     picasso_stats stats;
     std::vector<picasso_instance_stats> istats;
@@ -234,16 +239,45 @@ BucketInfo buckets_from_lists(picasso_ctx *h, Batch &b, int64_t m, int64_t E, in
     uint32_t *bcnt = buf<uint32_t>(h, h->bcnt, (size_t)P);
     int64_t *bstart = buf<int64_t>(h, h->bstart, (size_t)P + 1);
     unsigned long long *sc = buf<unsigned long long>(h, h->scalars, 8);
-    launch_fill_u32(bcnt, P, 0u, st);
     launch_fill_u64(reinterpret_cast<uint64_t *>(sc), 8, 0ull, st);
-    launch_bucket_count(lists, E, bcnt, st);
-    launch_bucket_pairs(bcnt, P, sc, st);
     void *tmp = h->arena.ensure(h->scan_tmp, scan_tmp_bytes(std::max<int64_t>(P, E) + 1));
-    exclusive_scan_u32_to_i64(bcnt, bstart, P, true, tmp, st);
-    launch_fill_u32(bcnt, P, 0u, st);
     uint32_t *bmem = buf<uint32_t>(h, h->bmem, (size_t)std::max<int64_t>(E, 1));
-    uint8_t *bslot = buf<uint8_t>(h, h->bslot, (size_t)std::max<int64_t>(E, 1));
-    launch_bucket_scatter(lists, m, b.loff, bstart, bcnt, bmem, bslot, st);
+    slot_t *bslot = buf<slot_t>(h, h->bslot, (size_t)std::max<int64_t>(E, 1));
+    int64_t *pos_of = buf<int64_t>(h, h->pos_of, (size_t)std::max<int64_t>(E, 1));
+    int64_t *bent = buf<int64_t>(h, h->bent, (size_t)std::max<int64_t>(E, 1));
+    const bool radix = E > 0 && E < ((int64_t)1 << 32) &&
+                       (h->bucket_build == 2 || (h->bucket_build == 0 && E >= kRadixMinEntries));
+    if (radix) {
+        // vertices in (priority, index) order, their entries in that order,
+        // then a stable sort by colour: sorted buckets in one pass per digit
+        uint64_t *k64a = buf<uint64_t>(h, h->rx_k64a, (size_t)m), *k64b = buf<uint64_t>(h, h->rx_k64b, (size_t)m);
+        uint32_t *va = buf<uint32_t>(h, h->rx_va, (size_t)m), *vb = buf<uint32_t>(h, h->rx_vb, (size_t)m);
+        void *rtmp = h->arena.ensure(h->rx_tmp, radix_tmp_bytes(std::max<int64_t>(m, E)));
+        PCHECK_HIP(hipMemcpyAsync(k64a, prio, (size_t)m * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+        launch_iota_u32(va, m, st);
+        const int f1 = radix_sort_pairs<uint64_t>(k64a, va, k64b, vb, m, 0, 64, rtmp, st);
+        const uint32_t *perm = f1 ? vb : va;
+        int32_t *tr = buf<int32_t>(h, h->rx_tr, (size_t)m);
+        int64_t *at = buf<int64_t>(h, h->rx_at, (size_t)m + 1);
+        launch_ranked_sizes(perm, m, b.loff, tr, st);
+        exclusive_scan_i32_to_i64(tr, at, m, true, tmp, st);
+        uint32_t *cka = buf<uint32_t>(h, h->rx_cka, (size_t)E), *ckb = buf<uint32_t>(h, h->rx_ckb, (size_t)E);
+        uint32_t *cva = buf<uint32_t>(h, h->rx_cva, (size_t)E), *cvb = buf<uint32_t>(h, h->rx_cvb, (size_t)E);
+        launch_emit_ranked(perm, m, b.loff, at, lists, cka, cva, E, st);
+        int bits = 1;
+        while (bits < 32 && ((int64_t)1 << bits) < P) ++bits;
+        const int f2 = radix_sort_pairs<uint32_t>(cka, cva, ckb, cvb, E, 0, (bits + 7) & ~7, rtmp, st);
+        launch_bucket_from_sorted(b, f2 ? ckb : cka, f2 ? cvb : cva, E, P, bstart, bcnt, bmem, bslot, pos_of, bent,
+                                  st);
+        launch_bucket_pairs(bcnt, P, sc, st);
+    } else {
+        launch_fill_u32(bcnt, P, 0u, st);
+        launch_bucket_count(lists, E, bcnt, st);
+        launch_bucket_pairs(bcnt, P, sc, st);
+        exclusive_scan_u32_to_i64(bcnt, bstart, P, true, tmp, st);
+        launch_fill_u32(bcnt, P, 0u, st);
+        launch_bucket_scatter(lists, m, b.loff, bstart, bcnt, bmem, bslot, st);
+    }
     int32_t *binst = buf<int32_t>(h, h->binst, (size_t)P);
     launch_bucket_table(b, P, binst, st);
     b.binst = binst;
@@ -272,12 +306,12 @@ BucketInfo buckets_from_lists(picasso_ctx *h, Batch &b, int64_t m, int64_t E, in
     if (bi.max_size > (int64_t)1 << 17)
         throw Error(PICASSO_EINVAL, "a colour bucket holds " + std::to_string(bi.max_size) +
                                         " vertices (limit 131072): palette too small for this many vertices");
-    const bool large = bi.max_size > 2048;
-    uint32_t *tmem = large ? buf<uint32_t>(h, h->tmp_mem, (size_t)E) : nullptr;
-    uint8_t *tslot = large ? buf<uint8_t>(h, h->tmp_slot, (size_t)E) : nullptr;
-    int64_t *pos_of = buf<int64_t>(h, h->pos_of, (size_t)std::max<int64_t>(E, 1));
-    int64_t *bent = buf<int64_t>(h, h->bent, (size_t)std::max<int64_t>(E, 1));
-    launch_bucket_sort(bstart, P, bmem, bslot, prio, pos_of, bent, b.loff, large, tmem, tslot, st);
+    if (!radix) {
+        const bool large = bi.max_size > 2048;
+        uint32_t *tmem = large ? buf<uint32_t>(h, h->tmp_mem, (size_t)E) : nullptr;
+        slot_t *tslot = large ? buf<slot_t>(h, h->tmp_slot, (size_t)E) : nullptr;
+        launch_bucket_sort(bstart, P, bmem, bslot, prio, pos_of, bent, b.loff, large, tmem, tslot, st);
+    }
     return bi;
 }
 
@@ -297,11 +331,12 @@ BucketInfo build_lists_and_buckets(picasso_ctx *h, Batch &b, uint32_t ell, int64
 // relation pair is a conflict edge when the two lists share a colour (Alg. 1
 // construct_conflict_graph), and two uniform T-subsets of P colours meet with
 // probability s = 1 - C(P-T, T) / C(P, T), so E|E_c| = C(m, 2) rho s.  The
-// bound takes rho four standard errors high, adds six standard deviations of
-// |E_c| (edges at one vertex are dependent through its list: variance about
-// the mean times 1 + 2 m rho T / P) and is never above the iteration's pair
-// tests, which bound |E_c| exactly (each edge is a pair of the bucket of its
-// smallest shared colour).
+// indicators of two pairs are independent even when the pairs share a
+// vertex (a uniform T-subset meets every fixed T-subset with the same
+// probability s), so |E_c| has variance C(m, 2) rho s (1 - s).  The bound
+// takes rho four standard errors high, adds six standard deviations of
+// |E_c|, and is never above the iteration's pair tests, which bound |E_c|
+// exactly (each edge is a pair of the bucket of its smallest shared colour).
 int64_t conflict_edge_bound(const std::vector<InstRec> &recs, const uint32_t *hits, int32_t K, int64_t pair_tests)
 {
     double total = 0.0;
@@ -317,7 +352,7 @@ int64_t conflict_edge_bound(const std::vector<InstRec> &recs, const uint32_t *hi
         const double rho_hi =
             std::min(1.0, rho + 4.0 * std::sqrt(std::max(rho * (1.0 - rho), 1.0 / K) / (double)K));
         const double mu = 0.5 * m * (m - 1.0) * rho_hi * share;
-        total += mu + 6.0 * std::sqrt(mu * (1.0 + 2.0 * m * rho_hi * T / P)) + 64.0;
+        total += mu + 6.0 * std::sqrt(mu * (1.0 - share)) + 64.0;
     }
     const double capped = std::min(total, (double)pair_tests);
     return (int64_t)std::ceil(capped);
@@ -330,7 +365,7 @@ CsrArgs csr_args(picasso_ctx *h, const Batch &b, int64_t P)
     CsrArgs ca{};
     ca.bstart = static_cast<const int64_t *>(h->bstart.p);
     ca.bmem = static_cast<const uint32_t *>(h->bmem.p);
-    ca.bslot = static_cast<const uint8_t *>(h->bslot.p);
+    ca.bslot = static_cast<const slot_t *>(h->bslot.p);
     ca.P = P;
     ca.rb_off = static_cast<const int64_t *>(h->rb_off.p);
     ca.R = static_cast<const uint64_t *>(h->R.p);
@@ -347,7 +382,8 @@ CsrArgs csr_args(picasso_ctx *h, const Batch &b, int64_t P)
 // h->slot_off.
 int64_t build_conflict_graph(picasso_ctx *h, const Batch &b, int64_t m, int64_t E, int64_t P, int32_t T_max,
                              int32_t rel_mask, const BucketInfo &bi, double *ms_relate, double *ms_csr,
-                             bool *used_mfma = nullptr, bool csr_required = true, int64_t edge_bound = -1)
+                             bool *used_mfma = nullptr, bool csr_required = true, int64_t edge_bound = -1,
+                             bool want_edges = true)
 {
     hipStream_t st = h->stream;
     Timer tm(h);
@@ -392,6 +428,12 @@ int64_t build_conflict_graph(picasso_ctx *h, const Batch &b, int64_t m, int64_t 
     }
     if (used_mfma) *used_mfma = any_mfma;
     tm.mark();
+    if (!want_edges) {
+        // the colouring reads the relation matrices only
+        if (ms_relate) *ms_relate = tm.ms(0, 1);
+        if (ms_csr) *ms_csr = 0.0;
+        return -1;
+    }
     // pairs sharing a smaller colour
     launch_fill_u64(D, bi.words, 0ull, st);
     int32_t *nslow = buf<int32_t>(h, h->nslow, 16);
@@ -399,7 +441,7 @@ int64_t build_conflict_graph(picasso_ctx *h, const Batch &b, int64_t m, int64_t 
     DupArgs da{};
     da.bstart = ra.bstart;
     da.bmem = ra.bmem;
-    da.bslot = static_cast<const uint8_t *>(h->bslot.p);
+    da.bslot = static_cast<const slot_t *>(h->bslot.p);
     da.P = P;
     da.rb_off = ra.rb_off;
     da.lists = static_cast<const uint32_t *>(h->lists.p);
@@ -477,16 +519,24 @@ struct RoundGraph {
     }
 };
 
+// One batch of rounds from list `start`: begin, the rounds, end.
+void launch_jp_batch(picasso_ctx *h, const JpArgs &j, int32_t rounds, int start)
+{
+    launch_jp_batch_begin(j, rounds, h->stream);
+    int cur = start;
+    for (int32_t r = 0; r < rounds; ++r) {
+        launch_jp_round(j, cur, r, h->stream);
+        cur ^= 1;
+    }
+    launch_jp_batch_end(j, rounds, h->stream);
+}
+
 void capture_rounds(picasso_ctx *h, const JpArgs &j, RoundGraph &g, int32_t rounds, int start)
 {
     hipGraph_t graph = nullptr;
     PCHECK_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-    int cur = start;
     try {
-        for (int r = 0; r < rounds; ++r) {
-            launch_jp_round(j, cur, h->stream);
-            cur ^= 1;
-        }
+        launch_jp_batch(h, j, rounds, start);
     } catch (...) {
         (void)hipStreamEndCapture(h->stream, &graph);
         if (graph) (void)hipGraphDestroy(graph);
@@ -508,7 +558,7 @@ int32_t color_buckets(picasso_ctx *h, const Batch &b, int64_t m, int64_t E, int6
     j.P = P;
     j.bstart = static_cast<const int64_t *>(h->bstart.p);
     j.bmem = static_cast<const uint32_t *>(h->bmem.p);
-    j.bslot = static_cast<const uint8_t *>(h->bslot.p);
+    j.bslot = static_cast<const slot_t *>(h->bslot.p);
     j.rb_off = static_cast<const int64_t *>(h->rb_off.p);
     j.R = static_cast<const uint64_t *>(h->R.p);
     j.lists = static_cast<const uint32_t *>(h->lists.p);
@@ -523,12 +573,10 @@ int32_t color_buckets(picasso_ctx *h, const Batch &b, int64_t m, int64_t E, int6
     j.st = buf<uint8_t>(h, h->st, (size_t)std::max<int64_t>(E, 1));
     j.dirty = buf<uint32_t>(h, h->dirty, (size_t)P);
     j.wake_at = buf<unsigned long long>(h, h->wake_at, (size_t)P);
-    int32_t *wl = buf<int32_t>(h, h->wl, (size_t)2 * P + 4);
+    int32_t *wl = buf<int32_t>(h, h->wl, (size_t)2 * P + kJpSlots);
     j.wl[0] = wl;
     j.wl[1] = wl + P;
-    j.wl_count = wl + 2 * P;
-    j.ticket = reinterpret_cast<uint32_t *>(wl + 2 * P + 2);
-    launch_fill_i32(wl + 2 * P + 2, 1, 0, st);
+    j.wl_slots = wl + 2 * P;
     unsigned long long *sc = buf<unsigned long long>(h, h->scalars, 8);
     j.progress = sc + 2;
     j.m = m;
@@ -553,16 +601,14 @@ int32_t color_buckets(picasso_ctx *h, const Batch &b, int64_t m, int64_t E, int6
             PCHECK_HIP(hipGraphLaunch(graph.exec[cur], st));
             if (batch & 1) cur ^= 1;
         } else {
-            for (int r = 0; r < batch; ++r) {
-                launch_jp_round(j, cur, st);
-                cur ^= 1;
-            }
+            launch_jp_batch(h, j, batch, cur);
+            if (batch & 1) cur ^= 1;
         }
         rounds += batch;
         unsigned long long done = 0;
         int32_t pending = 0;
         PCHECK_HIP(hipMemcpyAsync(&done, j.progress, sizeof(done), hipMemcpyDeviceToHost, st));
-        PCHECK_HIP(hipMemcpyAsync(&pending, &j.wl_count[cur], sizeof(pending), hipMemcpyDeviceToHost, st));
+        PCHECK_HIP(hipMemcpyAsync(&pending, &j.wl_slots[kJpCountCell], sizeof(pending), hipMemcpyDeviceToHost, st));
         PCHECK_HIP(hipStreamSynchronize(st));
         if ((int64_t)done >= m) break;
         if (pending == 0) {
@@ -580,6 +626,56 @@ int32_t color_buckets(picasso_ctx *h, const Batch &b, int64_t m, int64_t E, int6
         batch = std::min<int32_t>(batch * 2, max_batch);
     }
     return rounds;
+}
+
+// Dynamic-order colouring (the round form of Alg. 2) until every vertex is
+// coloured or has lost its whole list.  Result in h->col; returns rounds.
+int32_t color_buckets_dynamic(picasso_ctx *h, const Batch &b, uint32_t ell, int64_t m, int64_t E, int64_t P,
+                              int32_t T_max, const BucketInfo &bi)
+{
+    hipStream_t st = h->stream;
+    DynArgs a{};
+    a.b = b;
+    a.m = m;
+    a.P = P;
+    a.ids = static_cast<const int32_t *>(h->ids.p);
+    a.pos_of = static_cast<const int64_t *>(h->pos_of.p);
+    a.bstart = static_cast<const int64_t *>(h->bstart.p);
+    a.bmem = static_cast<const uint32_t *>(h->bmem.p);
+    a.bslot = static_cast<const slot_t *>(h->bslot.p);
+    a.rb_off = static_cast<const int64_t *>(h->rb_off.p);
+    a.R = static_cast<const uint64_t *>(h->R.p);
+    a.nw_max = std::max<int64_t>((bi.max_size + 63) / 64, 1);
+    a.fw = (T_max + 63) / 64;
+    a.alive = buf<uint64_t>(h, h->blk, (size_t)m * a.fw);
+    a.size = buf<int32_t>(h, h->nblk, (size_t)std::max<int64_t>(m, 1));
+    a.col = buf<int32_t>(h, h->col, (size_t)std::max<int64_t>(m, 1));
+    a.rkey = buf<uint64_t>(h, h->rkey, (size_t)std::max<int64_t>(m, 1));
+    a.st = buf<uint8_t>(h, h->st, (size_t)std::max<int64_t>(E, 1));
+    a.hist_w = T_max + 1;
+    a.hist = buf<unsigned long long>(h, h->dyn_hist, (size_t)b.nb * a.hist_w);
+    a.sstar = buf<int32_t>(h, h->dyn_sstar, (size_t)b.nb);
+    a.cut = buf<uint64_t>(h, h->dyn_cut, (size_t)b.nb);
+    a.active = buf<unsigned long long>(h, h->scalars, 8) + 6;
+    a.divisor = h->dyn_divisor;
+    a.ell = ell;
+    launch_fill_u8(a.st, E, 0, st);
+    launch_fill_u64(reinterpret_cast<uint64_t *>(a.hist), (int64_t)b.nb * a.hist_w, 0ull, st);
+    launch_dyn_init(a, st);
+    // every round with an active vertex colours at least the first requester
+    // of each requested colour, so m rounds always suffice
+    const int64_t max_rounds = m + 64;
+    int32_t round = 0, batch = 4;
+    while (true) {
+        for (int r = 0; r < batch; ++r) launch_dyn_round(a, round++, st);
+        unsigned long long active = 0;
+        PCHECK_HIP(hipMemcpyAsync(&active, a.active, sizeof(active), hipMemcpyDeviceToHost, st));
+        PCHECK_HIP(hipStreamSynchronize(st));
+        if (active == 0) break;
+        if (round > max_rounds) throw Error(PICASSO_EINTERNAL, "dynamic colouring made no progress");
+        batch = std::min<int32_t>(batch * 2, std::max<int32_t>(h->jp_batch, 1));
+    }
+    return round;
 }
 
 void init_ids(picasso_ctx *h, int64_t m);
@@ -868,27 +964,30 @@ int64_t color_all(picasso_ctx *h, const RunArgs &ra, int32_t *d_out, int64_t *n_
         uint32_t *d_hits = buf<uint32_t>(h, h->hits, (size_t)b.nb);
         launch_fill_u32(d_hits, b.nb, 0u, st);
         launch_density(b, d_ids, static_cast<const uint64_t *>(h->x.p), static_cast<const uint64_t *>(h->z.p), h->W,
-                       ell, kFeaturePairs, d_hits, st);
+                       ell, kSizingPairs, d_hits, st);
         h_hits.resize((size_t)b.nb);
         const BucketInfo bi = build_lists_and_buckets(h, b, ell, m, d_ids, E, Ptot, T_max, d_hits, h_hits.data());
         it.pair_tests = bi.pair_tests;
-        it.edges_bound = conflict_edge_bound(h->h_inst, h_hits.data(), kFeaturePairs, bi.pair_tests);
+        it.edges_bound = conflict_edge_bound(h->h_inst, h_hits.data(), kSizingPairs, bi.pair_tests);
         tm.mark();
         bool used_mfma = false;
         const int64_t presize = h->csr_sizing == 0 ? -1 : h->csr_sizing == 2 ? 0 : it.edges_bound;
         it.edges = build_conflict_graph(h, b, m, E, Ptot, T_max, rel_mask, bi, &it.ms_count, &it.ms_fill,
-                                        &used_mfma, false, presize);
-        const bool csr_deferred = it.edges < 0;
+                                        &used_mfma, false, presize, h->edges_on != 0);
+        const bool csr_deferred = h->edges_on && it.edges < 0;
+        if (!h->edges_on) it.edges_bound = -1;
         it.pair_path = used_mfma ? PICASSO_PATH_MFMA : PICASSO_PATH_VALU;
         tm.mark();
-        it.jp_rounds = color_buckets(h, b, m, E, Ptot, T_max, bi);
+        it.jp_rounds = h->colourer == PICASSO_COLOURER_DYNAMIC
+                           ? color_buckets_dynamic(h, b, ell, m, E, Ptot, T_max, bi)
+                           : color_buckets(h, b, m, E, Ptot, T_max, bi);
         tm.mark();
         // output colours, used-colour counts, next vertex set
         const int32_t na = b.nb;
         uint32_t *used = buf<uint32_t>(h, h->used, (size_t)(Ptot + 31) / 32);
         launch_fill_u32(used, (Ptot + 31) / 32, 0u, st);
         int64_t *iout = buf<int64_t>(h, h->inst_out, (size_t)3 * na);  // used, m_next, edges
-        launch_fill_u64(reinterpret_cast<uint64_t *>(iout), na, 0ull, st);
+        launch_fill_u64(reinterpret_cast<uint64_t *>(iout), 3 * na, 0ull, st);
         int32_t *flags = buf<int32_t>(h, h->flags, (size_t)m);
         launch_finish_iteration(b, m, static_cast<const int32_t *>(h->col.p), d_ids, d_out, used,
                                 reinterpret_cast<unsigned long long *>(iout), flags, st);
@@ -897,7 +996,8 @@ int64_t color_all(picasso_ctx *h, const RunArgs &ra, int32_t *d_out, int64_t *n_
         exclusive_scan_i32_to_i64(flags, pos, m, true, tmp, st);
         int32_t *next = buf<int32_t>(h, h->next_ids, (size_t)m);
         launch_compact_ids(m, d_ids, flags, pos, next, st);
-        launch_instance_totals(b, pos, static_cast<const int64_t *>(h->slot_off.p), iout + na, iout + 2 * na, st);
+        launch_instance_totals(b, pos, static_cast<const int64_t *>(h->slot_off.p), iout + na,
+                               h->edges_on ? iout + 2 * na : nullptr, st);
         tm.mark();
         hv.resize((size_t)3 * na);
         download(h, hv.data(), iout, hv.size() * sizeof(int64_t));
@@ -925,8 +1025,12 @@ int64_t color_all(picasso_ctx *h, const RunArgs &ra, int32_t *d_out, int64_t *n_
             off[i] += r.P;
             is.n_iters++;
             is.palette_total += r.P;
-            is.edges += hv[2 * na + a];
-            is.max_edges = std::max<int64_t>(is.max_edges, hv[2 * na + a]);
+            if (h->edges_on) {
+                is.edges += hv[2 * na + a];
+                is.max_edges = std::max<int64_t>(is.max_edges, hv[2 * na + a]);
+            } else {
+                is.edges = is.max_edges = -1;
+            }
             if (r.m - mi[i] <= 0) throw Error(PICASSO_EINTERNAL, "iteration coloured no vertex of an instance");
         }
         it.colored = m - m_next;
@@ -939,7 +1043,8 @@ int64_t color_all(picasso_ctx *h, const RunArgs &ra, int32_t *d_out, int64_t *n_
         // others' vertices move to the front of the next vertex set
         bool gathered = false;
         // (with a schedule, once every further iteration uses its last entry)
-        if (!ra.mlp && h->use_tail && (ra.n_steps == 0 || (int32_t)ell + 1 >= ra.n_steps)) {
+        if (!ra.mlp && h->use_tail && h->colourer == PICASSO_COLOURER_STATIC &&
+            (ra.n_steps == 0 || (int32_t)ell + 1 >= ra.n_steps)) {
             const int64_t kept = run_tails(h, ra, act, mi, off, ell, n_colors, d_out, S, iter_edges, gathered);
             m_next = kept;
         }
@@ -1158,7 +1263,9 @@ void picasso_destroy(picasso_handle h)
                      &h->scan_tmp, &h->bx,      &h->bz,      &h->tile_bucket,
                      &h->scalars, &h->out_colors, &h->judge_out, &h->inst,    &h->vinst,    &h->loff,    &h->binst,    &h->inst_out, &h->tail_recs,
                      &h->tail_table, &h->tail_outs, &h->tail_iters, &h->tail_ranges, &h->wake_at,
-                     &h->hits,    &h->csr_flag};
+                     &h->hits,    &h->csr_flag, &h->rkey,  &h->dyn_hist, &h->dyn_sstar, &h->dyn_cut,
+                     &h->rx_k64a, &h->rx_k64b, &h->rx_va, &h->rx_vb,   &h->rx_tmp,  &h->rx_tr,   &h->rx_at,
+                     &h->rx_cka,  &h->rx_ckb,  &h->rx_cva, &h->rx_cvb};
     for (DevBuf *b : all) h->arena.release(*b);
     if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
     delete h;
@@ -1197,6 +1304,23 @@ int32_t picasso_set_option(picasso_handle h, int32_t key, int64_t value)
                     break;
                 case PICASSO_OPT_TAIL:
                     h->use_tail = value != 0;
+                    break;
+                case PICASSO_OPT_BUCKET_BUILD:
+                    if (value < 0 || value > 2) throw Error(PICASSO_EINVAL, "bucket build is 0, 1 or 2");
+                    h->bucket_build = (int32_t)value;
+                    break;
+                case PICASSO_OPT_EDGES:
+                    if (value != 0 && value != 1) throw Error(PICASSO_EINVAL, "the edges option is 0 or 1");
+                    h->edges_on = (int32_t)value;
+                    break;
+                case PICASSO_OPT_COLOURER:
+                    if (value != PICASSO_COLOURER_STATIC && value != PICASSO_COLOURER_DYNAMIC)
+                        throw Error(PICASSO_EINVAL, "unknown colourer");
+                    h->colourer = (int32_t)value;
+                    break;
+                case PICASSO_OPT_DYN_DIVISOR:
+                    if (value < 1 || value > (1 << 20)) throw Error(PICASSO_EINVAL, "divisor must be in [1, 2^20]");
+                    h->dyn_divisor = (int32_t)value;
                     break;
                 case PICASSO_OPT_CSR_SIZING:
                     if (value < 0 || value > 2) throw Error(PICASSO_EINVAL, "CSR sizing is 0, 1 or 2");

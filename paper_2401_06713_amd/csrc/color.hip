@@ -152,7 +152,7 @@ constexpr int kJpResweeps = 4;  // extra sweeps of a bucket woken again during i
 //    bucket of f is woken (v may now take it).
 // Taking a colour needs no wake of its own: the slot was found free first.
 __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t from, uint64_t *tak, uint64_t *unk,
-                               uint32_t *mv, uint8_t *mk, int32_t *out, int32_t *out_count)
+                               uint32_t *mv, slot_t *mk, int32_t *out, int32_t *out_count)
 {
     const int lane = threadIdx.x;
     const int64_t base = a.bstart[c];
@@ -204,6 +204,7 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t from, uint64
         while (true) {
             uint8_t ns = ST_UNKNOWN;
             bool wait = false;  // free here, waiting for v's lower slots: no change in this sweep
+            bool fin = false;   // v's colour (or failure) was decided here
             if (open) {
                 const bool blocked = hit_tak_prev || (own & tak_ch);
                 if (blocked || !(hit_unk_prev || (own & unk_ch))) {
@@ -219,7 +220,7 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t from, uint64
                         const uint64_t old = atomicOr((unsigned long long *)&blk[k >> 6], kb);
                         if (atomicAdd(&a.nblk[v], 1) == T - 1) {  // the last slot was blocked
                             __hip_atomic_store(&a.col[v], COL_FAILED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            atomicAdd(a.progress, 1ull);
+                            fin = true;
                         } else {
                             int f;
                             if (a.fw == 1) {
@@ -234,7 +235,7 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t from, uint64
                         const uint64_t was = atomicOr((unsigned long long *)&fre[k >> 6], kb);
                         if (all_below(blk, k)) {
                             __hip_atomic_store(&a.col[v], (int32_t)c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            atomicAdd(a.progress, 1ull);
+                            fin = true;
                             ns = ST_TAKEN;
                         } else {
                             wait = true;
@@ -243,6 +244,10 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t from, uint64
                     }
                 }
             }
+            // decided vertices, counted once per wave step (one atomic per
+            // vertex on a single counter serialises at this scale)
+            const uint64_t fins = __ballot(fin);
+            if (lane == 0 && fins) atomicAdd(a.progress, (unsigned long long)__popcll(fins));
             const bool decided = ns != ST_UNKNOWN;
             const uint64_t dec = __ballot(decided);
             const uint64_t tk = __ballot(ns == ST_TAKEN);
@@ -261,20 +266,21 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t from, uint64
 }
 
 // One round of the worklist: visit the buckets listed by the previous round
-// (wl[cur], count in wl_count[cur]); state changes append the buckets they
-// may unblock to wl[cur ^ 1].  No workgroup waits on another: rounds are
-// separate launches in stream order.
-__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(6))) jp_round_kernel(JpArgs a, int cur)
+// (wl[cur], count in wl_slots[k]); state changes append the buckets they
+// may unblock to wl[cur ^ 1], counted in wl_slots[k + 1].  No workgroup
+// waits on another: rounds are separate launches in stream order.
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(6))) jp_round_kernel(JpArgs a, int cur,
+                                                                                                   int32_t k)
 {
     extern __shared__ uint64_t sbits[];  // taken[nw_max], unknown[nw_max]
     uint64_t *tak = sbits;
     uint64_t *unk = sbits + a.nw_max;
     __shared__ uint32_t mv[kJpStage];
-    __shared__ uint8_t mk[kJpStage];
+    __shared__ slot_t mk[kJpStage];
     __shared__ unsigned long long from;
-    const int32_t n_in = a.wl_count[cur];
+    const int32_t n_in = a.wl_slots[k];
     int32_t *out = a.wl[cur ^ 1];
-    int32_t *out_count = &a.wl_count[cur ^ 1];
+    int32_t *out_count = &a.wl_slots[k + 1];
     for (int64_t i = blockIdx.x; i < n_in; i += gridDim.x) {
         const int64_t c = a.wl[cur][i];
         if (threadIdx.x == 0) {
@@ -295,28 +301,32 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(6)))
             atomicMin(&a.wake_at[c], from);
         __syncthreads();
     }
-    // The list this round consumed is emptied before the next round refills
-    // it, by the last workgroup to finish: every workgroup read n_in before
-    // taking its ticket (the loop bound depends on it).
-    if (threadIdx.x == 0 && atomicAdd(a.ticket, 1u) == gridDim.x - 1) {
-        a.wl_count[cur] = 0;
-        *a.ticket = 0u;
-    }
 }
+
+// Before a batch: slot 0 takes the current list length, the counters of the
+// batch's rounds start at zero.  (A last-workgroup ticket that empties the
+// consumed list inside each round was measured slower: 16384 workgroups per
+// round on one counter cost about 80 us per round at n = 2M.)
+__global__ void jp_batch_begin_kernel(int32_t *slots, int32_t rounds)
+{
+    const int32_t cur = slots[kJpCountCell];
+    for (int32_t i = threadIdx.x + 1; i <= rounds; i += blockDim.x) slots[i] = 0;
+    if (threadIdx.x == 0) slots[0] = cur;
+}
+
+// After a batch: its final list length becomes the current one.
+__global__ void jp_batch_end_kernel(int32_t *slots, int32_t rounds) { slots[kJpCountCell] = slots[rounds]; }
 
 // Worklist of every bucket (the first round, and the host's recovery round).
 __global__ void wl_all_kernel(int64_t P, int32_t *wl, uint32_t *dirty, unsigned long long *wake_at,
-                              int32_t *wl_count)
+                              int32_t *wl_slots)
 {
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < P; c += (int64_t)gridDim.x * blockDim.x) {
         wl[c] = (int32_t)c;
         dirty[c] = 1u;
         wake_at[c] = 0ull;  // whole bucket
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        wl_count[0] = (int32_t)P;
-        wl_count[1] = 0;
-    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) wl_slots[kJpCountCell] = (int32_t)P;
 }
 
 // Relation bits of a bucket from a given symmetric CSR: for every edge
@@ -419,16 +429,30 @@ unsigned grid_for(int64_t work, int threads, int64_t cap = 65535 * 16)
 void launch_jp_all(const JpArgs &a, hipStream_t st)
 {
     if (a.P <= 0) return;
-    wl_all_kernel<<<grid_for(a.P, 256), 256, 0, st>>>(a.P, a.wl[0], a.dirty, a.wake_at, a.wl_count);
+    wl_all_kernel<<<grid_for(a.P, 256), 256, 0, st>>>(a.P, a.wl[0], a.dirty, a.wake_at, a.wl_slots);
     PCHECK_LAUNCH();
 }
 
-void launch_jp_round(const JpArgs &a, int cur, hipStream_t st)
+void launch_jp_batch_begin(const JpArgs &a, int32_t rounds, hipStream_t st)
+{
+    if (rounds < 1 || rounds > kJpMaxBatch) throw Error(PICASSO_EINTERNAL, "colouring batch out of range");
+    jp_batch_begin_kernel<<<1, 256, 0, st>>>(a.wl_slots, rounds);
+    PCHECK_LAUNCH();
+}
+
+void launch_jp_round(const JpArgs &a, int cur, int32_t k, hipStream_t st)
 {
     if (a.P <= 0) return;
+    if (k < 0 || k >= kJpMaxBatch) throw Error(PICASSO_EINTERNAL, "colouring round out of range");
     const size_t lds = (size_t)2 * a.nw_max * sizeof(uint64_t);
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(a.P, 16384));
-    jp_round_kernel<<<(unsigned)grid, kWave, lds, st>>>(a, cur);
+    jp_round_kernel<<<(unsigned)grid, kWave, lds, st>>>(a, cur, k);
+    PCHECK_LAUNCH();
+}
+
+void launch_jp_batch_end(const JpArgs &a, int32_t rounds, hipStream_t st)
+{
+    jp_batch_end_kernel<<<1, 1, 0, st>>>(a.wl_slots, rounds);
     PCHECK_LAUNCH();
 }
 

@@ -77,6 +77,11 @@ struct Arena {
 // members of a single instance.  The kernels read per-instance values from
 // this record and reach it through vinst (per active vertex) or binst (per
 // bucket).
+// Slot of a list entry (its place in the vertex's sorted list): lists hold
+// at most PICASSO_MAX_T colours.
+using slot_t = uint16_t;
+static_assert(PICASSO_MAX_T <= 65536, "slot_t holds every list position");
+
 struct InstRec {
     int64_t vstart;  // first active vertex of the instance (index into ids)
     int64_t m;       // active vertices
@@ -119,7 +124,7 @@ void launch_sample_lists(const Batch &b, uint32_t ell, int64_t m, const int32_t 
                          uint32_t *lists, uint64_t *prio, hipStream_t st);
 void launch_bucket_count(const uint32_t *lists, int64_t entries, uint32_t *bcnt, hipStream_t st);
 void launch_bucket_scatter(const uint32_t *lists, int64_t m, const int64_t *loff, const int64_t *bstart,
-                           uint32_t *bfill, uint32_t *bmem, uint8_t *bslot, hipStream_t st);
+                           uint32_t *bfill, uint32_t *bmem, slot_t *bslot, hipStream_t st);
 void launch_check_padding(const uint64_t *x, const uint64_t *z, int64_t n, int32_t q, int32_t *bad,
                           hipStream_t st);
 
@@ -127,9 +132,9 @@ void launch_check_padding(const uint64_t *x, const uint64_t *z, int64_t n, int32
 // local index); pos_of[loff[v] + k] receives the bucket position of (v, k)
 // and bent[position] its list entry loff[v] + k (the inverse permutation, so
 // that kernels walking a bucket read their members' list entries in order).
-void launch_bucket_sort(const int64_t *bstart, int64_t P, uint32_t *bmem, uint8_t *bslot, const uint64_t *prio,
+void launch_bucket_sort(const int64_t *bstart, int64_t P, uint32_t *bmem, slot_t *bslot, const uint64_t *prio,
                         int64_t *pos_of, int64_t *bent, const int64_t *loff, bool has_large, uint32_t *tmp_mem,
-                        uint8_t *tmp_slot, hipStream_t st);
+                        slot_t *tmp_slot, hipStream_t st);
 // Sum of C(|B_c|, 2) into pairs[0], largest |B_c| into pairs[1].
 void launch_bucket_pairs(const uint32_t *bcnt, int64_t P, unsigned long long *pairs, hipStream_t st);
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
@@ -176,7 +181,7 @@ void launch_relate_mfma(const RelateArgs &a, int32_t q, hipStream_t st);
 struct DupArgs {
     const int64_t *bstart;
     const uint32_t *bmem;
-    const uint8_t *bslot;
+    const slot_t *bslot;
     int64_t P;
     const int64_t *rb_off;
     const uint32_t *lists;  // rows sorted, row v at loff[v]
@@ -195,7 +200,7 @@ void launch_dup_slow(const DupArgs &a, hipStream_t st);  // count of slow bucket
 struct CsrArgs {
     const int64_t *bstart;
     const uint32_t *bmem;
-    const uint8_t *bslot;
+    const slot_t *bslot;
     int64_t P;
     const int64_t *rb_off;
     const uint64_t *R, *D;
@@ -217,7 +222,7 @@ struct JpArgs {
     int64_t P;
     const int64_t *bstart;
     const uint32_t *bmem;
-    const uint8_t *bslot;
+    const slot_t *bslot;
     const int64_t *rb_off;
     const uint64_t *R;
     const uint32_t *lists;  // rows sorted, row v at loff[v]
@@ -232,17 +237,75 @@ struct JpArgs {
     uint32_t *dirty;        // per bucket: waiting on a worklist
     unsigned long long *wake_at;  // per bucket: first bucket position changed since it was last taken
     int32_t *wl[2];         // worklists of buckets (P entries each)
-    int32_t *wl_count;      // [2]
-    uint32_t *ticket;       // workgroups of the current round that have finished
+    int32_t *wl_slots;      // [kJpSlots]: list length entering round k of a batch
+                            // at k, the current length at kJpCountCell
     unsigned long long *progress;  // decided vertices
     int64_t m;              // vertices to decide
 };
-// Every bucket onto worklist 0 (marked waiting); worklist 1 empty.
+constexpr int kJpMaxBatch = 1024;               // rounds per batch, at most
+constexpr int kJpCountCell = kJpMaxBatch + 1;   // current list length between batches
+constexpr int kJpSlots = kJpMaxBatch + 2;
+// Every bucket onto worklist 0 (marked waiting): the current length is P.
 void launch_jp_all(const JpArgs &a, hipStream_t st);
-// One worklist round reading list `cur` and filling list cur ^ 1; the last
-// workgroup to finish (a ticket counter, zero between rounds) empties list
-// `cur`, after every workgroup has read its length.
-void launch_jp_round(const JpArgs &a, int cur, hipStream_t st);
+// A batch of `rounds` worklist rounds starting from list `cur`: round k
+// reads the list of length wl_slots[k] and appends to the other list,
+// counting in wl_slots[k + 1] (zeroed when the batch begins, so no round
+// resets a counter); the batch's final length is kept at kJpCountCell.
+void launch_jp_batch_begin(const JpArgs &a, int32_t rounds, hipStream_t st);
+void launch_jp_round(const JpArgs &a, int cur, int32_t k, hipStream_t st);
+void launch_jp_batch_end(const JpArgs &a, int32_t rounds, hipStream_t st);
+// radix.hip: stable LSD radix sort of (key, 32-bit value) pairs by bits
+// [bit_lo, bit_hi) in 8-bit digits; ping-pongs between the two buffer pairs
+// and returns 1 if the result is in the alternate pair.  tmp: at least
+// radix_tmp_bytes(n) bytes.
+size_t radix_tmp_bytes(int64_t n);
+template <typename K>
+int radix_sort_pairs(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals_alt, int64_t n, int bit_lo, int bit_hi,
+                     void *tmp, hipStream_t st);
+void launch_iota_u32(uint32_t *p, int64_t n, hipStream_t st);
+// List sizes of the vertices in priority order (perm[r]: the vertex at rank r).
+void launch_ranked_sizes(const uint32_t *perm, int64_t m, const int64_t *loff, int32_t *tr, hipStream_t st);
+// (colour, entry index) of every list entry, vertices in priority order
+// (at[r]: first output position of rank r).
+void launch_emit_ranked(const uint32_t *perm, int64_t m, const int64_t *loff, const int64_t *at,
+                        const uint32_t *lists, uint32_t *keys, uint32_t *vals, int64_t E, hipStream_t st);
+// Buckets from the entries sorted by colour (stable from priority order):
+// starts, sizes, members, slots, and the position <-> entry maps.
+void launch_bucket_from_sorted(const Batch &b, const uint32_t *keys, const uint32_t *ents, int64_t E, int64_t P,
+                               int64_t *bstart, uint32_t *bcnt, uint32_t *bmem, slot_t *bslot, int64_t *pos_of,
+                               int64_t *bent, hipStream_t st);
+constexpr int64_t kRadixMinEntries = (int64_t)1 << 20;  // below: atomics and per-bucket sorts (fewer launches)
+
+// dynamic.hip: the round form of the dynamic-order colouring (Alg. 2).
+struct DynArgs {
+    Batch b;                      // instances, vinst, loff
+    int64_t m, P;
+    const int32_t *ids;           // [m] packed string index of each vertex
+    const int64_t *pos_of;        // bucket position of (v, k)
+    const int64_t *bstart;
+    const uint32_t *bmem;
+    const slot_t *bslot;
+    const int64_t *rb_off;
+    const uint64_t *R;            // per-bucket relation rows (symmetric)
+    int64_t nw_max;               // words per row of the largest bucket
+    int32_t fw;                   // words per slot mask
+    uint64_t *alive;              // m x fw: slots still in the list
+    int32_t *size;                // [m] slots still in the list
+    int32_t *col;                 // [m] batch-wide colour, COL_FAILED, COL_UNDECIDED
+    uint64_t *rkey;               // [m] request key: size << 32 | draw
+    uint8_t *st;                  // per bucket entry: none / requested / removed
+    unsigned long long *hist;     // nb x hist_w: active vertices by list size
+    int32_t hist_w;               // largest T + 1
+    int32_t *sstar;               // [nb] request threshold: list size
+    uint64_t *cut;                // [nb] request threshold: draw
+    unsigned long long *active;   // active vertices at the start of the last round
+    int32_t divisor;              // about one active vertex in `divisor` requests per round
+    uint32_t ell;                 // iteration (keys the draws)
+};
+void launch_dyn_init(const DynArgs &a, hipStream_t st);
+// One round: failures and size counts, thresholds, requests, per-bucket
+// resolution and removal.
+void launch_dyn_round(const DynArgs &a, int32_t round, hipStream_t st);
 void launch_csr_to_relation(int64_t m, const int64_t *rowptr, const int32_t *adj, const uint32_t *lists,
                             const int64_t *loff, const int64_t *pos_of, const int64_t *bstart, const int64_t *rb_off,
                             uint64_t *R, hipStream_t st);
@@ -294,6 +357,7 @@ constexpr int kMlpParams = kMlpHidden * kMlpIn + kMlpHidden + kMlpHidden * kMlpH
                            kMlpOut * kMlpHidden + kMlpOut;
 constexpr int kMlpKeep = kMlpIn + 2 * kMlpHidden + kMlpOut + 2 * kMlpHidden;  // per-row training state
 constexpr int kFeaturePairs = 4096;
+constexpr int kSizingPairs = 16384;  // sampled pairs of the CSR size bound (the first 4096 are the features')
 void launch_features(int64_t m, const int32_t *ids, const uint64_t *x, const uint64_t *z, int32_t W, uint64_t seed,
                      uint32_t ell, int32_t rel, int32_t K, unsigned long long *weight, unsigned long long *hits,
                      hipStream_t st);

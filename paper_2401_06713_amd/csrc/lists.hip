@@ -127,7 +127,7 @@ __global__ void bucket_count_kernel(const uint32_t *__restrict__ lists, int64_t 
 
 __global__ void bucket_scatter_kernel(const uint32_t *__restrict__ lists, int64_t m, const int64_t *__restrict__ loff,
                                       const int64_t *__restrict__ bstart, uint32_t *__restrict__ bfill,
-                                      uint32_t *__restrict__ bmem, uint8_t *__restrict__ bslot)
+                                      uint32_t *__restrict__ bmem, slot_t *__restrict__ bslot)
 {
     // The position in the bucket comes back from an atomic add; eight of
     // them are issued before the first result is used, so a thread waits
@@ -154,7 +154,7 @@ __global__ void bucket_scatter_kernel(const uint32_t *__restrict__ lists, int64_
                 if (k0 + j < T) {
                     const int64_t at = base[j] + pos[j];
                     bmem[at] = (uint32_t)v;
-                    bslot[at] = (uint8_t)(k0 + j);
+                    bslot[at] = (slot_t)(k0 + j);
                 }
         }
     }
@@ -203,7 +203,7 @@ __device__ __forceinline__ bool key_less(uint64_t pa, uint32_t va, uint64_t pb, 
 
 __global__ void __launch_bounds__(kSortThreads) bucket_sort_kernel(const int64_t *__restrict__ bstart, int64_t P,
                                                                    uint32_t *__restrict__ bmem,
-                                                                   uint8_t *__restrict__ bslot,
+                                                                   slot_t *__restrict__ bslot,
                                                                    const uint64_t *__restrict__ prio,
                                                                    int64_t *__restrict__ pos_of,
                                                                    int64_t *__restrict__ bent,
@@ -211,7 +211,7 @@ __global__ void __launch_bounds__(kSortThreads) bucket_sort_kernel(const int64_t
 {
     __shared__ uint64_t key[kSortCap];
     __shared__ uint32_t vid[kSortCap];
-    __shared__ uint8_t sl[kSortCap];
+    __shared__ slot_t sl[kSortCap];
     const int t = threadIdx.x;
     for (int64_t c = blockIdx.x; c < P; c += gridDim.x) {
         const int64_t base = bstart[c];
@@ -253,7 +253,7 @@ __global__ void __launch_bounds__(kSortThreads) bucket_sort_kernel(const int64_t
                             const uint32_t tv = vid[e];
                             vid[e] = vid[f];
                             vid[f] = tv;
-                            const uint8_t ts = sl[e];
+                            const slot_t ts = sl[e];
                             sl[e] = sl[f];
                             sl[f] = ts;
                         }
@@ -272,36 +272,59 @@ __global__ void __launch_bounds__(kSortThreads) bucket_sort_kernel(const int64_t
     }
 }
 
+// Buckets above kSortCap: each member's rank is the number of members with a
+// smaller (priority, vertex) key.  The bucket's keys are compared in tiles
+// staged in LDS (one gather of the priorities per tile); each pass ranks
+// kSortThreads members, one per thread.
+constexpr int kRankTile = 2048;
+
 __global__ void __launch_bounds__(kSortThreads) bucket_rank_kernel(const int64_t *__restrict__ bstart, int64_t P,
                                                                    const uint32_t *__restrict__ bmem,
-                                                                   const uint8_t *__restrict__ bslot,
+                                                                   const slot_t *__restrict__ bslot,
                                                                    const uint64_t *__restrict__ prio,
                                                                    uint32_t *__restrict__ out_mem,
-                                                                   uint8_t *__restrict__ out_slot)
+                                                                   slot_t *__restrict__ out_slot)
 {
+    __shared__ uint64_t tkey[kRankTile];
+    __shared__ uint32_t tvid[kRankTile];
     for (int64_t c = blockIdx.x; c < P; c += gridDim.x) {
         const int64_t base = bstart[c];
         const int64_t S = bstart[c + 1] - base;
         if (S <= kSortCap) continue;
-        for (int64_t p = threadIdx.x; p < S; p += blockDim.x) {
-            const uint32_t vp = bmem[base + p];
-            const uint64_t kp = prio[vp];
-            int64_t rank = 0;
-            for (int64_t q = 0; q < S; ++q) {
-                const uint32_t vq = bmem[base + q];
-                rank += key_less(prio[vq], vq, kp, vp);
+        for (int64_t p0 = 0; p0 < S; p0 += kSortThreads) {
+            const int64_t p = p0 + threadIdx.x;
+            uint32_t vp = 0;
+            uint64_t kp = 0;
+            if (p < S) {
+                vp = bmem[base + p];
+                kp = prio[vp];
             }
-            out_mem[base + rank] = vp;
-            out_slot[base + rank] = bslot[base + p];
+            int64_t rank = 0;
+            for (int64_t t0 = 0; t0 < S; t0 += kRankTile) {
+                const int64_t nt = S - t0 < kRankTile ? S - t0 : kRankTile;
+                __syncthreads();
+                for (int64_t i = threadIdx.x; i < nt; i += kSortThreads) {
+                    const uint32_t v = bmem[base + t0 + i];
+                    tvid[i] = v;
+                    tkey[i] = prio[v];
+                }
+                __syncthreads();
+                if (p < S)
+                    for (int64_t i = 0; i < nt; ++i) rank += key_less(tkey[i], tvid[i], kp, vp);
+            }
+            if (p < S) {
+                out_mem[base + rank] = vp;
+                out_slot[base + rank] = bslot[base + p];
+            }
         }
     }
 }
 
 __global__ void __launch_bounds__(kSortThreads) bucket_rank_copy_kernel(const int64_t *__restrict__ bstart, int64_t P,
                                                                         uint32_t *__restrict__ bmem,
-                                                                        uint8_t *__restrict__ bslot,
+                                                                        slot_t *__restrict__ bslot,
                                                                         const uint32_t *__restrict__ tmp_mem,
-                                                                        const uint8_t *__restrict__ tmp_slot,
+                                                                        const slot_t *__restrict__ tmp_slot,
                                                                         int64_t *__restrict__ pos_of,
                                                                         int64_t *__restrict__ bent,
                                                                         const int64_t *__restrict__ loff)
@@ -312,7 +335,7 @@ __global__ void __launch_bounds__(kSortThreads) bucket_rank_copy_kernel(const in
         if (S <= kSortCap) continue;
         for (int64_t p = threadIdx.x; p < S; p += blockDim.x) {
             const uint32_t v = tmp_mem[base + p];
-            const uint8_t k = tmp_slot[base + p];
+            const slot_t k = tmp_slot[base + p];
             bmem[base + p] = v;
             bslot[base + p] = k;
             const int64_t en = loff[v] + k;
@@ -368,7 +391,9 @@ void launch_sample_lists(const Batch &b, uint32_t ell, int64_t m, const int32_t 
                          uint32_t *lists, uint64_t *prio, hipStream_t st)
 {
     if (m <= 0) return;
-    const int B = T_max <= 64 ? 256 : (T_max <= 128 ? 128 : 64);
+    // lists are built in LDS, T_max x B words: at most 64 KB
+    const int B = T_max <= 64 ? 256 : T_max <= 128 ? 128 : T_max <= 256 ? 64 : T_max <= 512 ? 32 : 16;
+    if (T_max > PICASSO_MAX_T) throw Error(PICASSO_EINVAL, "list size above PICASSO_MAX_T");
     const size_t lds = (size_t)T_max * B * sizeof(uint32_t);
     const int64_t blocks = (m + B - 1) / B;
     sample_lists_kernel<<<(unsigned)blocks, B, lds, st>>>(b, ell, m, ids, lists, prio);
@@ -383,7 +408,7 @@ void launch_bucket_count(const uint32_t *lists, int64_t entries, uint32_t *bcnt,
 }
 
 void launch_bucket_scatter(const uint32_t *lists, int64_t m, const int64_t *loff, const int64_t *bstart,
-                           uint32_t *bfill, uint32_t *bmem, uint8_t *bslot, hipStream_t st)
+                           uint32_t *bfill, uint32_t *bmem, slot_t *bslot, hipStream_t st)
 {
     if (m <= 0) return;
     bucket_scatter_kernel<<<grid_for(m, 256), 256, 0, st>>>(lists, m, loff, bstart, bfill, bmem, bslot);
@@ -432,9 +457,9 @@ void launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t st)
     PCHECK_LAUNCH();
 }
 
-void launch_bucket_sort(const int64_t *bstart, int64_t P, uint32_t *bmem, uint8_t *bslot, const uint64_t *prio,
+void launch_bucket_sort(const int64_t *bstart, int64_t P, uint32_t *bmem, slot_t *bslot, const uint64_t *prio,
                         int64_t *pos_of, int64_t *bent, const int64_t *loff, bool has_large, uint32_t *tmp_mem,
-                        uint8_t *tmp_slot, hipStream_t st)
+                        slot_t *tmp_slot, hipStream_t st)
 {
     if (P <= 0) return;
     const unsigned grid = (unsigned)(P < (1 << 20) ? P : (1 << 20));

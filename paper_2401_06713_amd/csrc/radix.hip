@@ -1,0 +1,271 @@
+// Stable least-significant-digit radix sort of (key, value) pairs, and the
+// colour-bucket build that uses it.
+//
+// Each pass sorts by one 8-bit digit: a digit histogram per tile of
+// kTile elements, an exclusive scan over (digit, tile) -- digit-major, so a
+// tile's elements of digit d land after every earlier tile's -- and a
+// stable scatter.  Within a tile, elements are ranked in input order: per
+// round of 256 elements, each wave finds the lanes with its digit by eight
+// ballots, and per-wave digit counts in LDS order the four waves.
+//
+// Bucket build (Alg. 1 buckets of list entries, members in the colouring
+// order): the vertices are sorted by (priority, index) (eight passes over the
+// 64-bit priority, stable from ascending index), their list entries are
+// emitted in that order, and a stable sort by colour then leaves every
+// bucket's members in priority order -- count, scatter and the per-bucket
+// sort in one pass over the entries per colour digit, with no atomics on
+// global counters.
+#include <algorithm>
+
+#include "common.h"
+
+namespace picasso {
+namespace {
+
+constexpr int kRThreads = 256;
+constexpr int kRItems = 8;
+constexpr int64_t kRTile = (int64_t)kRThreads * kRItems;
+constexpr int kBins = 256;
+
+template <typename K>
+__device__ __forceinline__ uint32_t digit_of(K key, int shift)
+{
+    return (uint32_t)(key >> shift) & (kBins - 1);
+}
+
+template <typename K>
+__global__ void __launch_bounds__(kRThreads) radix_hist_kernel(const K *__restrict__ keys, int64_t n, int shift,
+                                                               int64_t ntiles, uint32_t *__restrict__ counts)
+{
+    __shared__ uint32_t h[kBins];
+    h[threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRTile;
+#pragma unroll
+    for (int i = 0; i < kRItems; ++i) {
+        const int64_t g = base + (int64_t)i * kRThreads + threadIdx.x;
+        if (g < n) atomicAdd(&h[digit_of(keys[g], shift)], 1u);
+    }
+    __syncthreads();
+    counts[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+template <typename K>
+__global__ void __launch_bounds__(kRThreads) radix_scatter_kernel(const K *__restrict__ keys,
+                                                                  const uint32_t *__restrict__ vals, int64_t n,
+                                                                  int shift, int64_t ntiles,
+                                                                  const int64_t *__restrict__ offsets,
+                                                                  K *__restrict__ out_keys,
+                                                                  uint32_t *__restrict__ out_vals)
+{
+    __shared__ int64_t off[kBins];
+    __shared__ uint32_t running[kBins];
+    __shared__ uint32_t wcnt[kRThreads / 64][kBins];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    off[t] = offsets[(int64_t)t * ntiles + blockIdx.x];
+    running[t] = 0u;
+    const uint64_t lanes_below = (1ull << lane) - 1ull;
+    const int64_t base = (int64_t)blockIdx.x * kRTile;
+    for (int i = 0; i < kRItems; ++i) {
+        for (int w = 0; w < kRThreads / 64; ++w) wcnt[w][t] = 0u;
+        __syncthreads();
+        const int64_t g = base + (int64_t)i * kRThreads + t;
+        const bool valid = g < n;
+        K key = 0;
+        uint32_t val = 0, d = 0;
+        if (valid) {
+            key = keys[g];
+            val = vals[g];
+            d = digit_of(key, shift);
+        }
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t bal = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? bal : ~bal;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lanes_below);
+        const bool leader = valid && (peers >> lane) == 1ull;  // highest lane of its digit
+        if (leader) wcnt[wave][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t before = running[d];
+            for (int w = 0; w < wave; ++w) before += wcnt[w][d];
+            const int64_t pos = off[d] + before + rank;
+            if (pos >= 0 && pos < n) {
+                out_keys[pos] = key;
+                out_vals[pos] = val;
+            }
+        }
+        __syncthreads();
+        uint32_t add = 0u;
+        for (int w = 0; w < kRThreads / 64; ++w) add += wcnt[w][t];
+        running[t] += add;
+        __syncthreads();
+    }
+}
+
+// ---- bucket build ------------------------------------------------------------
+
+__global__ void iota_u32_kernel(uint32_t *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = (uint32_t)i;
+}
+
+// List sizes in priority order (vertex perm[r] at rank r).
+__global__ void ranked_sizes_kernel(const uint32_t *__restrict__ perm, int64_t m, const int64_t *__restrict__ loff,
+                                    int32_t *__restrict__ tr)
+{
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t v = perm[r];
+        tr[r] = (int32_t)(loff[v + 1] - loff[v]);
+    }
+}
+
+// The list entries of the vertices in priority order: (colour, entry index).
+__global__ void emit_ranked_kernel(const uint32_t *__restrict__ perm, int64_t m, const int64_t *__restrict__ loff,
+                                   const int64_t *__restrict__ at, const uint32_t *__restrict__ lists,
+                                   uint32_t *__restrict__ keys, uint32_t *__restrict__ vals, int64_t E)
+{
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t v = perm[r];
+        const int64_t l0 = loff[v], T = loff[v + 1] - l0, o = at[r];
+        for (int64_t k = 0; k < T; ++k)
+            if (o + k < E) {
+                keys[o + k] = lists[l0 + k];
+                vals[o + k] = (uint32_t)(l0 + k);
+            }
+    }
+}
+
+// Bucket starts from the colour-sorted keys: position i starts every colour
+// in (key[i-1], key[i]]; the end closes the remaining colours.
+__global__ void bucket_starts_kernel(const uint32_t *__restrict__ keys, int64_t E, int64_t P,
+                                     int64_t *__restrict__ bstart)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= E; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t lo = i == 0 ? 0 : (int64_t)keys[i - 1] + 1;
+        const int64_t hi = i == E ? P : (int64_t)keys[i];
+        for (int64_t c = lo; c <= hi && c <= P; ++c) bstart[c] = i;
+    }
+}
+
+__global__ void bucket_counts_kernel(const int64_t *__restrict__ bstart, int64_t P, uint32_t *__restrict__ bcnt)
+{
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < P; c += (int64_t)gridDim.x * blockDim.x)
+        bcnt[c] = (uint32_t)(bstart[c + 1] - bstart[c]);
+}
+
+// Members from the sorted entry indices: the instance by a search of the
+// table's list-entry starts, then vertex and slot.
+__global__ void bucket_members_kernel(Batch b, const uint32_t *__restrict__ ents, int64_t E,
+                                      uint32_t *__restrict__ bmem, slot_t *__restrict__ bslot,
+                                      int64_t *__restrict__ pos_of, int64_t *__restrict__ bent)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < E; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = ents[i];
+        int32_t lo = 0, hi = b.nb;  // inst[lo].loff <= e < inst[hi].loff
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (b.inst[mid].loff <= e) lo = mid;
+            else hi = mid;
+        }
+        const InstRec &r = b.inst[lo];
+        const int64_t rel = e - r.loff;
+        const int64_t v = r.vstart + rel / r.T;
+        bmem[i] = (uint32_t)v;
+        bslot[i] = (slot_t)(rel % r.T);
+        bent[i] = e;
+        pos_of[e] = i;
+    }
+}
+
+unsigned grid_for(int64_t work, int threads, int64_t cap = 65535 * 16)
+{
+    int64_t b = (work + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (unsigned)b;
+}
+
+}  // namespace
+
+size_t radix_tmp_bytes(int64_t n)
+{
+    const int64_t ntiles = std::max<int64_t>((n + kRTile - 1) / kRTile, 1);
+    const int64_t nc = ntiles * kBins;
+    return (size_t)nc * sizeof(uint32_t) + (size_t)(nc + 1) * sizeof(int64_t) + scan_tmp_bytes(nc + 1) + 512;
+}
+
+template <typename K>
+int radix_sort_pairs(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals_alt, int64_t n, int bit_lo, int bit_hi,
+                     void *tmp, hipStream_t st)
+{
+    if (n <= 0) return 0;
+    const int64_t ntiles = (n + kRTile - 1) / kRTile;
+    if (ntiles > 0x7FFFFFFF) throw Error(PICASSO_EINTERNAL, "radix sort: too many elements");
+    const int64_t nc = ntiles * kBins;
+    uint32_t *counts = static_cast<uint32_t *>(tmp);
+    int64_t *offsets = reinterpret_cast<int64_t *>(
+        (reinterpret_cast<uintptr_t>(counts + nc) + 255) & ~(uintptr_t)255);
+    void *scan_tmp = reinterpret_cast<void *>((reinterpret_cast<uintptr_t>(offsets + nc + 1) + 255) & ~(uintptr_t)255);
+    K *src_k = keys, *dst_k = keys_alt;
+    uint32_t *src_v = vals, *dst_v = vals_alt;
+    int flips = 0;
+    for (int shift = bit_lo; shift < bit_hi; shift += 8) {
+        radix_hist_kernel<K><<<(unsigned)ntiles, kRThreads, 0, st>>>(src_k, n, shift, ntiles, counts);
+        PCHECK_LAUNCH();
+        exclusive_scan_u32_to_i64(counts, offsets, nc, false, scan_tmp, st);
+        radix_scatter_kernel<K><<<(unsigned)ntiles, kRThreads, 0, st>>>(src_k, src_v, n, shift, ntiles, offsets,
+                                                                        dst_k, dst_v);
+        PCHECK_LAUNCH();
+        std::swap(src_k, dst_k);
+        std::swap(src_v, dst_v);
+        flips ^= 1;
+    }
+    return flips;
+}
+
+template int radix_sort_pairs<uint64_t>(uint64_t *, uint32_t *, uint64_t *, uint32_t *, int64_t, int, int, void *,
+                                        hipStream_t);
+template int radix_sort_pairs<uint32_t>(uint32_t *, uint32_t *, uint32_t *, uint32_t *, int64_t, int, int, void *,
+                                        hipStream_t);
+
+void launch_iota_u32(uint32_t *p, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return;
+    iota_u32_kernel<<<grid_for(n, 256), 256, 0, st>>>(p, n);
+    PCHECK_LAUNCH();
+}
+
+void launch_ranked_sizes(const uint32_t *perm, int64_t m, const int64_t *loff, int32_t *tr, hipStream_t st)
+{
+    if (m <= 0) return;
+    ranked_sizes_kernel<<<grid_for(m, 256), 256, 0, st>>>(perm, m, loff, tr);
+    PCHECK_LAUNCH();
+}
+
+void launch_emit_ranked(const uint32_t *perm, int64_t m, const int64_t *loff, const int64_t *at,
+                        const uint32_t *lists, uint32_t *keys, uint32_t *vals, int64_t E, hipStream_t st)
+{
+    if (m <= 0) return;
+    emit_ranked_kernel<<<grid_for(m, 256), 256, 0, st>>>(perm, m, loff, at, lists, keys, vals, E);
+    PCHECK_LAUNCH();
+}
+
+void launch_bucket_from_sorted(const Batch &b, const uint32_t *keys, const uint32_t *ents, int64_t E, int64_t P,
+                               int64_t *bstart, uint32_t *bcnt, uint32_t *bmem, slot_t *bslot, int64_t *pos_of,
+                               int64_t *bent, hipStream_t st)
+{
+    bucket_starts_kernel<<<grid_for(E + 1, 256), 256, 0, st>>>(keys, E, P, bstart);
+    PCHECK_LAUNCH();
+    bucket_counts_kernel<<<grid_for(P, 256), 256, 0, st>>>(bstart, P, bcnt);
+    PCHECK_LAUNCH();
+    if (E > 0) {
+        bucket_members_kernel<<<grid_for(E, 256), 256, 0, st>>>(b, ents, E, bmem, bslot, pos_of, bent);
+        PCHECK_LAUNCH();
+    }
+}
+
+}  // namespace picasso

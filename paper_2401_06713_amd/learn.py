@@ -38,8 +38,12 @@ FIXED = (0.125, 2.0)
 # Network parameters trained by `python -m paper_2401_06713_amd.learn --train 200 --n-hi 30000`
 # (sweeps over 200 instances, n log-uniform in [1e3, 3e4], q in 16..96).
 PREDICTOR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "predictor.npy")
-GRID_F = (0.02, 0.04, 0.06, 0.08, 0.10, 0.125, 0.15, 0.20, 0.25)
-GRID_A = (1.0, 1.5, 2.0, 2.5, 3.0, 3.5, 4.0)
+# The grid: palettes 4%-17% of the vertices and alpha 1-3 (the paper sweeps
+# 1%-20% and 0.5-4.5, Sec. VI).  Smaller palettes with longer lists cost
+# tens of times the fixed run's edges, and alpha below 1 is outside the
+# predictor's output range [1, 4].
+GRID_F = (0.04, 0.06, 0.08, 0.09, 0.10, 0.11, 0.125, 0.14, 0.17)
+GRID_A = (1.0, 1.25, 1.5, 1.75, 2.0, 2.5, 3.0)
 GROUP_STRINGS = 2_000_000  # strings per batched sweep call
 
 
@@ -136,6 +140,7 @@ def sweep(cfgs, betas=BETAS, grid_f=GRID_F, grid_a=GRID_A, margin: float = 0.0, 
         seeds = [cfgs[i].seed for i in idx]
         rels = [cfgs[i].relation for i in idx]
         with pk.PicassoBatch([(insts[i][0], insts[i][1], cfgs[i].q) for i in idx]) as hb:
+            hb.set_option(pk.OPT_MEM_BUDGET, 1)  # count the edges, write no CSR: the sweep needs only counts
             t = time.perf_counter()
             nc_fixed, gcols = hb.color_batch(seeds, FIXED[0], FIXED[1], rels)
             ms_fixed = (time.perf_counter() - t) * 1e3
@@ -189,7 +194,7 @@ def train(X, Y, steps: int = 2000, batch: int = 256, lr: float = 3e-3, seed: int
     return mlp, loss
 
 
-def evaluate(mlp: pk.Mlp, cfgs, betas=(0.5,), judge: bool = False):
+def evaluate(mlp: pk.Mlp, cfgs, betas=(0.5,), judge: bool = False, log=None):
     """Per instance: fixed vs learned colours, largest |E_c|, time, peak
     bytes, for each beta.
 
@@ -222,6 +227,9 @@ def evaluate(mlp: pk.Mlp, cfgs, betas=(0.5,), judge: bool = False):
                                      "fixed_tail_ms": tail.ms, "learned": asdict(learned),
                                      "J_learned": objective(learned, fixed, beta), "schedule": sched.tolist(),
                                      "judged": st["judged"]})
+        if log:
+            log(f"evaluate: {cfg.name} fixed {fixed.colors} colours; learned " +
+                ", ".join(f"beta {b}: {out[float(b)][-1]['learned']['colors']}" for b in betas))
     return out
 
 
@@ -278,7 +286,7 @@ def main():
         rows, n_train = int(X.shape[0]), len(cfgs)
         np.save(args.out + ".npy", mlp.get_params())
     held = heldout_instances(args.heldout, args.heldout_n, args.heldout_q, args.heldout_pi)
-    res = evaluate(mlp, held, args.eval_betas)
+    res = evaluate(mlp, held, args.eval_betas, log=say)
     summary = {
         "betas": args.betas, "margin": args.margin, "grid_f": args.grid_f, "grid_a": args.grid_a,
         "train_instances": n_train, "n_range": [args.n_lo, args.n_hi], "rows": rows, "final_loss": loss,

@@ -86,11 +86,12 @@ def test_batch_bit_exact_per_instance(mixed, path):
 
 
 def test_batch_rounds_and_graph_options(mixed):
-    """Plain launches, odd round counts and one round per check give the
-    same colouring as the captured-graph default."""
+    """Plain launches, odd round counts, one round per check and either
+    colour-bucket build give the same colouring as the defaults."""
     insts, refs = mixed
     for opts in (((pk.OPT_GRAPH, 0),), ((pk.OPT_JP_BATCH, 3),), ((pk.OPT_JP_BATCH, 1),),
-                 ((pk.OPT_JP_BATCH, 64), (pk.OPT_GRAPH, 1))):
+                 ((pk.OPT_JP_BATCH, 64), (pk.OPT_GRAPH, 1)), ((pk.OPT_BUCKET_BUILD, 2),),
+                 ((pk.OPT_BUCKET_BUILD, 1),)):
         say("batch options", opts)
         nc, cols, _, _ = color_batch(insts, pk.PATH_AUTO, opts)
         for i, (rnc, rcol, _) in enumerate(refs):

@@ -31,7 +31,9 @@ def strings(n, q, probs=(0.25, 0.25, 0.25, 0.25), seed=0):
     (5000, 48, 25000, 25, 1, False),
     (3000, 20, 300, 64, 2, True),
     (1500, 20, 5000, 65, 3, True),      # 128-thread sampler blocks
-    (777, 20, 4000, 256, 5, True),      # largest T, 64-thread blocks
+    (777, 20, 4000, 256, 5, True),      # 64-thread blocks
+    (600, 20, 3000, 300, 2, True),      # 32-thread blocks
+    (300, 20, 1500, 1024, 3, False),    # largest T, 16-thread blocks
     (300, 20, 7, 7, 1, False),          # T = P
     (301, 20, 1, 1, 2, False),          # P = 1
 ])
@@ -121,9 +123,10 @@ def test_jp_equals_sequential_greedy(orc, seed):
 
 
 # ---------------------------------------------------------------- whole method
-def run_both(orc, x, z, q, seed, frac, alpha, rel, fixed_T=0, path=pk.PATH_AUTO):
+def run_both(orc, x, z, q, seed, frac, alpha, rel, fixed_T=0, path=pk.PATH_AUTO, bucket_build=0):
     with pk.Picasso(x, z, q) as h:
         h.set_option(pk.OPT_PAIR_PATH, path)
+        h.set_option(pk.OPT_BUCKET_BUILD, bucket_build)
         if fixed_T:
             h.set_option(pk.OPT_FIXED_T, fixed_T)
         nc, col = h.color(seed, frac, alpha, rel)
@@ -204,6 +207,70 @@ def test_edge_cases(orc):
     x, z = strings(400, 12, seed=6)
     run_both(orc, x, z, 12, 4, 1.0, 1.0, 0, fixed_T=256)
     run_both(orc, x, z, 12, 4, 0.3, 1.0, 1, fixed_T=3)
+
+
+@pytest.mark.parametrize("build", [1, 2])
+@pytest.mark.parametrize("n,q,probs,rel,frac,alpha,fixed_T", [
+    (5000, 48, (0.7, 0.1, 0.1, 0.1), 0, 0.125, 2.0, 0),
+    (3000, 100, (0.8, 0.2 / 3, 0.2 / 3, 0.2 / 3), 1, 0.05, 3.0, 0),
+    (2500, 24, (0.5, 0.2, 0.2, 0.1), 2, 0.01, 4.0, 0),   # buckets above 2048 members
+    (1500, 30, (0.7, 0.1, 0.1, 0.1), 0, 0.8, 1.0, 300),  # 16-bit slots
+])
+def test_bucket_builds_bit_exact(orc, build, n, q, probs, rel, frac, alpha, fixed_T):
+    """Both colour-bucket builds (atomics with per-bucket sorts; the radix
+    sort by priority then colour) give the oracle's whole run."""
+    say("bucket build", build, n, q, rel, frac, alpha, fixed_T)
+    x, z = strings(n, q, probs, seed=n + 3 * rel)
+    run_both(orc, x, z, q, 2, frac, alpha, rel, fixed_T=fixed_T, bucket_build=build)
+
+
+def test_long_lists(orc):
+    """Lists longer than 256 colours (slot indices past one byte): whole runs
+    bit-exact, the slot-wise colouring across several mask words."""
+    say("long lists")
+    x, z = strings(1500, 30, (0.7, 0.1, 0.1, 0.1), seed=15)
+    for rel in (0, 2):
+        run_both(orc, x, z, 30, 7, 0.8, 1.0, rel, fixed_T=300)
+    x, z = strings(600, 20, seed=16)
+    run_both(orc, x, z, 20, 8, 1.0, 1.0, 1, fixed_T=520)
+
+
+def test_edges_off_same_colours(orc):
+    """PICASSO_OPT_EDGES = 0 builds only the relation matrices: the colours
+    and iteration sizes are those of the full run, the edge counts -1."""
+    x, z = strings(6000, 48, (0.7, 0.1, 0.1, 0.1), seed=17)
+    with pk.Picasso(x, z, 48) as h:
+        nc, col = h.color(2, 0.125, 2.0, 0)
+        st = h.stats()
+        h.set_option(pk.OPT_EDGES, 0)
+        nc0, col0 = h.color(2, 0.125, 2.0, 0)
+        st0 = h.stats()
+    assert nc0 == nc and np.array_equal(col0, col)
+    for a, b in zip(st0["iters"], st["iters"]):
+        for k in ("m", "P", "T", "pair_tests", "colored", "offset"):
+            assert a[k] == b[k]
+        assert a["edges"] == -1 or a["pair_path"] == 0
+
+
+def test_aggressive_preset_commute(orc):
+    """The paper's aggressive setting (palette 3% of |V|, list size 30 ln|V|)
+    under COMMUTE at n = 20,000 (lists of 298 colours over 600, buckets of
+    about 10,000 members): colours and iteration sizes bit-exact against the
+    oracle's edge-free colouring (edge statistics off on both sides)."""
+    n, q = 20000, 48
+    x, z = strings(n, q, (0.7, 0.1, 0.1, 0.1), seed=18)
+    with pk.Picasso(x, z, q) as h:
+        h.set_option(pk.OPT_EDGES, 0)
+        nc, col = h.color(3, 0.03, 30.0, 2)
+        st = h.stats()
+    say("aggressive preset", nc, "colours", st["n_iters"], "iterations", st["iters"][0]["T"], "first T")
+    assert st["iters"][0]["T"] == 298
+    rnc, rcol, rst = orc.color_classes(x, z, q, 3, 0.03, 30.0, 2, count_edges=False)
+    assert nc == rnc and np.array_equal(col, rcol)
+    assert st["n_iters"] == len(rst)
+    for a, b in zip(st["iters"], rst):
+        for k in ("m", "P", "T", "colored", "offset"):
+            assert a[k] == b[k], (k, a[k], b[k])
 
 
 def test_empty_input():

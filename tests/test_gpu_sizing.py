@@ -46,7 +46,9 @@ def test_predicted_bound_holds(case):
     for it in its:
         assert it["edges"] <= it["edges_bound"] <= it["pair_tests"], it
         if it["edges"] >= 1_000_000:
-            assert it["edges_bound"] <= 1.1 * it["edges"], it
+            # the density is sampled from 16384 pairs and taken four standard
+            # errors high (about 3% at density 1/2)
+            assert it["edges_bound"] <= 1.08 * it["edges"], it
     assert st["csr_refills"] == 0
 
 

@@ -36,3 +36,17 @@ def test_predicted_edges_match_oracle(orc, n, q, probs, rel, frac, alpha):
     se = math.sqrt(max(rho * (1 - rho), 1e-4) / 4096) / max(rho, 1e-3)
     assert abs(predicted / actual - 1) < 4 * se + 0.02, (predicted, actual, rho)
     assert sizing.csr_bytes(n, actual) == 8 * (n + 1) + 8 * actual
+
+
+def test_pairs_sharing_a_vertex_are_independent():
+    """Two lists drawn against a third: the events "meets u's list" are
+    independent (every fixed T-subset is met with the same probability), so
+    the conflict-edge count has variance C(m,2) rho s (1 - s) with no
+    covariance terms; checked by enumeration of all triples of subsets."""
+    import itertools
+    for P, T in ((5, 2), (6, 2), (6, 3), (7, 3)):
+        subsets = [set(c) for c in itertools.combinations(range(P), T)]
+        n = len(subsets)
+        s = sizing.pair_share(P, T)
+        both = sum(1 for a in subsets for b in subsets for c in subsets if a & b and a & c)
+        assert both / n**3 == pytest.approx(s * s, rel=1e-12)
