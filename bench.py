@@ -137,8 +137,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-fixed comparison")
-    ap.add_argument("--beta", type=float, default=0.3,
-                    help="trade-off input of the learned parameters (weight of the colour count)")
+    ap.add_argument("--beta", type=float, default=None,
+                    help="trade-off input of the learned parameters (weight of the colour count); default: the "
+                         "beta the stored network's held-out evaluation accepted")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the timed steps, copy MIB MiB device to device once (a plain copy of known size "
                          "that calibrates the HBM byte counters of a profiler run)")
@@ -338,13 +339,19 @@ def main():
         # on a fresh handle so that peak device bytes count only its own run
         log("bench: learned vs fixed parameters")
         mlp = pk.Mlp(params)
-        cmp = {}
-        for name in ("fixed", "learned"):
+        summary_path = os.path.splitext(learn.PREDICTOR)[0] + ".json"
+        summary = json.load(open(summary_path)) if os.path.exists(summary_path) else {}
+        beta = args.beta if args.beta is not None else (summary.get("acceptance_beta") or 0.3)
+        cmp = {"beta": beta}
+        for name in ("fixed", "fixed_tail", "learned"):
             hh = pk.Picasso(xd, zd, cfg.q)
             hh.set_option(pk.OPT_PAIR_PATH, pk.PATH_VALU)
-            hh.set_option(pk.OPT_TAIL, 0)  # the learned run consults the network every iteration
-            run = (lambda: hh.color(args.seed, cfg.frac, cfg.alpha, cfg.relation)[0]) if name == "fixed" else \
-                (lambda: hh.color_learned(mlp, args.seed, cfg.relation, args.beta)[0])
+            # the learned run consults the network every iteration, so it
+            # cannot hand the last iterations to the tail kernel: the fixed
+            # run is timed both ways
+            hh.set_option(pk.OPT_TAIL, int(name == "fixed_tail"))
+            run = (lambda: hh.color(args.seed, cfg.frac, cfg.alpha, cfg.relation)[0]) if name != "learned" else \
+                (lambda: hh.color_learned(mlp, args.seed, cfg.relation, beta)[0])
             run()
             torch.cuda.synchronize()
             t1 = time.perf_counter()
@@ -358,8 +365,8 @@ def main():
                 cmp[name]["first_iteration_params"] = [sl["iters"][0]["P"], sl["iters"][0]["T"]]
             hh.close()
         mlp.close()
-        cmp["note"] = "host-output calls, tail kernel off for both (the learned run consults the network " \
-                      "every iteration); network trained on sweeps over 200 instances, n in [1e3, 3e4]"
+        cmp["note"] = "host-output calls; network trained on sweeps over %s instances, n in %s" % (
+            summary.get("train_instances"), summary.get("n_range"))
         line["learned_vs_fixed"] = cmp
     if args.copy_calibration > 0:
         src = torch.ones(args.copy_calibration << 20, dtype=torch.uint8, device="cuda")

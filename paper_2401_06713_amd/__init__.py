@@ -489,19 +489,6 @@ class Mlp:
         return loss.value
 
 
-def squash(o):
-    """Network outputs -> (palette fraction, list multiplier)."""
-    o = np.asarray(o, dtype=np.float64)
-    return 0.01 + 0.24 / (1 + np.exp(-o[..., 0])), 1.0 + 3.0 / (1 + np.exp(-o[..., 1]))
-
-
-def unsquash(frac, alpha):
-    """(palette fraction, list multiplier) -> network targets (inverse of squash)."""
-    u = np.clip((np.asarray(frac, dtype=np.float64) - 0.01) / 0.24, 1e-3, 1 - 1e-3)
-    w = np.clip((np.asarray(alpha, dtype=np.float64) - 1.0) / 3.0, 1e-3, 1 - 1e-3)
-    return np.stack([np.log(u / (1 - u)), np.log(w / (1 - w))], axis=-1)
-
-
 def list_color_csr(prio, lists, P: int, rowptr, adj, handle: Picasso | None = None):
     """Jones-Plassmann list colouring of a given symmetric CSR."""
     prio = np.ascontiguousarray(prio, dtype=np.uint64)

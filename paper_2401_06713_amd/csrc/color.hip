@@ -74,6 +74,7 @@ __device__ __forceinline__ void wake(const JpArgs &a, int64_t c2, int64_t pos, i
 __device__ __forceinline__ void release_later_slots(const JpArgs &a, int64_t l0, int k, int T, int32_t *out,
                                                     int32_t *out_count)
 {
+    // (slots k+1 .. T-1; the caller may pass an earlier end)
     constexpr int G = 4;
     for (int k0 = k + 1; k0 < T; k0 += G) {
         int64_t pos[G];
@@ -212,9 +213,9 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t from, uint64
                     const int k = staged ? mk[p] : a.bslot[base + p];
                     const int64_t l0 = a.loff[v];
                     const int T = (int)(a.loff[v + 1] - l0);
+                    const uint64_t kb = 1ull << (k & 63);
                     uint64_t *blk = a.blk + v * a.fw;
                     uint64_t *fre = a.fre + v * a.fw;
-                    const uint64_t kb = 1ull << (k & 63);
                     if (blocked) {
                         ns = ST_NOT;
                         const uint64_t old = atomicOr((unsigned long long *)&blk[k >> 6], kb);
@@ -240,7 +241,18 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t from, uint64
                         } else {
                             wait = true;
                         }
-                        if (!(was & kb)) release_later_slots(a, l0, k, T, out, out_count);
+                        if (!(was & kb)) {
+                            // the slots after the first slot j already found free
+                            // were released then: only k+1 .. j are new (j itself
+                            // stays unknown while v waits on lower slots, and v
+                            // now takes k or an earlier slot); if j < k, nothing
+                            int hi = T;
+                            if (a.fw == 1 && was) {
+                                const int j = __builtin_ctzll(was);
+                                hi = j < k ? k : j + 1;
+                            }
+                            if (hi > k + 1) release_later_slots(a, l0, k, hi, out, out_count);
+                        }
                     }
                 }
             }

@@ -8,6 +8,8 @@ oracle fed the same FP32 (f, alpha) schedule; an explicit schedule is
 bit-exact against the oracle's schedule driver; the fixed-parameter run
 serves as fallback (invalid network outputs) and judge.
 """
+import json
+import os
 import sys
 
 import numpy as np
@@ -68,8 +70,8 @@ def test_forward_within_1e4_of_fp64(orc):
         # layer sums where those cancel (the FP32 sum's own error scale)
         scale = np.maximum(np.abs(ref), output_term_scale(p, rows))
         assert np.all(np.abs(o - ref) <= 1e-4 * scale)
-        f, a = pk.squash(o)
-        fr, ar = pk.squash(ref)
+        f, a = learn.squash(o)
+        fr, ar = np.array([orc.mlp_squash(r) for r in ref]).T
         assert np.all(np.abs(f - fr) <= 1e-4 * fr) and np.all(np.abs(a - ar) <= 1e-4 * ar)
 
 
@@ -176,7 +178,7 @@ def constant_net(f, a):
     """Network parameters whose outputs are the same (f, alpha) for every
     input: all weights zero, output biases at the inverse squash."""
     p = np.zeros(pk.MLP_NPARAMS, np.float32)
-    p[-2:] = pk.unsquash(f, a).astype(np.float32)
+    p[-2:] = learn.unsquash(f, a).astype(np.float32)
     return p
 
 
@@ -212,3 +214,24 @@ def test_fallback_on_invalid_network_output():
         nf, colf = h.color(6, 0.125, 2.0, rel)
     assert np.isnan(sched).all()
     assert nl == nf and np.array_equal(coll, colf)
+
+
+def test_stored_predictor_on_heldout_instances():
+    """The stored network (trained on sweeps over instances with n in
+    [1e3, 1e5]) on two instances of the held-out evaluation set (n = 500,000,
+    q = 96) at the beta its evaluation records: colours at most the fixed
+    parameters', and a smaller largest conflict graph and device peak."""
+    if not os.path.exists(learn.PREDICTOR) or np.load(learn.PREDICTOR).shape != (pk.MLP_NPARAMS,):
+        pytest.skip("no stored network for this input width")
+    summary = json.load(open(os.path.splitext(learn.PREDICTOR)[0] + ".json"))
+    beta = float(summary["acceptance_beta"])
+    held = learn.heldout_instances(2, 500_000, 96, 0.75)
+    with pk.Mlp(np.load(learn.PREDICTOR)) as m:
+        res = learn.evaluate(m, held, (beta,), log=say)[beta]
+    for r in res:
+        say("held-out", r["seed"], "fixed", r["fixed"]["colors"], "learned", r["learned"]["colors"],
+            "edges", r["learned"]["max_edges"] / r["fixed"]["max_edges"],
+            "peak", r["learned"]["peak_bytes"] / r["fixed"]["peak_bytes"])
+        assert r["learned"]["colors"] <= r["fixed"]["colors"]
+        assert r["learned"]["max_edges"] < r["fixed"]["max_edges"]
+        assert r["learned"]["peak_bytes"] < r["fixed"]["peak_bytes"]
