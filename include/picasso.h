@@ -394,6 +394,34 @@ int64_t picasso_color_schedule(picasso_handle h, uint64_t seed, const double *pa
 int64_t picasso_color_learned(picasso_handle h, uint64_t seed, picasso_mlp mlp, double beta, int32_t relation,
                               int32_t *out_colors, float *out_schedule, int32_t max_sched);
 
+/* ---- Colouring without device allocation ------------------------------- */
+
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): the same colouring as
+ * picasso_color_device on a handle created from these strings, for at most
+ * PICASSO_NOALLOC_MAX_N strings, with no handle and no allocation.  Every
+ * iteration runs in one device workgroup; its working memory (staged
+ * strings, the (P, T) table, iteration records, a padding flag) is a fixed
+ * PICASSO_NOALLOC_SCRATCH_BYTES array that each device holds from the first
+ * call until the process ends.
+ * x_words, z_words: device, n*W uint64 each (W = ceil(q/64)), padding bits
+ * zero; out_colors: device, n int32 (global colour ids as from
+ * picasso_color_device); seed, palette_frac, list_size, relation: as in
+ * picasso_color; stream: hipStream_t to run on (NULL: the null stream).
+ * Returns the number of distinct colours, or PICASSO_EINVAL when
+ * n > PICASSO_NOALLOC_MAX_N, when some iteration's lists would exceed
+ * PICASSO_NOALLOC_MAX_LIST_ENTRIES entries (T x m), or on the argument
+ * errors of picasso_create / picasso_color.  Calls on one device share its
+ * array: calls that overlap on one device (other threads, other streams)
+ * race and must be serialised by the caller.  Returns after the stream has
+ * finished the work. */
+#define PICASSO_NOALLOC_MAX_N 256
+#define PICASSO_NOALLOC_MAX_LIST_ENTRIES 16384
+#define PICASSO_NOALLOC_SCRATCH_BYTES 65536
+int64_t picasso_color_device_noalloc(int64_t n, int32_t q, const uint64_t *x_words, const uint64_t *z_words,
+                                     uint64_t seed, double palette_frac, double list_size, int32_t relation,
+                                     int32_t *out_colors, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -57,6 +57,7 @@ EXPORTS = (
     "picasso_mlp_train_step",
     "picasso_color_schedule",
     "picasso_color_learned",
+    "picasso_color_device_noalloc",
 )
 MLP_NPARAMS = 4738
 MLP_INPUTS = 6
@@ -202,6 +203,8 @@ def lib() -> ctypes.CDLL:
     L.picasso_color_schedule.argtypes = [p, u64, p, p, i32, i32, p]
     L.picasso_color_learned.restype = i64
     L.picasso_color_learned.argtypes = [p, u64, p, dbl, i32, p, p, i32]
+    L.picasso_color_device_noalloc.restype = i64
+    L.picasso_color_device_noalloc.argtypes = [i64, i32, p, p, u64, dbl, dbl, i32, p, p]
     _lib = L
     return L
 

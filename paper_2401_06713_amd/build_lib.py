@@ -16,7 +16,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libpicasso.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["scan.hip", "radix.hip", "lists.hip", "relate.hip", "pairs.hip", "color.hip", "dynamic.hip", "tail.hip", "learned.hip", "api.hip"]
+SOURCES = ["scan.hip", "radix.hip", "lists.hip", "relate.hip", "pairs.hip", "color.hip", "dynamic.hip", "tail.hip", "learned.hip", "noalloc.hip", "api.hip"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",
