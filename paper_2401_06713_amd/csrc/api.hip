@@ -567,9 +567,12 @@ int32_t color_buckets(picasso_ctx *h, const Batch &b, int64_t m, int64_t E, int6
     j.nw_max = std::max<int64_t>((bi.max_size + 63) / 64, 1);
     j.fw = (T_max + 63) / 64;
     j.col = buf<int32_t>(h, h->col, (size_t)std::max<int64_t>(m, 1));
+    j.packed = T_max <= 32;
     j.blk = buf<uint64_t>(h, h->blk, (size_t)m * j.fw);
-    j.fre = buf<uint64_t>(h, h->fre, (size_t)m * j.fw);
-    j.nblk = buf<int32_t>(h, h->nblk, (size_t)std::max<int64_t>(m, 1));
+    if (!j.packed) {
+        j.fre = buf<uint64_t>(h, h->fre, (size_t)m * j.fw);
+        j.nblk = buf<int32_t>(h, h->nblk, (size_t)std::max<int64_t>(m, 1));
+    }
     j.st = buf<uint8_t>(h, h->st, (size_t)std::max<int64_t>(E, 1));
     j.dirty = buf<uint32_t>(h, h->dirty, (size_t)P);
     j.wake_at = buf<unsigned long long>(h, h->wake_at, (size_t)P);
@@ -582,8 +585,10 @@ int32_t color_buckets(picasso_ctx *h, const Batch &b, int64_t m, int64_t E, int6
     j.m = m;
     launch_fill_i32(j.col, m, COL_UNDECIDED, st);
     launch_fill_u64(j.blk, m * j.fw, 0ull, st);
-    launch_fill_u64(j.fre, m * j.fw, 0ull, st);
-    launch_fill_i32(j.nblk, m, 0, st);
+    if (!j.packed) {
+        launch_fill_u64(j.fre, m * j.fw, 0ull, st);
+        launch_fill_i32(j.nblk, m, 0, st);
+    }
     launch_fill_u8(j.st, E, 0, st);
     launch_fill_u64(reinterpret_cast<uint64_t *>(j.progress), 1, 0ull, st);
     launch_jp_all(j, st);

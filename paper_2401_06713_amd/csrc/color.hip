@@ -214,6 +214,43 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t from, uint64
                     const int64_t l0 = a.loff[v];
                     const int T = (int)(a.loff[v + 1] - l0);
                     const uint64_t kb = 1ull << (k & 63);
+                    if (a.packed) {
+                        // one atomic returns both masks: the decision needs no
+                        // further load (a blocked-slot count is their popcount)
+                        unsigned long long *w = (unsigned long long *)(a.blk + v);
+                        if (blocked) {
+                            ns = ST_NOT;
+                            const uint32_t bl = (uint32_t)atomicOr(w, (unsigned long long)kb) | (uint32_t)kb;
+                            if (__popc(bl) == T) {  // the last slot was blocked
+                                __hip_atomic_store(&a.col[v], COL_FAILED, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                                fin = true;
+                            } else {
+                                const int f = __builtin_ctz(~bl);
+                                if (f > k && f < T) wake(a, a.lists[l0 + f], a.pos_of[l0 + f], out, out_count);
+                            }
+                        } else {
+                            const uint64_t old = atomicOr(w, (unsigned long long)(kb << 32));
+                            const uint32_t bl = (uint32_t)old, fr = (uint32_t)(old >> 32);
+                            const uint32_t below_k = (uint32_t)(kb - 1ull);
+                            if ((bl & below_k) == below_k) {
+                                __hip_atomic_store(&a.col[v], (int32_t)c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                fin = true;
+                                ns = ST_TAKEN;
+                            } else {
+                                wait = true;
+                            }
+                            if (!(fr & (uint32_t)kb)) {
+                                // as below: only k+1 .. (first free slot j) are new
+                                int hi = T;
+                                if (fr) {
+                                    const int j = __builtin_ctz(fr);
+                                    hi = j < k ? k : j + 1;
+                                }
+                                if (hi > k + 1) release_later_slots(a, l0, k, hi, out, out_count);
+                            }
+                        }
+                    } else {
                     uint64_t *blk = a.blk + v * a.fw;
                     uint64_t *fre = a.fre + v * a.fw;
                     if (blocked) {
@@ -253,6 +290,7 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t from, uint64
                             }
                             if (hi > k + 1) release_later_slots(a, l0, k, hi, out, out_count);
                         }
+                    }
                     }
                 }
             }

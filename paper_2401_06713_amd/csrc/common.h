@@ -233,6 +233,8 @@ struct JpArgs {
     int32_t *col;           // batch-wide colour, -1 failed, -2 undecided
     uint64_t *blk, *fre;    // m x fw: slots known blocked / known free
     int32_t *nblk;          // blocked-slot count per vertex
+    int32_t packed;         // lists of at most 32 slots: blk[v] holds both masks (blocked in
+                            // bits 0-31, free in bits 32-63), fre and nblk are unused
     uint8_t *st;            // per bucket entry: unknown / taken / not taken
     uint32_t *dirty;        // per bucket: waiting on a worklist
     unsigned long long *wake_at;  // per bucket: first bucket position changed since it was last taken
