@@ -55,8 +55,9 @@ enum {
 enum {
     PICASSO_OK = 0,
     PICASSO_EINVAL = -1,   /* bad argument; nothing was changed                */
-    PICASSO_ENOMEM = -2,   /* a device allocation failed, or the CSR asked of
-                              picasso_conflict_graph exceeds the memory budget */
+    PICASSO_ENOMEM = -2,   /* a device allocation failed, or one row of the
+                              CSR asked of picasso_conflict_graph exceeds the
+                              memory budget                                   */
     PICASSO_EDEVICE = -3,  /* a HIP call failed; the message names it           */
     PICASSO_EINTERNAL = -4 /* internal invariant violated                        */
 };
@@ -65,8 +66,10 @@ enum {
 enum {
     PICASSO_OPT_MEM_BUDGET = 1, /* max device bytes for one iteration's conflict
                                    graph (CSR); 0 = no limit beyond the device.
-                                   picasso_conflict_graph fails with ENOMEM above
-                                   it; the colouring calls count the edges and
+                                   Above it picasso_conflict_graph writes the
+                                   CSR in chunks of whole rows of at most this
+                                   many bytes (ENOMEM if one row exceeds it);
+                                   the colouring calls count the edges and
                                    skip writing the CSR (they colour from the
                                    per-bucket relation matrices)                */
     PICASSO_OPT_PAIR_PATH = 2,  /* 0 auto, 1 popcount VALU, 2 int8 MFMA          */
@@ -315,7 +318,10 @@ int32_t picasso_sample_lists(picasso_handle h, uint64_t seed, int32_t ell, int64
  * CSR in local indices: out_rowptr host int64[m+1]; out_adj host int32,
  * capacity adj_cap entries (2|E_c| are needed; rows are unordered).  Either
  * output may be NULL to only count.  Returns |E_c| (undirected) or an error;
- * if 2|E_c| > adj_cap nothing is written to out_adj. */
+ * if 2|E_c| > adj_cap nothing is written to out_adj.  When the CSR exceeds
+ * PICASSO_OPT_MEM_BUDGET it is filled and copied out in chunks of whole rows
+ * (Alg. 3 builds it on the host past the device's memory; here the device
+ * writes each chunk within the budget), with the same result. */
 int64_t picasso_conflict_graph(picasso_handle h, uint64_t seed, int32_t ell, int64_t m, const int32_t *ids,
                                int64_t P, int32_t T, int32_t relation, int64_t *out_rowptr, int32_t *out_adj,
                                int64_t adj_cap);

@@ -5,6 +5,7 @@
 // scan -> pair fill pass into the CSR -> list colouring -> write global
 // colours, compact the uncoloured vertices (ascending ids) -> next palette.
 // The only device->host traffic inside the loop is a few scalars.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -373,6 +374,9 @@ CsrArgs csr_args(picasso_ctx *h, const Batch &b, int64_t P)
     ca.loff = b.loff;
     ca.bent = static_cast<const int64_t *>(h->bent.p);
     ca.slot_off = static_cast<const int64_t *>(h->slot_off.p);
+    ca.v_lo = 0;
+    ca.v_hi = INT64_MAX;
+    ca.adj_base = 0;
     return ca;
 }
 
@@ -504,6 +508,36 @@ int64_t build_conflict_graph(picasso_ctx *h, const Batch &b, int64_t m, int64_t 
     if (ms_relate) *ms_relate = tm.ms(0, 1);
     if (ms_csr) *ms_csr = tm.ms(2, 3);
     return total / 2;
+}
+
+// The CSR of the last build_conflict_graph written to the host in chunks of
+// whole rows, each at most the memory budget: chunk [v0, v1) is filled on the
+// device from the bucket matrices (rows of other vertices skipped) and copied
+// to out_adj[rowptr[v0] .. rowptr[v1]).  rowptr: host copy of the row
+// pointers.  ENOMEM if one row alone exceeds the budget.
+void fill_csr_chunks(picasso_ctx *h, const Batch &b, int64_t m, int64_t P, const BucketInfo &bi, const int64_t *rowptr,
+                     int32_t *out_adj)
+{
+    const int64_t cap = h->mem_budget / (int64_t)sizeof(int32_t);
+    const int64_t total = rowptr[m];
+    int32_t *chunk = buf<int32_t>(h, h->adj, (size_t)std::max<int64_t>(std::min(cap, total), 1));
+    CsrArgs ca = csr_args(h, b, P);
+    ca.adj = chunk;
+    for (int64_t v0 = 0; v0 < m;) {
+        // the longest run of rows from v0 within the budget
+        const int64_t *end = std::upper_bound(rowptr + v0, rowptr + m + 1, rowptr[v0] + cap);
+        const int64_t v1 = (int64_t)(end - rowptr) - 1;
+        if (v1 <= v0)
+            throw Error(PICASSO_ENOMEM, "row " + std::to_string(v0) + " of the conflict graph needs " +
+                                            std::to_string((rowptr[v0 + 1] - rowptr[v0]) * 4) + " bytes, budget " +
+                                            std::to_string(h->mem_budget));
+        ca.v_lo = v0;
+        ca.v_hi = v1;
+        ca.adj_base = rowptr[v0];
+        launch_fill(ca, bi.max_size, h->stream);
+        download(h, out_adj + rowptr[v0], chunk, (size_t)(rowptr[v1] - rowptr[v0]) * sizeof(int32_t));
+        v0 = v1;
+    }
 }
 
 // Colouring rounds: `count` rounds starting from worklist `cur`, either
@@ -1509,9 +1543,24 @@ int64_t picasso_conflict_graph(picasso_handle h, uint64_t seed, int32_t ell, int
             upload(h, d_ids, ids, (size_t)m * sizeof(int32_t));
             Batch b = single_instance(h, seed, m, P, T, relation);
             const BucketInfo bi = build_lists_and_buckets(h, b, (uint32_t)ell, m, d_ids, m * T, P, T);
-            const int64_t edges = build_conflict_graph(h, b, m, m * T, P, T, 1 << relation, bi, nullptr, nullptr);
-            if (out_rowptr) download(h, out_rowptr, h->rowptr.p, (size_t)(m + 1) * sizeof(int64_t));
-            if (out_adj && 2 * edges <= adj_cap) download(h, out_adj, h->adj.p, (size_t)(2 * edges) * sizeof(int32_t));
+            // above the memory budget the CSR is counted here and written in chunks below
+            const int64_t edges =
+                build_conflict_graph(h, b, m, m * T, P, T, 1 << relation, bi, nullptr, nullptr, nullptr, false);
+            const int64_t total = 2 * edges;
+            const bool whole = h->mem_budget <= 0 || total * (int64_t)sizeof(int32_t) <= h->mem_budget;
+            std::vector<int64_t> rp;
+            int64_t *rowptr = out_rowptr;
+            if (!rowptr && out_adj && total <= adj_cap && !whole) {
+                rp.resize((size_t)m + 1);
+                rowptr = rp.data();
+            }
+            if (rowptr) download(h, rowptr, h->rowptr.p, (size_t)(m + 1) * sizeof(int64_t));
+            if (out_adj && total <= adj_cap) {
+                if (whole)
+                    download(h, out_adj, h->adj.p, (size_t)total * sizeof(int32_t));
+                else
+                    fill_csr_chunks(h, b, m, P, bi, rowptr, out_adj);
+            }
             return edges;
         },
         PICASSO_EINTERNAL);

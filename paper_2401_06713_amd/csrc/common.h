@@ -210,6 +210,8 @@ struct CsrArgs {
     const int64_t *slot_off; // fill pass: exclusive scan of slot_cnt
     int32_t *adj;            // fill pass: CSR column indices
     const int32_t *skip;     // fill pass: if non-null and nonzero, write nothing
+    int64_t v_lo, v_hi;      // fill pass: only the rows of vertices in [v_lo, v_hi) ...
+    int64_t adj_base;        // ... written at adj[CSR position - adj_base]
 };
 void launch_count(const CsrArgs &a, hipStream_t st);
 void launch_fill(const CsrArgs &a, int64_t max_size, hipStream_t st);  // max_size: largest bucket

@@ -445,7 +445,8 @@ __global__ void __launch_bounds__(kWave * kFillWaves) fill_kernel(CsrArgs a, int
             for (int64_t w = threadIdx.x; w < S * nw; w += blockDim.x) rows[w] = Rm[w] & ~Dm[w];
             __syncthreads();
             for (int64_t p = wave; p < S; p += kFillWaves) {
-                int64_t at = seg[p];
+                if ((int64_t)mv[p] < a.v_lo || (int64_t)mv[p] >= a.v_hi) continue;  // another chunk's row
+                int64_t at = seg[p] - a.adj_base;
                 for (int64_t w = 0; w < nw; ++w) {
                     const uint64_t bits = rows[p * nw + w];
                     const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bits >> 32),
@@ -456,7 +457,9 @@ __global__ void __launch_bounds__(kWave * kFillWaves) fill_kernel(CsrArgs a, int
             }
         } else {
             for (int64_t p = wave; p < S; p += kFillWaves) {
-                int64_t at = a.slot_off[a.bent[base + p]];
+                const int64_t v = a.bmem[base + p];
+                if (v < a.v_lo || v >= a.v_hi) continue;  // another chunk's row
+                int64_t at = a.slot_off[a.bent[base + p]] - a.adj_base;
                 for (int64_t w = 0; w < nw; ++w) {
                     const uint64_t bits = Rm[p * nw + w] & ~Dm[p * nw + w];
                     const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bits >> 32),

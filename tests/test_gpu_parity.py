@@ -301,16 +301,25 @@ def test_memory_budget(orc):
     with pk.Picasso(x, z, 16) as h:
         nc0, col0 = h.color(0, 0.125, 2.0, 0)
         e0 = h.stats()["edges"]
-        h.set_option(pk.OPT_MEM_BUDGET, 1024)
-        # the CSR itself cannot be had under the budget ...
+        e1 = h.stats()["iters"][0]["edges"]
         ids = np.arange(h.n, dtype=np.int32)
         P, T = orc.params(h.n, 0.125, 2.0)
+        rp0, adj0 = h.conflict_graph(0, 1, ids, P, T, 0)
+        assert 2 * e1 == adj0.shape[0] and adj0.nbytes > 16 * 65536
+        h.set_option(pk.OPT_MEM_BUDGET, 65536)
+        # the CSR is written in chunks of whole rows of at most 64 KiB (more
+        # than 16 of them): the same row pointers and adjacency
+        rp, adj = h.conflict_graph(0, 1, ids, P, T, 0)
+        assert np.array_equal(rp, rp0) and np.array_equal(adj, adj0)
+        assert h.conflict_rowptr(0, 1, ids, P, T, 0)[0] == e1
+        # the colouring does not need the CSR: same colours, edges still counted
+        nc, col = h.color(0, 0.125, 2.0, 0)
+        assert nc == nc0 and np.array_equal(col, col0) and h.stats()["edges"] == e0
+        # a budget below the longest row cannot be met
+        h.set_option(pk.OPT_MEM_BUDGET, 4 * (int(np.diff(rp0).max()) - 1))
         with pytest.raises(pk.PicassoError) as ei:
             h.conflict_graph(0, 1, ids, P, T, 0)
         assert ei.value.code == pk.ENOMEM
-        # ... but the colouring does not need it: same colours, edges still counted
-        nc, col = h.color(0, 0.125, 2.0, 0)
-        assert nc == nc0 and np.array_equal(col, col0) and h.stats()["edges"] == e0
         h.set_option(pk.OPT_MEM_BUDGET, 0)
 
 
