@@ -137,9 +137,10 @@ constexpr int kJpResweeps = 4;  // extra sweeps of a bucket woken again during i
 // walks the bucket in chunks of 64 members, each lane testing its member's
 // relation row prefix against the chunk states (taken / unknown bits in LDS);
 // dependencies inside a chunk settle in registers (ballots), and the chunk's
-// final taken/unknown bits are what later chunks see.
-// A member waiting on an earlier unknown member needs nothing but its row:
-// per-vertex state is read only by members that decide.  What other buckets
+// final taken/unknown bits are what later chunks see.  Per-vertex state is
+// read once per chunk, before the settle (whether v's lower slots are all
+// blocked), and the chunk's decisions are published after it, so the settle
+// steps wait on no memory.  What other buckets
 // decide about v reaches this bucket through the status bytes: a slot found
 // free marks v's later slots not-taken there, and v's earlier slots are
 // blocked, so a vertex coloured elsewhere never looks undecided here for long
@@ -193,7 +194,26 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t from, uint64
         bool open = (unk_ch >> lane) & 1ull;  // still to decide in this sweep
         bool hit_tak_prev = false, hit_unk_prev = false;
         uint64_t own = 0ull;
+        int64_t v = 0, l0 = 0;
+        int k = 0, T = 0;
+        bool low_blocked = false;  // v's slots below k all known blocked when the chunk began
         if (open) {
+            v = staged ? mv[p] : a.bmem[base + p];
+            k = staged ? mk[p] : a.bslot[base + p];
+            l0 = a.loff[v];
+            T = (int)(a.loff[v + 1] - l0);
+            // blocked bits only ever get set, so "all lower slots blocked" read
+            // now stays true; if it reads false and the last lower slot is
+            // blocked later, that blocker wakes this bucket (slot k is then v's
+            // first open slot) and a later sweep takes it
+            if (k == 0)
+                low_blocked = true;
+            else if (a.packed) {
+                const uint32_t need = (1u << k) - 1u;
+                low_blocked = ((uint32_t)load_u64(a.blk + v) & need) == need;
+            } else {
+                low_blocked = all_below(a.blk + v * a.fw, k);
+            }
             // earlier chunks are final for this sweep
             for (int64_t w = 0; w < ch; ++w) {
                 const uint64_t r = Rm[p * nw + w];
@@ -202,111 +222,109 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t from, uint64
             }
             own = Rm[p * nw + ch] & below;
         }
+        // Settle the chunk in registers: no memory access between ballots.
+        // act: 0 nothing, 1 slot blocked, 2 slot free and taken, 3 slot free
+        // while v waits on lower slots (stays unknown here).
+        int act = 0;
         while (true) {
             uint8_t ns = ST_UNKNOWN;
-            bool wait = false;  // free here, waiting for v's lower slots: no change in this sweep
-            bool fin = false;   // v's colour (or failure) was decided here
             if (open) {
-                const bool blocked = hit_tak_prev || (own & tak_ch);
-                if (blocked || !(hit_unk_prev || (own & unk_ch))) {
-                    const int64_t v = staged ? mv[p] : a.bmem[base + p];
-                    const int k = staged ? mk[p] : a.bslot[base + p];
-                    const int64_t l0 = a.loff[v];
-                    const int T = (int)(a.loff[v + 1] - l0);
-                    const uint64_t kb = 1ull << (k & 63);
-                    if (a.packed) {
-                        // one atomic returns both masks: the decision needs no
-                        // further load (a blocked-slot count is their popcount)
-                        unsigned long long *w = (unsigned long long *)(a.blk + v);
-                        if (blocked) {
-                            ns = ST_NOT;
-                            const uint32_t bl = (uint32_t)atomicOr(w, (unsigned long long)kb) | (uint32_t)kb;
-                            if (__popc(bl) == T) {  // the last slot was blocked
-                                __hip_atomic_store(&a.col[v], COL_FAILED, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-                                fin = true;
-                            } else {
-                                const int f = __builtin_ctz(~bl);
-                                if (f > k && f < T) wake(a, a.lists[l0 + f], a.pos_of[l0 + f], out, out_count);
-                            }
-                        } else {
-                            const uint64_t old = atomicOr(w, (unsigned long long)(kb << 32));
-                            const uint32_t bl = (uint32_t)old, fr = (uint32_t)(old >> 32);
-                            const uint32_t below_k = (uint32_t)(kb - 1ull);
-                            if ((bl & below_k) == below_k) {
-                                __hip_atomic_store(&a.col[v], (int32_t)c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                                fin = true;
-                                ns = ST_TAKEN;
-                            } else {
-                                wait = true;
-                            }
-                            if (!(fr & (uint32_t)kb)) {
-                                // as below: only k+1 .. (first free slot j) are new
-                                int hi = T;
-                                if (fr) {
-                                    const int j = __builtin_ctz(fr);
-                                    hi = j < k ? k : j + 1;
-                                }
-                                if (hi > k + 1) release_later_slots(a, l0, k, hi, out, out_count);
-                            }
-                        }
+                if (hit_tak_prev || (own & tak_ch)) {
+                    ns = ST_NOT;
+                    act = 1;
+                } else if (!(hit_unk_prev || (own & unk_ch))) {
+                    if (low_blocked) {
+                        ns = ST_TAKEN;
+                        act = 2;
                     } else {
-                    uint64_t *blk = a.blk + v * a.fw;
-                    uint64_t *fre = a.fre + v * a.fw;
-                    if (blocked) {
-                        ns = ST_NOT;
-                        const uint64_t old = atomicOr((unsigned long long *)&blk[k >> 6], kb);
-                        if (atomicAdd(&a.nblk[v], 1) == T - 1) {  // the last slot was blocked
-                            __hip_atomic_store(&a.col[v], COL_FAILED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            fin = true;
-                        } else {
-                            int f;
-                            if (a.fw == 1) {
-                                const uint64_t nb = ~(old | kb);
-                                f = nb ? __builtin_ctzll(nb) : 64;
-                            } else {
-                                f = first_open(blk, T);
-                            }
-                            if (f > k && f < T) wake(a, a.lists[l0 + f], a.pos_of[l0 + f], out, out_count);
-                        }
-                    } else {
-                        const uint64_t was = atomicOr((unsigned long long *)&fre[k >> 6], kb);
-                        if (all_below(blk, k)) {
-                            __hip_atomic_store(&a.col[v], (int32_t)c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            fin = true;
-                            ns = ST_TAKEN;
-                        } else {
-                            wait = true;
-                        }
-                        if (!(was & kb)) {
-                            // the slots after the first slot j already found free
-                            // were released then: only k+1 .. j are new (j itself
-                            // stays unknown while v waits on lower slots, and v
-                            // now takes k or an earlier slot); if j < k, nothing
-                            int hi = T;
-                            if (a.fw == 1 && was) {
-                                const int j = __builtin_ctzll(was);
-                                hi = j < k ? k : j + 1;
-                            }
-                            if (hi > k + 1) release_later_slots(a, l0, k, hi, out, out_count);
-                        }
-                    }
+                        act = 3;
                     }
                 }
+                if (act) open = false;
             }
-            // decided vertices, counted once per wave step (one atomic per
-            // vertex on a single counter serialises at this scale)
-            const uint64_t fins = __ballot(fin);
-            if (lane == 0 && fins) atomicAdd(a.progress, (unsigned long long)__popcll(fins));
-            const bool decided = ns != ST_UNKNOWN;
-            const uint64_t dec = __ballot(decided);
+            const uint64_t dec = __ballot(ns != ST_UNKNOWN);
             const uint64_t tk = __ballot(ns == ST_TAKEN);
-            if (decided) __hip_atomic_store(&a.st[base + p], ns, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (decided || wait) open = false;
             tak_ch |= tk;
             unk_ch &= ~dec;
             if (!dec) break;  // lanes still open wait on an undecided earlier member
         }
+        // Publish the chunk's decisions: status bytes and colours, then the
+        // per-vertex slot masks, failures and the wakes they imply (all lanes'
+        // atomics in flight together).
+        bool fin = false;  // v's colour (or failure) was decided here
+        if (act) {
+            const uint64_t kb = 1ull << (k & 63);
+            if (act != 3)
+                __hip_atomic_store(&a.st[base + p], act == 1 ? ST_NOT : ST_TAKEN, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            if (act == 2) {
+                __hip_atomic_store(&a.col[v], (int32_t)c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                fin = true;
+            }
+            if (a.packed) {
+                // blocked mask in bits 0-31, free mask in bits 32-63: one atomic
+                // returns both (a blocked-slot count is their popcount)
+                unsigned long long *w = (unsigned long long *)(a.blk + v);
+                if (act == 1) {
+                    const uint32_t bl = (uint32_t)atomicOr(w, (unsigned long long)kb) | (uint32_t)kb;
+                    if (__popc(bl) == T) {  // the last slot was blocked
+                        __hip_atomic_store(&a.col[v], COL_FAILED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        fin = true;
+                    } else {
+                        const int f = __builtin_ctz(~bl);
+                        if (f > k && f < T) wake(a, a.lists[l0 + f], a.pos_of[l0 + f], out, out_count);
+                    }
+                } else {
+                    const uint32_t fr = (uint32_t)(atomicOr(w, (unsigned long long)(kb << 32)) >> 32);
+                    if (!(fr & (uint32_t)kb)) {
+                        // as below: only k+1 .. (first free slot j) are new
+                        int hi = T;
+                        if (fr) {
+                            const int j = __builtin_ctz(fr);
+                            hi = j < k ? k : j + 1;
+                        }
+                        if (hi > k + 1) release_later_slots(a, l0, k, hi, out, out_count);
+                    }
+                }
+            } else {
+                uint64_t *blk = a.blk + v * a.fw;
+                uint64_t *fre = a.fre + v * a.fw;
+                if (act == 1) {
+                    const uint64_t old = atomicOr((unsigned long long *)&blk[k >> 6], kb);
+                    if (atomicAdd(&a.nblk[v], 1) == T - 1) {  // the last slot was blocked
+                        __hip_atomic_store(&a.col[v], COL_FAILED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        fin = true;
+                    } else {
+                        int f;
+                        if (a.fw == 1) {
+                            const uint64_t nb = ~(old | kb);
+                            f = nb ? __builtin_ctzll(nb) : 64;
+                        } else {
+                            f = first_open(blk, T);
+                        }
+                        if (f > k && f < T) wake(a, a.lists[l0 + f], a.pos_of[l0 + f], out, out_count);
+                    }
+                } else {
+                    const uint64_t was = atomicOr((unsigned long long *)&fre[k >> 6], kb);
+                    if (!(was & kb)) {
+                        // the slots after the first slot j already found free
+                        // were released then: only k+1 .. j are new (j itself
+                        // stays unknown while v waits on lower slots, and v
+                        // now takes k or an earlier slot); if j < k, nothing
+                        int hi = T;
+                        if (a.fw == 1 && was) {
+                            const int j = __builtin_ctzll(was);
+                            hi = j < k ? k : j + 1;
+                        }
+                        if (hi > k + 1) release_later_slots(a, l0, k, hi, out, out_count);
+                    }
+                }
+            }
+        }
+        // decided vertices, counted once per chunk (one atomic per vertex on a
+        // single counter serialises at this scale)
+        const uint64_t fins = __ballot(fin);
+        if (lane == 0 && fins) atomicAdd(a.progress, (unsigned long long)__popcll(fins));
         if (lane == 0) {
             tak[ch] = tak_ch;
             unk[ch] = unk_ch;
@@ -314,6 +332,159 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t from, uint64
         __syncthreads();
     }
 }
+
+// The sweep of a bucket of at most NW chunks whose vertices have lists of at
+// most 32 colours (blocked and free masks in one word), with the rule of
+// resolve_bucket and every memory access batched: the lane's member of each
+// chunk (status, vertex, slot) in one set of loads; for the members still
+// unknown, the list offset and length, the blocked mask and the relation row
+// words of earlier chunks in a second; the chunks settle in registers; then
+// all status bytes and colours are written, one slot-mask atomic per decided
+// member is issued for every chunk before any result is used, and the
+// failures, wakes and releases follow.
+template <int NW>
+__device__ void sweep_small(const JpArgs &a, int64_t c, int64_t base, int S, int nw, const uint64_t *Rm, uint64_t from,
+                            int32_t *out, int32_t *out_count)
+{
+    const int lane = threadIdx.x;
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int ch0 = from <= (uint64_t)base ? 0 : (int)((from - (uint64_t)base) >> 6);
+    uint8_t s[NW];
+    uint32_t v[NW];
+    int k[NW];
+#pragma unroll
+    for (int ch = 0; ch < NW; ++ch) {
+        const int p = ch * kWave + lane;
+        s[ch] = ST_NOT;
+        v[ch] = 0u;
+        k[ch] = 0;
+        if (ch < nw && p < S) {
+            s[ch] = __hip_atomic_load(&a.st[base + p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (ch >= ch0) {
+                v[ch] = a.bmem[base + p];
+                k[ch] = a.bslot[base + p];
+            }
+        }
+    }
+    uint64_t unk[NW], tak[NW];
+#pragma unroll
+    for (int ch = 0; ch < NW; ++ch) {
+        unk[ch] = __ballot(s[ch] == ST_UNKNOWN);
+        tak[ch] = __ballot(s[ch] == ST_TAKEN);
+    }
+    int64_t l0[NW];
+    int T[NW];
+    uint32_t blw[NW];
+    uint64_t r[NW][NW];
+#pragma unroll
+    for (int ch = 0; ch < NW; ++ch) {
+        l0[ch] = 0;
+        T[ch] = 0;
+        blw[ch] = 0u;
+#pragma unroll
+        for (int w = 0; w <= ch; ++w) r[ch][w] = 0ull;
+        if (ch >= ch0 && ch < nw && s[ch] == ST_UNKNOWN) {
+            const int64_t p = (int64_t)ch * kWave + lane;
+            l0[ch] = a.loff[v[ch]];
+            T[ch] = (int)(a.loff[v[ch] + 1] - l0[ch]);
+            // blocked bits only ever get set (see resolve_bucket)
+            if (k[ch]) blw[ch] = (uint32_t)load_u64(a.blk + v[ch]);
+#pragma unroll
+            for (int w = 0; w <= ch; ++w) r[ch][w] = Rm[p * nw + w];
+        }
+    }
+    // settle, chunk by chunk; act as in resolve_bucket
+    int act[NW];
+#pragma unroll
+    for (int ch = 0; ch < NW; ++ch) {
+        act[ch] = 0;
+        if (ch < ch0 || ch >= nw || unk[ch] == 0ull) continue;  // wave-uniform
+        uint64_t unk_ch = unk[ch], tak_ch = tak[ch];
+        bool open = (unk_ch >> lane) & 1ull;
+        bool hit_tak_prev = false, hit_unk_prev = false;
+#pragma unroll
+        for (int w = 0; w < ch; ++w) {
+            hit_tak_prev |= (r[ch][w] & tak[w]) != 0ull;
+            hit_unk_prev |= (r[ch][w] & unk[w]) != 0ull;
+        }
+        const uint64_t own = r[ch][ch] & below;
+        const uint32_t need = (1u << k[ch]) - 1u;
+        const bool low_blocked = (blw[ch] & need) == need;
+        while (true) {
+            uint8_t ns = ST_UNKNOWN;
+            if (open) {
+                if (hit_tak_prev || (own & tak_ch)) {
+                    ns = ST_NOT;
+                    act[ch] = 1;
+                } else if (!(hit_unk_prev || (own & unk_ch))) {
+                    if (low_blocked) {
+                        ns = ST_TAKEN;
+                        act[ch] = 2;
+                    } else {
+                        act[ch] = 3;
+                    }
+                }
+                if (act[ch]) open = false;
+            }
+            const uint64_t dec = __ballot(ns != ST_UNKNOWN);
+            tak_ch |= __ballot(ns == ST_TAKEN);
+            unk_ch &= ~dec;
+            if (!dec) break;
+        }
+        tak[ch] = tak_ch;
+        unk[ch] = unk_ch;
+    }
+    // publish: status bytes and colours, then the slot-mask atomics
+#pragma unroll
+    for (int ch = 0; ch < NW; ++ch) {
+        if (act[ch] == 1 || act[ch] == 2)
+            __hip_atomic_store(&a.st[base + (int64_t)ch * kWave + lane], act[ch] == 1 ? ST_NOT : ST_TAKEN,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (act[ch] == 2) __hip_atomic_store(&a.col[v[ch]], (int32_t)c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    uint64_t old[NW];
+#pragma unroll
+    for (int ch = 0; ch < NW; ++ch) {
+        old[ch] = 0ull;
+        if (act[ch]) {
+            const unsigned long long bit = 1ull << k[ch];
+            old[ch] = atomicOr((unsigned long long *)(a.blk + v[ch]), act[ch] == 1 ? bit : bit << 32);
+        }
+    }
+    int nfin = 0;
+#pragma unroll
+    for (int ch = 0; ch < NW; ++ch) {
+        if (!act[ch]) continue;
+        const uint32_t kb = 1u << k[ch];
+        if (act[ch] == 2) ++nfin;
+        if (act[ch] == 1) {
+            const uint32_t bl = (uint32_t)old[ch] | kb;
+            if (__popc(bl) == T[ch]) {  // the last slot was blocked
+                __hip_atomic_store(&a.col[v[ch]], COL_FAILED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ++nfin;
+            } else {
+                const int f = __builtin_ctz(~bl);
+                if (f > k[ch] && f < T[ch]) wake(a, a.lists[l0[ch] + f], a.pos_of[l0[ch] + f], out, out_count);
+            }
+        } else {
+            const uint32_t fr = (uint32_t)(old[ch] >> 32);
+            if (!(fr & kb)) {  // first free slot of v: release the later slots up to the next free one
+                int hi = T[ch];
+                if (fr) {
+                    const int j = __builtin_ctz(fr);
+                    hi = j < k[ch] ? k[ch] : j + 1;
+                }
+                if (hi > k[ch] + 1) release_later_slots(a, l0[ch], k[ch], hi, out, out_count);
+            }
+        }
+    }
+    // decided vertices of the sweep, one add per wave (nfin < 8)
+    const unsigned long long n = __popcll(__ballot(nfin & 1)) + 2 * __popcll(__ballot(nfin & 2)) +
+                                 4 * __popcll(__ballot(nfin & 4));
+    if (lane == 0 && n) atomicAdd(a.progress, n);
+}
+
+constexpr int kJpSmallChunks = 4;  // buckets of at most 256 members take sweep_small
 
 // One round of the worklist: visit the buckets listed by the previous round
 // (wl[cur], count in wl_slots[k]); state changes append the buckets they
@@ -341,7 +512,13 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(6)))
         // a bucket woken again while it was swept is swept again at once (its
         // pending position consumed: the next round's visit finds nothing)
         for (int sweep = 0; sweep <= kJpResweeps && from != ~0ull; ++sweep) {
-            resolve_bucket(a, c, from, tak, unk, mv, mk, out, out_count);
+            const int64_t base = a.bstart[c];
+            const int64_t S = a.bstart[c + 1] - base;
+            const int nwc = (int)((S + 63) >> 6);
+            if (a.packed && nwc <= kJpSmallChunks)
+                sweep_small<kJpSmallChunks>(a, c, base, (int)S, nwc, a.R + a.rb_off[c], from, out, out_count);
+            else
+                resolve_bucket(a, c, from, tak, unk, mv, mk, out, out_count);
             __syncthreads();
             if (threadIdx.x == 0)
                 from = __hip_atomic_exchange(&a.wake_at[c], ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
