@@ -10,6 +10,9 @@ SHA-256 of the little-endian int32 colour array and the per-iteration sizes.
     python tests/golden/make_golden.py C4 [workers]   # n = 2,000,000, q = 128, seed 0
     python tests/golden/make_golden.py C2dyn [divisor] # C2 seed 0, dynamic colourer (round form),
                                                      # with the sequential Alg. 2 colour count beside it
+    python tests/golden/make_golden.py Llearned [beta] # the first held-out instance coloured with the
+                                                     # stored network's parameters (FP64 twin), at the
+                                                     # beta its evaluation accepted unless given
 
 The C4 run colours each iteration from its colour classes (the oracle's
 edge-free mode: its conflict graph, 3.6e9 edges in iteration 1, does not fit
@@ -166,8 +169,57 @@ def c2_dynamic_main(divisor):
     print(out, nc, nseq, nst, flush=True)
 
 
+def learned_main(beta):
+    """Held-out instance 0 (n = 500,000, q = 96) coloured by Alg. 1 with each
+    iteration's (f, alpha) from the FP64 twin of the stored network, given the
+    iteration's features and beta.  Records the schedule and, per iteration,
+    how far f m and alpha ln m sit from the integers P and T round to (a
+    float32 evaluation of the network within 1e-4 relative of the FP64 one
+    gives the same P and T when these margins are larger)."""
+    import math
+
+    pkg = os.path.join(ROOT, "paper_2401_06713_amd")
+    params = np.load(os.path.join(pkg, "predictor.npy"))
+    summary = json.load(open(os.path.join(pkg, "predictor.json")))
+    if beta is None:
+        beta = float(summary["acceptance_beta"])
+    cfg = wl.LHELD0
+    oracle.build(force=False)
+    x, z = wl.make(cfg)
+    seed = cfg.seed
+    t = time.time()
+    nc, col, st, sched = oracle.color_learned(x, z, cfg.q, seed, params.astype(np.float64), cfg.relation, beta)
+    secs = round(time.time() - t, 1)
+    margins = []
+    for it, (f, a) in zip(st, sched):
+        m = it["m"]
+        fm, al = f * m, a * math.log(m) if m > 1 else 0.0
+
+        def rel_gap(v):
+            return abs(v - round(v)) / max(abs(v), 1e-300)
+
+        margins.append({"fm": fm, "fm_rel_gap": rel_gap(fm), "alpha_ln_m": al, "alpha_ln_m_rel_gap": rel_gap(al)})
+    rec = {
+        "config": cfg.name, "n": cfg.n, "q": cfg.q, "probs": list(cfg.probs), "gen_seed": cfg.seed, "seed": seed,
+        "relation": cfg.relation, "beta": beta,
+        "predictor_sha256": hashlib.sha256(open(os.path.join(pkg, "predictor.npy"), "rb").read()).hexdigest(),
+        "n_colors": nc,
+        "colors_sha256": hashlib.sha256(np.ascontiguousarray(col, dtype="<i4").tobytes()).hexdigest(),
+        "colors_head": col[:32].tolist(), "iters": st, "schedule": sched.tolist(), "rounding_margins": margins,
+        "oracle_seconds": secs,
+        "method": "Alg. 1 with the FP64 network twin choosing (f, alpha) per iteration; edge-free colouring "
+                  "(colour classes), edges counted",
+    }
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "l_learned_seed7000000.json")
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(out, nc, secs, flush=True)
+
+
 def main():
     name = sys.argv[1]
+    if name == "Llearned":
+        return learned_main(float(sys.argv[2]) if len(sys.argv) > 2 else None)
     if name == "C2dyn":
         return c2_dynamic_main(int(sys.argv[2]) if len(sys.argv) > 2 else 16)
     if name == "C3":

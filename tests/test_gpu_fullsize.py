@@ -1,7 +1,8 @@
 """Full-size workloads on the HIP path.
 
 C2 (n=200,000, q=48) and the first held-out instance of the learned
-evaluation (n=500,000, q=96): bit-exact against stored oracle results written
+evaluation (n=500,000, q=96), at the fixed parameters and with the stored
+network choosing them: bit-exact against stored oracle results written
 by tests/golden/make_golden.py (which calls only the CPU oracle), plus
 properties that hold at any size: every colour class is independent in the
 relation graph, colours lie in their iteration's palette, and each
@@ -116,6 +117,43 @@ def test_heldout_instance_matches_oracle():
         nc, col = h.color(g["seed"], cfg.frac, cfg.alpha, cfg.relation)
         st = h.stats()
     assert nc == g["n_colors"]
+    assert hashlib.sha256(np.ascontiguousarray(col, dtype="<i4").tobytes()).hexdigest() == g["colors_sha256"]
+    assert st["n_iters"] == len(g["iters"])
+    for a, b in zip(st["iters"], g["iters"]):
+        for k in ("m", "P", "T", "pair_tests", "edges", "colored", "offset"):
+            assert a[k] == b[k], (k, a[k], b[k])
+
+
+def test_heldout_learned_run_matches_oracle():
+    """The first held-out instance (n = 500,000) coloured with the stored
+    network choosing the parameters, at the beta its evaluation accepted,
+    against the oracle's run with its FP64 twin: each iteration's (f, alpha)
+    within 1e-6 relative (hence the same P and T: the stored rounding gaps are
+    wider), the colouring bit-exact, every iteration's sizes equal."""
+    gpath = os.path.join(GOLDEN, "l_learned_seed7000000.json")
+    if not os.path.exists(gpath):
+        pytest.skip("no stored oracle result for the learned run")
+    g = json.load(open(gpath))
+    pred = os.path.join(os.path.dirname(pk.__file__), "predictor.npy")
+    assert hashlib.sha256(open(pred, "rb").read()).hexdigest() == g["predictor_sha256"], \
+        "the stored network changed: write the learned run's stored result again (make_golden.py Llearned)"
+    # P = ceil(f m) and T = ceil(alpha ln m) flip only if f or alpha moves by
+    # the stored relative gap; every gap of this run exceeds 1e-6
+    for mg in g["rounding_margins"]:
+        assert mg["fm_rel_gap"] > 1e-6 and (mg["alpha_ln_m_rel_gap"] > 1e-6 or mg["alpha_ln_m"] == 0.0), mg
+    cfg = wl.LHELD0
+    say("held-out instance 0, learned, beta", g["beta"])
+    x, z = wl.make(cfg)
+    with pk.Picasso(x, z, cfg.q) as h, pk.Mlp(np.load(pred)) as mlp:
+        nc, col, sched = h.color_learned(mlp, g["seed"], cfg.relation, g["beta"])
+        st = h.stats()
+    ref = np.array(g["schedule"])
+    assert sched.shape == ref.shape
+    # the network's bar is 1e-4 relative; the gaps above need 1e-6, which the
+    # FP32 evaluation meets here (about 2e-7)
+    assert np.all(np.abs(sched - ref) <= 1e-6 * np.abs(ref))
+    assert nc == g["n_colors"]
+    assert col[:32].tolist() == g["colors_head"]
     assert hashlib.sha256(np.ascontiguousarray(col, dtype="<i4").tobytes()).hexdigest() == g["colors_sha256"]
     assert st["n_iters"] == len(g["iters"])
     for a, b in zip(st["iters"], g["iters"]):

@@ -108,6 +108,10 @@ def test_adam_step_matches_fp64(orc):
 
 @pytest.mark.parametrize("rel", [0, 1, 2])
 def test_learned_colouring_bit_exact(orc, rel):
+    """The learned colouring against the oracle's own (its FP64 network twin
+    choosing each iteration's parameters from its own features): the device's
+    FP32 schedule within 1e-4 relative of the twin's, the same P and T in
+    every iteration, and the same colours."""
     n, q = 4000, 48
     x, z = wl.pauli_strings(n, q, (0.7, 0.1, 0.1, 0.1), seed=11 + rel)
     beta = 0.25 + 0.25 * rel
@@ -116,23 +120,24 @@ def test_learned_colouring_bit_exact(orc, rel):
         st = h.stats()
         p = m.get_params().astype(np.float64)
     assert sched.shape[0] == st["n_iters"]
-    rnc, rcol, rst = orc.color_schedule(x, z, q, 5, sched[:, 0].astype(np.float64), sched[:, 1].astype(np.float64),
-                                        rel)
+    rnc, rcol, rst, rsched = orc.color_learned(x, z, q, 5, p, rel, beta)
+    assert sched.shape == rsched.shape
+    assert np.all(np.abs(sched - rsched) <= 1e-4 * np.abs(rsched))
     assert nc == rnc and np.array_equal(col, rcol)
-    # the schedule is the FP64 twin's output on the oracle's features, to 1e-4
-    for k, it in enumerate(rst):
-        ids = np.nonzero(rcol >= it["offset"])[0].astype(np.int32)
-        feat = np.r_[orc.features(x, z, q, ids, 5, k + 1, rel), beta]
-        f, a = orc.mlp_squash(orc.mlp_forward(p, feat[None, :])[0])
-        assert abs(sched[k, 0] - f) <= 1e-4 * f and abs(sched[k, 1] - a) <= 1e-4 * a
+    assert st["n_iters"] == len(rst)
+    for a, b in zip(st["iters"], rst):
+        for k in ("m", "P", "T", "pair_tests", "edges", "colored", "offset"):
+            assert a[k] == b[k], (k, a[k], b[k])
 
 
 def test_trained_predictor_gains_over_fixed():
     """Sweeps over small training instances, training on the device, and a
     held-out evaluation: the learned parameters must beat the fixed ones on the
-    sweep objective (colours and largest conflict graph, equal weight)."""
+    sweep objective (colours and largest conflict graph, equal weight) with no
+    more colours on average (labels ask for 1% fewer)."""
     train_cfgs = learn.training_instances(24, seed=2000, n_lo=1000, n_hi=8000)
-    X, Y, recs = learn.sweep(train_cfgs, (0.5,), grid_f=(0.04, 0.08, 0.125, 0.2), grid_a=(1.0, 2.0, 3.0), log=say)
+    X, Y, recs = learn.sweep(train_cfgs, (0.5,), grid_f=(0.04, 0.08, 0.125, 0.2), grid_a=(1.0, 2.0, 3.0),
+                             margin=0.01, log=say)
     assert X.shape[1] == pk.MLP_INPUTS and np.all(X[:, 5] == 0.5)
     mlp, loss = learn.train(X, Y, steps=1500, batch=128, lr=3e-3, log=say)
     held = learn.training_instances(6, seed=9000, n_lo=3000, n_hi=8000)
@@ -140,7 +145,7 @@ def test_trained_predictor_gains_over_fixed():
     J = [r["J_learned"] for r in res]
     say("held-out J (fixed = 1):", np.round(J, 3))
     assert np.mean(J) < 1.0
-    assert np.mean([r["learned"]["colors"] / r["fixed"]["colors"] for r in res]) <= 1.05
+    assert np.mean([r["learned"]["colors"] / r["fixed"]["colors"] for r in res]) <= 1.0
     mlp.close()
 
 
@@ -220,18 +225,22 @@ def test_stored_predictor_on_heldout_instances():
     """The stored network (trained on sweeps over instances with n in
     [1e3, 1e5]) on two instances of the held-out evaluation set (n = 500,000,
     q = 96) at the beta its evaluation records: colours at most the fixed
-    parameters', and a smaller largest conflict graph and device peak."""
+    parameters', a smaller largest conflict graph and device peak, and less
+    time than the fixed parameters with the tail kernel."""
     if not os.path.exists(learn.PREDICTOR) or np.load(learn.PREDICTOR).shape != (pk.MLP_NPARAMS,):
         pytest.skip("no stored network for this input width")
     summary = json.load(open(os.path.splitext(learn.PREDICTOR)[0] + ".json"))
     beta = float(summary["acceptance_beta"])
     held = learn.heldout_instances(2, 500_000, 96, 0.75)
     with pk.Mlp(np.load(learn.PREDICTOR)) as m:
-        res = learn.evaluate(m, held, (beta,), log=say)[beta]
+        res = learn.evaluate(m, held, (beta,), repeats=3, log=say)[beta]
     for r in res:
         say("held-out", r["seed"], "fixed", r["fixed"]["colors"], "learned", r["learned"]["colors"],
             "edges", r["learned"]["max_edges"] / r["fixed"]["max_edges"],
-            "peak", r["learned"]["peak_bytes"] / r["fixed"]["peak_bytes"])
+            "peak", r["learned"]["peak_bytes"] / r["fixed"]["peak_bytes"],
+            "ms", r["learned"]["ms"], "fixed (tail kernel on)", r["fixed_tail_ms"])
         assert r["learned"]["colors"] <= r["fixed"]["colors"]
         assert r["learned"]["max_edges"] < r["fixed"]["max_edges"]
         assert r["learned"]["peak_bytes"] < r["fixed"]["peak_bytes"]
+        # fastest of three calls each, against the fixed run with its tail kernel
+        assert r["learned"]["ms"] < r["fixed_tail_ms"]
