@@ -90,7 +90,7 @@ struct picasso_ctx {
     DevBuf x, z, xz;  // bit-planes, and the interleaved copy the member gather reads
     // iteration buffers
     DevBuf ids, next_ids, lists, prio, bcnt, bstart, bmem, bslot, pos_of, bent, tmp_mem, tmp_slot, tiles, words, tile_off,
-        rb_off, R, D, bx, bz, tile_bucket, nslow, slow, slot_cnt, slot_off, rowptr, adj, col, blk, fre, nblk, st,
+        rb_off, R, D, bx, bz, tile_bucket, nslow, slow, slot_cnt, slot_off, rowptr, adj, col, blk, fre, nblk, st, rdy, jp_prog,
         dirty, wake_at, wl, flags, pos, used, scan_tmp, scalars, out_colors, judge_out, inst, vinst, loff, binst,
         inst_out, tail_recs, tail_table, tail_outs, tail_iters, tail_ranges, hits, csr_flag, rkey, dyn_hist, dyn_sstar,
         dyn_cut, rx_k64a, rx_k64b, rx_va, rx_vb, rx_tmp, rx_tr, rx_at, rx_cka, rx_ckb, rx_cva, rx_cvb;
@@ -267,7 +267,7 @@ BucketInfo buckets_from_lists(picasso_ctx *h, Batch &b, int64_t m, int64_t E, in
         launch_emit_ranked(perm, m, b.loff, at, lists, cka, cva, E, st);
         int bits = 1;
         while (bits < 32 && ((int64_t)1 << bits) < P) ++bits;
-        const int f2 = radix_sort_pairs<uint32_t>(cka, cva, ckb, cvb, E, 0, (bits + 7) & ~7, rtmp, st);
+        const int f2 = radix_sort_pairs<uint32_t>(cka, cva, ckb, cvb, E, 0, bits, rtmp, st);
         launch_bucket_from_sorted(b, f2 ? ckb : cka, f2 ? cvb : cva, E, P, bstart, bcnt, bmem, bslot, pos_of, bent,
                                   st);
         launch_bucket_pairs(bcnt, P, sc, st);
@@ -598,6 +598,8 @@ int32_t color_buckets(picasso_ctx *h, const Batch &b, int64_t m, int64_t E, int6
     j.lists = static_cast<const uint32_t *>(h->lists.p);
     j.loff = b.loff;
     j.pos_of = static_cast<const int64_t *>(h->pos_of.p);
+    j.inst = b.inst;
+    j.binst = b.binst;
     j.nw_max = std::max<int64_t>((bi.max_size + 63) / 64, 1);
     j.fw = (T_max + 63) / 64;
     j.col = buf<int32_t>(h, h->col, (size_t)std::max<int64_t>(m, 1));
@@ -608,14 +610,18 @@ int32_t color_buckets(picasso_ctx *h, const Batch &b, int64_t m, int64_t E, int6
         j.nblk = buf<int32_t>(h, h->nblk, (size_t)std::max<int64_t>(m, 1));
     }
     j.st = buf<uint8_t>(h, h->st, (size_t)std::max<int64_t>(E, 1));
+    j.rdy = buf<uint8_t>(h, h->rdy, (size_t)std::max<int64_t>(E, 1));
     j.dirty = buf<uint32_t>(h, h->dirty, (size_t)P);
     j.wake_at = buf<unsigned long long>(h, h->wake_at, (size_t)P);
-    int32_t *wl = buf<int32_t>(h, h->wl, (size_t)2 * P + kJpSlots);
+    j.wl_cap = (P + kJpSeg - 1) / kJpSeg;
+    const int64_t wl_len = kJpSeg * j.wl_cap;
+    int32_t *wl = buf<int32_t>(h, h->wl, (size_t)(2 * wl_len + (int64_t)kJpSlots * kJpRow));
     j.wl[0] = wl;
-    j.wl[1] = wl + P;
-    j.wl_slots = wl + 2 * P;
-    unsigned long long *sc = buf<unsigned long long>(h, h->scalars, 8);
-    j.progress = sc + 2;
+    j.wl[1] = wl + wl_len;
+    j.wl_cnt = wl + 2 * wl_len;
+    unsigned long long *prog = buf<unsigned long long>(h, h->jp_prog, (size_t)kJpSeg * kJpProgStride + 2);
+    j.progress = prog;
+    j.totals = prog + (size_t)kJpSeg * kJpProgStride;
     j.m = m;
     launch_fill_i32(j.col, m, COL_UNDECIDED, st);
     launch_fill_u64(j.blk, m * j.fw, 0ull, st);
@@ -624,7 +630,8 @@ int32_t color_buckets(picasso_ctx *h, const Batch &b, int64_t m, int64_t E, int6
         launch_fill_i32(j.nblk, m, 0, st);
     }
     launch_fill_u8(j.st, E, 0, st);
-    launch_fill_u64(reinterpret_cast<uint64_t *>(j.progress), 1, 0ull, st);
+    launch_fill_u8(j.rdy, E, 0, st);
+    launch_fill_u64(reinterpret_cast<uint64_t *>(j.progress), (int64_t)kJpSeg * kJpProgStride + 2, 0ull, st);
     launch_jp_all(j, st);
     RoundGraph graph;
     const int32_t max_batch = std::max<int32_t>(h->jp_batch, 1);
@@ -644,11 +651,11 @@ int32_t color_buckets(picasso_ctx *h, const Batch &b, int64_t m, int64_t E, int6
             if (batch & 1) cur ^= 1;
         }
         rounds += batch;
-        unsigned long long done = 0;
-        int32_t pending = 0;
-        PCHECK_HIP(hipMemcpyAsync(&done, j.progress, sizeof(done), hipMemcpyDeviceToHost, st));
-        PCHECK_HIP(hipMemcpyAsync(&pending, &j.wl_slots[kJpCountCell], sizeof(pending), hipMemcpyDeviceToHost, st));
+        unsigned long long tot[2] = {0, 0};
+        PCHECK_HIP(hipMemcpyAsync(tot, j.totals, sizeof(tot), hipMemcpyDeviceToHost, st));
         PCHECK_HIP(hipStreamSynchronize(st));
+        const unsigned long long done = tot[0];
+        const unsigned long long pending = tot[1];
         if ((int64_t)done >= m) break;
         if (pending == 0) {
             // Nothing left on the worklist but vertices remain: start again
@@ -1298,7 +1305,7 @@ void picasso_destroy(picasso_handle h)
                      &h->bstart,  &h->bmem,     &h->bslot,   &h->pos_of,   &h->bent, &h->tmp_mem, &h->tmp_slot, &h->tiles,
                      &h->words,   &h->tile_off, &h->rb_off,  &h->R,        &h->D,       &h->nslow,    &h->slow,
                      &h->slot_cnt, &h->slot_off, &h->rowptr, &h->adj,      &h->col,     &h->blk,      &h->fre,
-                     &h->nblk,    &h->st,       &h->dirty,   &h->wl,       &h->flags,   &h->pos,      &h->used,
+                     &h->nblk,    &h->st,       &h->rdy,     &h->jp_prog, &h->dirty,   &h->wl,       &h->flags,   &h->pos,      &h->used,
                      &h->scan_tmp, &h->bx,      &h->bz,      &h->tile_bucket,
                      &h->scalars, &h->out_colors, &h->judge_out, &h->inst,    &h->vinst,    &h->loff,    &h->binst,    &h->inst_out, &h->tail_recs,
                      &h->tail_table, &h->tail_outs, &h->tail_iters, &h->tail_ranges, &h->wake_at,

@@ -37,18 +37,6 @@ __device__ __forceinline__ uint64_t load_u64(const uint64_t *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Bits [0, k) of a multi-word mask all set.
-__device__ __forceinline__ bool all_below(const uint64_t *m, int k)
-{
-    for (int w = 0; w < (k >> 6); ++w)
-        if (load_u64(&m[w]) != ~0ull) return false;
-    if (k & 63) {
-        const uint64_t need = (1ull << (k & 63)) - 1ull;
-        if ((load_u64(&m[k >> 6]) & need) != need) return false;
-    }
-    return true;
-}
-
 // Put bucket c2 on the next round's worklist unless it is already waiting,
 // noting the bucket position pos of the member whose state changed (members
 // before it cannot change because of it, so the next sweep of c2 starts at
@@ -57,12 +45,33 @@ __device__ __forceinline__ bool all_below(const uint64_t *m, int k)
 // written with coherent stores and atomics) before the bucket can be taken
 // off a list.  No cache flush or invalidate is needed: readers use coherent
 // loads.
+// Bucket c2 onto the next list: its segment's counter (row `cnt` of the
+// round's counters) gives its place.
+__device__ __forceinline__ void append(const JpArgs &a, int64_t c2, int32_t *out, int32_t *cnt)
+{
+    const int64_t sg = c2 % kJpSeg;
+    const int32_t at = atomicAdd(&cnt[sg * kJpCntStride], 1);
+    out[sg * a.wl_cap + at] = (int32_t)c2;
+}
+
 __device__ __forceinline__ void wake(const JpArgs &a, int64_t c2, int64_t pos, int32_t *out, int32_t *out_count)
 {
     __builtin_amdgcn_s_waitcnt(0);  // the state change is complete before its position is published
     atomicMin(&a.wake_at[c2], (unsigned long long)pos);
     if (__hip_atomic_exchange(&a.dirty[c2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
-        out[atomicAdd(out_count, 1)] = (int32_t)c2;
+        append(a, c2, out, out_count);
+}
+
+// The blocked slots of a vertex now run up to its slot at list entry e: that
+// member's bucket may let it take its colour.  Its ready byte is set first
+// (a sweep reads it with the bucket's status bytes instead of the vertex's
+// slot masks), then the bucket is woken at its position.
+__device__ __forceinline__ void ready_and_wake(const JpArgs &a, int64_t e, int32_t *out, int32_t *out_count)
+{
+    const int64_t pos = a.pos_of[e];
+    const uint32_t c2 = a.lists[e];
+    __hip_atomic_store(&a.rdy[pos], (uint8_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    wake(a, c2, pos, out, out_count);
 }
 
 // Slot k of v (list entries from l0, T of them) was found free: v takes
@@ -70,7 +79,7 @@ __device__ __forceinline__ void wake(const JpArgs &a, int64_t c2, int64_t pos, i
 // still unknown in its bucket is marked not-taken there and its bucket is
 // woken (members after v in it may have waited on v).  Groups of 4 slots:
 // independent loads, one wait so the marks are complete before any wake,
-// independent exchanges, one append per group.
+// independent exchanges.
 __device__ __forceinline__ void release_later_slots(const JpArgs &a, int64_t l0, int k, int T, int32_t *out,
                                                     int32_t *out_count)
 {
@@ -103,15 +112,9 @@ __device__ __forceinline__ void release_later_slots(const JpArgs &a, int64_t l0,
         for (int j = 0; j < G; ++j)
             old[j] = need[j] ? __hip_atomic_exchange(&a.dirty[cc[j]], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                              : 1u;
-        int n = 0;
 #pragma unroll
-        for (int j = 0; j < G; ++j) n += old[j] == 0u;
-        if (n) {
-            int at = atomicAdd(out_count, n);
-#pragma unroll
-            for (int j = 0; j < G; ++j)
-                if (old[j] == 0u) out[at++] = (int32_t)cc[j];
-        }
+        for (int j = 0; j < G; ++j)
+            if (old[j] == 0u) append(a, cc[j], out, out_count);
     }
 }
 
@@ -129,6 +132,7 @@ __device__ __forceinline__ int first_open(const uint64_t *blk, int T)
 }
 
 constexpr int kJpStage = 1024;  // members whose (vertex, slot) are staged in LDS
+static_assert(kJpSeg == kWave, "a round's workgroup (one wave) scans the segment lengths lane by lane");
 constexpr int kJpResweeps = 4;  // extra sweeps of a bucket woken again during its sweep
 
 // Resolve what can be resolved in bucket c.  A member depends only on the
@@ -137,10 +141,12 @@ constexpr int kJpResweeps = 4;  // extra sweeps of a bucket woken again during i
 // walks the bucket in chunks of 64 members, each lane testing its member's
 // relation row prefix against the chunk states (taken / unknown bits in LDS);
 // dependencies inside a chunk settle in registers (ballots), and the chunk's
-// final taken/unknown bits are what later chunks see.  Per-vertex state is
-// read once per chunk, before the settle (whether v's lower slots are all
-// blocked), and the chunk's decisions are published after it, so the settle
-// steps wait on no memory.  What other buckets
+// final taken/unknown bits are what later chunks see.  Whether v's lower
+// slots are all blocked is read from the member's ready byte (set by the
+// wave that blocked the last of them), beside its status byte, and the
+// chunk's decisions are published after the settle, so the settle steps wait
+// on no memory and no sweep reads per-vertex words at scattered addresses.
+// What other buckets
 // decide about v reaches this bucket through the status bytes: a slot found
 // free marks v's later slots not-taken there, and v's earlier slots are
 // blocked, so a vertex coloured elsewhere never looks undecided here for long
@@ -162,6 +168,9 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t from, uint64
     const int64_t nw = (S + 63) >> 6;
     const uint64_t *Rm = a.R + a.rb_off[c];
     const bool staged = S <= kJpStage;
+    // the bucket's members share an instance: list size and list offsets from its record
+    const InstRec &ir = a.inst[a.binst[c]];
+    const int T = ir.T;
     // the bucket's taken/unknown words, one ballot per chunk of 64 members
     __syncthreads();
     for (int64_t w = 0; w < nw; ++w) {
@@ -195,25 +204,19 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t from, uint64
         bool hit_tak_prev = false, hit_unk_prev = false;
         uint64_t own = 0ull;
         int64_t v = 0, l0 = 0;
-        int k = 0, T = 0;
+        int k = 0;
         bool low_blocked = false;  // v's slots below k all known blocked when the chunk began
         if (open) {
             v = staged ? mv[p] : a.bmem[base + p];
             k = staged ? mk[p] : a.bslot[base + p];
-            l0 = a.loff[v];
-            T = (int)(a.loff[v + 1] - l0);
+            l0 = ir.loff + (v - ir.vstart) * T;
             // blocked bits only ever get set, so "all lower slots blocked" read
             // now stays true; if it reads false and the last lower slot is
-            // blocked later, that blocker wakes this bucket (slot k is then v's
-            // first open slot) and a later sweep takes it
-            if (k == 0)
-                low_blocked = true;
-            else if (a.packed) {
-                const uint32_t need = (1u << k) - 1u;
-                low_blocked = ((uint32_t)load_u64(a.blk + v) & need) == need;
-            } else {
-                low_blocked = all_below(a.blk + v * a.fw, k);
-            }
+            // blocked later, that blocker sets the ready byte and wakes this
+            // bucket (slot k is then v's first open slot), and a later sweep
+            // takes it
+            low_blocked = k == 0 ||
+                          __hip_atomic_load(&a.rdy[base + p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
             // earlier chunks are final for this sweep
             for (int64_t w = 0; w < ch; ++w) {
                 const uint64_t r = Rm[p * nw + w];
@@ -272,7 +275,7 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t from, uint64
                         fin = true;
                     } else {
                         const int f = __builtin_ctz(~bl);
-                        if (f > k && f < T) wake(a, a.lists[l0 + f], a.pos_of[l0 + f], out, out_count);
+                        if (f > k && f < T) ready_and_wake(a, l0 + f, out, out_count);
                     }
                 } else {
                     const uint32_t fr = (uint32_t)(atomicOr(w, (unsigned long long)(kb << 32)) >> 32);
@@ -302,7 +305,7 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t from, uint64
                         } else {
                             f = first_open(blk, T);
                         }
-                        if (f > k && f < T) wake(a, a.lists[l0 + f], a.pos_of[l0 + f], out, out_count);
+                        if (f > k && f < T) ready_and_wake(a, l0 + f, out, out_count);
                     }
                 } else {
                     const uint64_t was = atomicOr((unsigned long long *)&fre[k >> 6], kb);
@@ -324,7 +327,8 @@ __device__ void resolve_bucket(const JpArgs &a, int64_t c, uint64_t from, uint64
         // decided vertices, counted once per chunk (one atomic per vertex on a
         // single counter serialises at this scale)
         const uint64_t fins = __ballot(fin);
-        if (lane == 0 && fins) atomicAdd(a.progress, (unsigned long long)__popcll(fins));
+        if (lane == 0 && fins)
+            atomicAdd(&a.progress[(blockIdx.x % kJpSeg) * kJpProgStride], (unsigned long long)__popcll(fins));
         if (lane == 0) {
             tak[ch] = tak_ch;
             unk[ch] = unk_ch;
@@ -349,18 +353,23 @@ __device__ void sweep_small(const JpArgs &a, int64_t c, int64_t base, int S, int
     const int lane = threadIdx.x;
     const uint64_t below = (1ull << lane) - 1ull;
     const int ch0 = from <= (uint64_t)base ? 0 : (int)((from - (uint64_t)base) >> 6);
-    uint8_t s[NW];
+    // the bucket's members share an instance: list size and list offsets from its record
+    const InstRec &ir = a.inst[a.binst[c]];
+    const int T = ir.T;
+    uint8_t s[NW], rd[NW];
     uint32_t v[NW];
     int k[NW];
 #pragma unroll
     for (int ch = 0; ch < NW; ++ch) {
         const int p = ch * kWave + lane;
         s[ch] = ST_NOT;
+        rd[ch] = 0;
         v[ch] = 0u;
         k[ch] = 0;
         if (ch < nw && p < S) {
             s[ch] = __hip_atomic_load(&a.st[base + p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (ch >= ch0) {
+                rd[ch] = __hip_atomic_load(&a.rdy[base + p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 v[ch] = a.bmem[base + p];
                 k[ch] = a.bslot[base + p];
             }
@@ -372,23 +381,13 @@ __device__ void sweep_small(const JpArgs &a, int64_t c, int64_t base, int S, int
         unk[ch] = __ballot(s[ch] == ST_UNKNOWN);
         tak[ch] = __ballot(s[ch] == ST_TAKEN);
     }
-    int64_t l0[NW];
-    int T[NW];
-    uint32_t blw[NW];
     uint64_t r[NW][NW];
 #pragma unroll
     for (int ch = 0; ch < NW; ++ch) {
-        l0[ch] = 0;
-        T[ch] = 0;
-        blw[ch] = 0u;
 #pragma unroll
         for (int w = 0; w <= ch; ++w) r[ch][w] = 0ull;
         if (ch >= ch0 && ch < nw && s[ch] == ST_UNKNOWN) {
             const int64_t p = (int64_t)ch * kWave + lane;
-            l0[ch] = a.loff[v[ch]];
-            T[ch] = (int)(a.loff[v[ch] + 1] - l0[ch]);
-            // blocked bits only ever get set (see resolve_bucket)
-            if (k[ch]) blw[ch] = (uint32_t)load_u64(a.blk + v[ch]);
 #pragma unroll
             for (int w = 0; w <= ch; ++w) r[ch][w] = Rm[p * nw + w];
         }
@@ -408,8 +407,8 @@ __device__ void sweep_small(const JpArgs &a, int64_t c, int64_t base, int S, int
             hit_unk_prev |= (r[ch][w] & unk[w]) != 0ull;
         }
         const uint64_t own = r[ch][ch] & below;
-        const uint32_t need = (1u << k[ch]) - 1u;
-        const bool low_blocked = (blw[ch] & need) == need;
+        // (ready bytes only ever get set: see resolve_bucket)
+        const bool low_blocked = k[ch] == 0 || rd[ch] != 0;
         while (true) {
             uint8_t ns = ST_UNKNOWN;
             if (open) {
@@ -456,39 +455,40 @@ __device__ void sweep_small(const JpArgs &a, int64_t c, int64_t base, int S, int
     for (int ch = 0; ch < NW; ++ch) {
         if (!act[ch]) continue;
         const uint32_t kb = 1u << k[ch];
+        const int64_t l0 = ir.loff + ((int64_t)v[ch] - ir.vstart) * T;
         if (act[ch] == 2) ++nfin;
         if (act[ch] == 1) {
             const uint32_t bl = (uint32_t)old[ch] | kb;
-            if (__popc(bl) == T[ch]) {  // the last slot was blocked
+            if (__popc(bl) == T) {  // the last slot was blocked
                 __hip_atomic_store(&a.col[v[ch]], COL_FAILED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 ++nfin;
             } else {
                 const int f = __builtin_ctz(~bl);
-                if (f > k[ch] && f < T[ch]) wake(a, a.lists[l0[ch] + f], a.pos_of[l0[ch] + f], out, out_count);
+                if (f > k[ch] && f < T) ready_and_wake(a, l0 + f, out, out_count);
             }
         } else {
             const uint32_t fr = (uint32_t)(old[ch] >> 32);
             if (!(fr & kb)) {  // first free slot of v: release the later slots up to the next free one
-                int hi = T[ch];
+                int hi = T;
                 if (fr) {
                     const int j = __builtin_ctz(fr);
                     hi = j < k[ch] ? k[ch] : j + 1;
                 }
-                if (hi > k[ch] + 1) release_later_slots(a, l0[ch], k[ch], hi, out, out_count);
+                if (hi > k[ch] + 1) release_later_slots(a, l0, k[ch], hi, out, out_count);
             }
         }
     }
     // decided vertices of the sweep, one add per wave (nfin < 8)
     const unsigned long long n = __popcll(__ballot(nfin & 1)) + 2 * __popcll(__ballot(nfin & 2)) +
                                  4 * __popcll(__ballot(nfin & 4));
-    if (lane == 0 && n) atomicAdd(a.progress, n);
+    if (lane == 0 && n) atomicAdd(&a.progress[(blockIdx.x % kJpSeg) * kJpProgStride], n);
 }
 
 constexpr int kJpSmallChunks = 4;  // buckets of at most 256 members take sweep_small
 
 // One round of the worklist: visit the buckets listed by the previous round
-// (wl[cur], count in wl_slots[k]); state changes append the buckets they
-// may unblock to wl[cur ^ 1], counted in wl_slots[k + 1].  No workgroup
+// (wl[cur], segment lengths in counter row k); state changes append the
+// buckets they may unblock to wl[cur ^ 1], counted in row k + 1.  No workgroup
 // waits on another: rounds are separate launches in stream order.
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(6))) jp_round_kernel(JpArgs a, int cur,
                                                                                                    int32_t k)
@@ -499,11 +499,30 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(6)))
     __shared__ uint32_t mv[kJpStage];
     __shared__ slot_t mk[kJpStage];
     __shared__ unsigned long long from;
-    const int32_t n_in = a.wl_slots[k];
+    __shared__ int32_t pre[kJpSeg + 1];  // segment starts of this round's list, and its length
+    {
+        // one wave: lane g holds segment g's length; inclusive prefix by shuffles
+        const int g = threadIdx.x;
+        int32_t x = g < kJpSeg ? a.wl_cnt[(int64_t)k * kJpRow + g * kJpCntStride] : 0;
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int32_t y = __shfl_up(x, d, kWave);
+            if (g >= d) x += y;
+        }
+        if (g < kJpSeg) pre[g + 1] = x;
+        if (g == 0) pre[0] = 0;
+        __syncthreads();
+    }
+    const int32_t n_in = pre[kJpSeg];
     int32_t *out = a.wl[cur ^ 1];
-    int32_t *out_count = &a.wl_slots[k + 1];
+    int32_t *out_count = a.wl_cnt + (int64_t)(k + 1) * kJpRow;
     for (int64_t i = blockIdx.x; i < n_in; i += gridDim.x) {
-        const int64_t c = a.wl[cur][i];
+        int lo = 0, hi = kJpSeg;  // pre[lo] <= i < pre[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (pre[mid] <= i) lo = mid;
+            else hi = mid;
+        }
+        const int64_t c = a.wl[cur][lo * a.wl_cap + (i - pre[lo])];
         if (threadIdx.x == 0) {
             __hip_atomic_exchange(&a.dirty[c], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             from = __hip_atomic_exchange(&a.wake_at[c], ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -534,26 +553,50 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(6)))
 // batch's rounds start at zero.  (A last-workgroup ticket that empties the
 // consumed list inside each round was measured slower: 16384 workgroups per
 // round on one counter cost about 80 us per round at n = 2M.)
-__global__ void jp_batch_begin_kernel(int32_t *slots, int32_t rounds)
+__global__ void jp_batch_begin_kernel(int32_t *cnt, int32_t rounds)
 {
-    const int32_t cur = slots[kJpCountCell];
-    for (int32_t i = threadIdx.x + 1; i <= rounds; i += blockDim.x) slots[i] = 0;
-    if (threadIdx.x == 0) slots[0] = cur;
+    for (int32_t i = threadIdx.x; i < kJpSeg; i += blockDim.x)
+        cnt[i * kJpCntStride] = cnt[(int64_t)kJpCountCell * kJpRow + i * kJpCntStride];
+    for (int64_t i = threadIdx.x; i < (int64_t)rounds * kJpSeg; i += blockDim.x)
+        cnt[(1 + i / kJpSeg) * kJpRow + (i % kJpSeg) * kJpCntStride] = 0;
 }
 
-// After a batch: its final list length becomes the current one.
-__global__ void jp_batch_end_kernel(int32_t *slots, int32_t rounds) { slots[kJpCountCell] = slots[rounds]; }
+// After a batch: its final lengths become the current ones; the totals the
+// host reads (decided vertices, listed buckets) are summed here.  One wave.
+__global__ void jp_batch_end_kernel(int32_t *cnt, int32_t rounds, const unsigned long long *progress,
+                                    unsigned long long *totals)
+{
+    const int g = threadIdx.x;
+    unsigned long long listed = 0, decided = 0;
+    if (g < kJpSeg) {
+        const int32_t n = cnt[(int64_t)rounds * kJpRow + g * kJpCntStride];
+        cnt[(int64_t)kJpCountCell * kJpRow + g * kJpCntStride] = n;
+        listed = (unsigned long long)n;
+        decided = progress[g * kJpProgStride];
+    }
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        listed += __shfl_down(listed, d, kWave);
+        decided += __shfl_down(decided, d, kWave);
+    }
+    if (g == 0) {
+        totals[0] = decided;
+        totals[1] = listed;
+    }
+}
 
 // Worklist of every bucket (the first round, and the host's recovery round).
-__global__ void wl_all_kernel(int64_t P, int32_t *wl, uint32_t *dirty, unsigned long long *wake_at,
-                              int32_t *wl_slots)
+__global__ void wl_all_kernel(int64_t P, int64_t cap, int32_t *wl, uint32_t *dirty, unsigned long long *wake_at,
+                              int32_t *cnt)
 {
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < P; c += (int64_t)gridDim.x * blockDim.x) {
-        wl[c] = (int32_t)c;
+        wl[(c % kJpSeg) * cap + c / kJpSeg] = (int32_t)c;
         dirty[c] = 1u;
         wake_at[c] = 0ull;  // whole bucket
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) wl_slots[kJpCountCell] = (int32_t)P;
+    if (blockIdx.x == 0 && threadIdx.x < kJpSeg) {
+        const int64_t g = threadIdx.x;
+        cnt[(int64_t)kJpCountCell * kJpRow + g * kJpCntStride] = (int32_t)((P - g + kJpSeg - 1) / kJpSeg);
+    }
 }
 
 // Relation bits of a bucket from a given symmetric CSR: for every edge
@@ -656,14 +699,14 @@ unsigned grid_for(int64_t work, int threads, int64_t cap = 65535 * 16)
 void launch_jp_all(const JpArgs &a, hipStream_t st)
 {
     if (a.P <= 0) return;
-    wl_all_kernel<<<grid_for(a.P, 256), 256, 0, st>>>(a.P, a.wl[0], a.dirty, a.wake_at, a.wl_slots);
+    wl_all_kernel<<<grid_for(a.P, 256), 256, 0, st>>>(a.P, a.wl_cap, a.wl[0], a.dirty, a.wake_at, a.wl_cnt);
     PCHECK_LAUNCH();
 }
 
 void launch_jp_batch_begin(const JpArgs &a, int32_t rounds, hipStream_t st)
 {
     if (rounds < 1 || rounds > kJpMaxBatch) throw Error(PICASSO_EINTERNAL, "colouring batch out of range");
-    jp_batch_begin_kernel<<<1, 256, 0, st>>>(a.wl_slots, rounds);
+    jp_batch_begin_kernel<<<1, 256, 0, st>>>(a.wl_cnt, rounds);
     PCHECK_LAUNCH();
 }
 
@@ -679,7 +722,7 @@ void launch_jp_round(const JpArgs &a, int cur, int32_t k, hipStream_t st)
 
 void launch_jp_batch_end(const JpArgs &a, int32_t rounds, hipStream_t st)
 {
-    jp_batch_end_kernel<<<1, 1, 0, st>>>(a.wl_slots, rounds);
+    jp_batch_end_kernel<<<1, kWave, 0, st>>>(a.wl_cnt, rounds, a.progress, a.totals);
     PCHECK_LAUNCH();
 }
 

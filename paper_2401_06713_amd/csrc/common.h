@@ -230,6 +230,8 @@ struct JpArgs {
     const uint32_t *lists;  // rows sorted, row v at loff[v]
     const int64_t *loff;    // [m+1]; T_v = loff[v+1] - loff[v]
     const int64_t *pos_of;  // bucket position of (vertex, slot)
+    const InstRec *inst;    // instance table: a bucket's members share its list size and list offsets
+    const int32_t *binst;   // [P] instance of each bucket
     int64_t nw_max;         // words per row of the largest bucket
     int32_t fw;             // words per slot mask = ceil(T_max/64)
     int32_t *col;           // batch-wide colour, -1 failed, -2 undecided
@@ -238,23 +240,35 @@ struct JpArgs {
     int32_t packed;         // lists of at most 32 slots: blk[v] holds both masks (blocked in
                             // bits 0-31, free in bits 32-63), fre and nblk are unused
     uint8_t *st;            // per bucket entry: unknown / taken / not taken
+    uint8_t *rdy;           // per bucket entry: 1 once the vertex's lower slots are all known blocked
     uint32_t *dirty;        // per bucket: waiting on a worklist
     unsigned long long *wake_at;  // per bucket: first bucket position changed since it was last taken
-    int32_t *wl[2];         // worklists of buckets (P entries each)
-    int32_t *wl_slots;      // [kJpSlots]: list length entering round k of a batch
-                            // at k, the current length at kJpCountCell
-    unsigned long long *progress;  // decided vertices
+    int32_t *wl[2];         // worklists of buckets: kJpSeg segments of wl_cap entries each
+                            // (bucket c in segment c % kJpSeg)
+    int64_t wl_cap;         // entries per segment, ceil(P / kJpSeg)
+    int32_t *wl_cnt;        // [kJpSlots][kJpRow]: segment lengths entering round k of a batch
+                            // in row k, the current lengths in row kJpCountCell
+    unsigned long long *progress;  // [kJpSeg * kJpProgStride]: decided vertices, in kJpSeg counters
+    unsigned long long *totals;    // [2]: decided vertices and listed buckets after the last batch
     int64_t m;              // vertices to decide
 };
 constexpr int kJpMaxBatch = 1024;               // rounds per batch, at most
-constexpr int kJpCountCell = kJpMaxBatch + 1;   // current list length between batches
+constexpr int kJpCountCell = kJpMaxBatch + 1;   // current list lengths between batches
 constexpr int kJpSlots = kJpMaxBatch + 2;
-// Every bucket onto worklist 0 (marked waiting): the current length is P.
+// Appends and progress counts are spread over kJpSeg counters, each on a
+// cache line of its own: a single counter takes one atomic per woken
+// bucket and per sweep, which serialise at one address.
+constexpr int kJpSeg = 64;
+constexpr int kJpCntStride = 32;                 // int32 between segment counters (128 bytes)
+constexpr int kJpRow = kJpSeg * kJpCntStride;    // int32 per round's row of counters
+constexpr int kJpProgStride = 16;                // uint64 between progress counters (128 bytes)
+// Every bucket onto worklist 0 (marked waiting): the current lengths sum to P.
 void launch_jp_all(const JpArgs &a, hipStream_t st);
 // A batch of `rounds` worklist rounds starting from list `cur`: round k
-// reads the list of length wl_slots[k] and appends to the other list,
-// counting in wl_slots[k + 1] (zeroed when the batch begins, so no round
-// resets a counter); the batch's final length is kept at kJpCountCell.
+// reads the segments of lengths in row k and appends to the other list,
+// counting in row k + 1 (zeroed when the batch begins, so no round resets a
+// counter); the batch's final lengths are kept in row kJpCountCell, and the
+// batch's end sums the decided vertices and the listed buckets into totals.
 void launch_jp_batch_begin(const JpArgs &a, int32_t rounds, hipStream_t st);
 void launch_jp_round(const JpArgs &a, int cur, int32_t k, hipStream_t st);
 void launch_jp_batch_end(const JpArgs &a, int32_t rounds, hipStream_t st);

@@ -1,12 +1,13 @@
 // Stable least-significant-digit radix sort of (key, value) pairs, and the
 // colour-bucket build that uses it.
 //
-// Each pass sorts by one 8-bit digit: a digit histogram per tile of
+// Each pass sorts by one 8- or 9-bit digit: a digit histogram per tile of
 // kTile elements, an exclusive scan over (digit, tile) -- digit-major, so a
 // tile's elements of digit d land after every earlier tile's -- and a
 // stable scatter.  Within a tile, elements are ranked in input order: per
-// round of 256 elements, each wave finds the lanes with its digit by eight
-// ballots, and per-wave digit counts in LDS order the four waves.
+// round of 256 elements, each wave finds the lanes with its digit by one
+// ballot per digit bit, and per-wave digit counts in LDS order the four
+// waves.
 //
 // Bucket build (Alg. 1 buckets of list entries, members in the colouring
 // order): the vertices are sorted by (priority, index) (eight passes over the
@@ -25,32 +26,33 @@ namespace {
 constexpr int kRThreads = 256;
 constexpr int kRItems = 8;
 constexpr int64_t kRTile = (int64_t)kRThreads * kRItems;
-constexpr int kBins = 256;
+constexpr int kMaxDigitBits = 9;
 
-template <typename K>
+template <typename K, int DB>
 __device__ __forceinline__ uint32_t digit_of(K key, int shift)
 {
-    return (uint32_t)(key >> shift) & (kBins - 1);
+    return (uint32_t)(key >> shift) & ((1u << DB) - 1u);
 }
 
-template <typename K>
+template <typename K, int DB>
 __global__ void __launch_bounds__(kRThreads) radix_hist_kernel(const K *__restrict__ keys, int64_t n, int shift,
                                                                int64_t ntiles, uint32_t *__restrict__ counts)
 {
+    constexpr int kBins = 1 << DB;
     __shared__ uint32_t h[kBins];
-    h[threadIdx.x] = 0u;
+    for (int d = threadIdx.x; d < kBins; d += kRThreads) h[d] = 0u;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kRTile;
 #pragma unroll
     for (int i = 0; i < kRItems; ++i) {
         const int64_t g = base + (int64_t)i * kRThreads + threadIdx.x;
-        if (g < n) atomicAdd(&h[digit_of(keys[g], shift)], 1u);
+        if (g < n) atomicAdd(&h[digit_of<K, DB>(keys[g], shift)], 1u);
     }
     __syncthreads();
-    counts[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+    for (int d = threadIdx.x; d < kBins; d += kRThreads) counts[(int64_t)d * ntiles + blockIdx.x] = h[d];
 }
 
-template <typename K>
+template <typename K, int DB>
 __global__ void __launch_bounds__(kRThreads) radix_scatter_kernel(const K *__restrict__ keys,
                                                                   const uint32_t *__restrict__ vals, int64_t n,
                                                                   int shift, int64_t ntiles,
@@ -58,16 +60,20 @@ __global__ void __launch_bounds__(kRThreads) radix_scatter_kernel(const K *__res
                                                                   K *__restrict__ out_keys,
                                                                   uint32_t *__restrict__ out_vals)
 {
+    constexpr int kBins = 1 << DB;
     __shared__ int64_t off[kBins];
     __shared__ uint32_t running[kBins];
     __shared__ uint32_t wcnt[kRThreads / 64][kBins];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    off[t] = offsets[(int64_t)t * ntiles + blockIdx.x];
-    running[t] = 0u;
+    for (int d = t; d < kBins; d += kRThreads) {
+        off[d] = offsets[(int64_t)d * ntiles + blockIdx.x];
+        running[d] = 0u;
+    }
     const uint64_t lanes_below = (1ull << lane) - 1ull;
     const int64_t base = (int64_t)blockIdx.x * kRTile;
     for (int i = 0; i < kRItems; ++i) {
-        for (int w = 0; w < kRThreads / 64; ++w) wcnt[w][t] = 0u;
+        for (int w = 0; w < kRThreads / 64; ++w)
+            for (int d = t; d < kBins; d += kRThreads) wcnt[w][d] = 0u;
         __syncthreads();
         const int64_t g = base + (int64_t)i * kRThreads + t;
         const bool valid = g < n;
@@ -76,11 +82,11 @@ __global__ void __launch_bounds__(kRThreads) radix_scatter_kernel(const K *__res
         if (valid) {
             key = keys[g];
             val = vals[g];
-            d = digit_of(key, shift);
+            d = digit_of<K, DB>(key, shift);
         }
         uint64_t peers = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
+        for (int b = 0; b < DB; ++b) {
             const uint64_t bal = __ballot((d >> b) & 1u);
             peers &= ((d >> b) & 1u) ? bal : ~bal;
         }
@@ -98,9 +104,11 @@ __global__ void __launch_bounds__(kRThreads) radix_scatter_kernel(const K *__res
             }
         }
         __syncthreads();
-        uint32_t add = 0u;
-        for (int w = 0; w < kRThreads / 64; ++w) add += wcnt[w][t];
-        running[t] += add;
+        for (int dd = t; dd < kBins; dd += kRThreads) {
+            uint32_t add = 0u;
+            for (int w = 0; w < kRThreads / 64; ++w) add += wcnt[w][dd];
+            running[dd] += add;
+        }
         __syncthreads();
     }
 }
@@ -124,18 +132,41 @@ __global__ void ranked_sizes_kernel(const uint32_t *__restrict__ perm, int64_t m
 }
 
 // The list entries of the vertices in priority order: (colour, entry index).
-__global__ void emit_ranked_kernel(const uint32_t *__restrict__ perm, int64_t m, const int64_t *__restrict__ loff,
-                                   const int64_t *__restrict__ at, const uint32_t *__restrict__ lists,
-                                   uint32_t *__restrict__ keys, uint32_t *__restrict__ vals, int64_t E)
+// A workgroup takes kEmitRanks consecutive ranks and strides over their
+// output range, so that consecutive threads write consecutive entries (and
+// read consecutive entries of one list); each thread finds its rank by a
+// binary search of the ranks' output offsets, kept in LDS.
+constexpr int kEmitRanks = 256;
+
+__global__ void __launch_bounds__(256) emit_ranked_kernel(const uint32_t *__restrict__ perm, int64_t m,
+                                                          const int64_t *__restrict__ loff,
+                                                          const int64_t *__restrict__ at,
+                                                          const uint32_t *__restrict__ lists,
+                                                          uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                                          int64_t E)
 {
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t v = perm[r];
-        const int64_t l0 = loff[v], T = loff[v + 1] - l0, o = at[r];
-        for (int64_t k = 0; k < T; ++k)
-            if (o + k < E) {
-                keys[o + k] = lists[l0 + k];
-                vals[o + k] = (uint32_t)(l0 + k);
+    __shared__ int64_t o[kEmitRanks + 1];  // output offsets of the ranks, and the end
+    __shared__ int64_t l[kEmitRanks];      // their first list entries
+    for (int64_t r0 = (int64_t)blockIdx.x * kEmitRanks; r0 < m; r0 += (int64_t)gridDim.x * kEmitRanks) {
+        const int nr = (int)min<int64_t>(kEmitRanks, m - r0);
+        __syncthreads();
+        for (int i = threadIdx.x; i <= nr; i += blockDim.x) {
+            o[i] = at[r0 + i];  // at holds m + 1 offsets
+            if (i < nr) l[i] = loff[perm[r0 + i]];
+        }
+        __syncthreads();
+        const int64_t end = min<int64_t>(o[nr], E);
+        for (int64_t x = o[0] + threadIdx.x; x < end; x += blockDim.x) {
+            int lo = 0, hi = nr;  // o[lo] <= x < o[hi]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (o[mid] <= x) lo = mid;
+                else hi = mid;
             }
+            const int64_t e = l[lo] + (x - o[lo]);
+            keys[x] = lists[e];
+            vals[x] = (uint32_t)e;
+        }
     }
 }
 
@@ -194,10 +225,25 @@ unsigned grid_for(int64_t work, int threads, int64_t cap = 65535 * 16)
 size_t radix_tmp_bytes(int64_t n)
 {
     const int64_t ntiles = std::max<int64_t>((n + kRTile - 1) / kRTile, 1);
-    const int64_t nc = ntiles * kBins;
+    const int64_t nc = ntiles << kMaxDigitBits;
     return (size_t)nc * sizeof(uint32_t) + (size_t)(nc + 1) * sizeof(int64_t) + scan_tmp_bytes(nc + 1) + 512;
 }
 
+template <typename K, int DB>
+void radix_pass(const K *src_k, const uint32_t *src_v, K *dst_k, uint32_t *dst_v, int64_t n, int shift, int64_t ntiles,
+                uint32_t *counts, int64_t *offsets, void *scan_tmp, hipStream_t st)
+{
+    const int64_t nc = ntiles << DB;
+    radix_hist_kernel<K, DB><<<(unsigned)ntiles, kRThreads, 0, st>>>(src_k, n, shift, ntiles, counts);
+    PCHECK_LAUNCH();
+    exclusive_scan_u32_to_i64(counts, offsets, nc, false, scan_tmp, st);
+    radix_scatter_kernel<K, DB><<<(unsigned)ntiles, kRThreads, 0, st>>>(src_k, src_v, n, shift, ntiles, offsets,
+                                                                        dst_k, dst_v);
+    PCHECK_LAUNCH();
+}
+
+// Passes of 9-bit digits where they save a pass over 8-bit ones (18 bits:
+// two passes instead of three), else of 8-bit digits.
 template <typename K>
 int radix_sort_pairs(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals_alt, int64_t n, int bit_lo, int bit_hi,
                      void *tmp, hipStream_t st)
@@ -205,7 +251,10 @@ int radix_sort_pairs(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals_alt, i
     if (n <= 0) return 0;
     const int64_t ntiles = (n + kRTile - 1) / kRTile;
     if (ntiles > 0x7FFFFFFF) throw Error(PICASSO_EINTERNAL, "radix sort: too many elements");
-    const int64_t nc = ntiles * kBins;
+    const int bits = bit_hi - bit_lo;
+    const int p8 = (bits + 7) / 8, p9 = (bits + 8) / 9;
+    const int db = p9 < p8 ? 9 : 8;
+    const int64_t nc = ntiles << kMaxDigitBits;
     uint32_t *counts = static_cast<uint32_t *>(tmp);
     int64_t *offsets = reinterpret_cast<int64_t *>(
         (reinterpret_cast<uintptr_t>(counts + nc) + 255) & ~(uintptr_t)255);
@@ -213,13 +262,11 @@ int radix_sort_pairs(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals_alt, i
     K *src_k = keys, *dst_k = keys_alt;
     uint32_t *src_v = vals, *dst_v = vals_alt;
     int flips = 0;
-    for (int shift = bit_lo; shift < bit_hi; shift += 8) {
-        radix_hist_kernel<K><<<(unsigned)ntiles, kRThreads, 0, st>>>(src_k, n, shift, ntiles, counts);
-        PCHECK_LAUNCH();
-        exclusive_scan_u32_to_i64(counts, offsets, nc, false, scan_tmp, st);
-        radix_scatter_kernel<K><<<(unsigned)ntiles, kRThreads, 0, st>>>(src_k, src_v, n, shift, ntiles, offsets,
-                                                                        dst_k, dst_v);
-        PCHECK_LAUNCH();
+    for (int shift = bit_lo; shift < bit_hi; shift += db) {
+        if (db == 9)
+            radix_pass<K, 9>(src_k, src_v, dst_k, dst_v, n, shift, ntiles, counts, offsets, scan_tmp, st);
+        else
+            radix_pass<K, 8>(src_k, src_v, dst_k, dst_v, n, shift, ntiles, counts, offsets, scan_tmp, st);
         std::swap(src_k, dst_k);
         std::swap(src_v, dst_v);
         flips ^= 1;
@@ -250,7 +297,8 @@ void launch_emit_ranked(const uint32_t *perm, int64_t m, const int64_t *loff, co
                         const uint32_t *lists, uint32_t *keys, uint32_t *vals, int64_t E, hipStream_t st)
 {
     if (m <= 0) return;
-    emit_ranked_kernel<<<grid_for(m, 256), 256, 0, st>>>(perm, m, loff, at, lists, keys, vals, E);
+    emit_ranked_kernel<<<grid_for((m + kEmitRanks - 1) / kEmitRanks, 1, 65535), 256, 0, st>>>(perm, m, loff, at, lists,
+                                                                                              keys, vals, E);
     PCHECK_LAUNCH();
 }
 
