@@ -26,28 +26,28 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM bytes of the pair kernel's and the CSR fill's iteration-1 launches on
 # the default workload, from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE;
-# summary and commands in profiles/pair_and_fill_c2_n200000_q48_counters.md),
+# summary and commands in profiles/pair_and_fill_c4_n2000000_q128_counters.md),
 # each scaled by what the counter read for a 1 GiB device copy in the same
 # runs.  Valid only for the kernel source they were taken from (its SHA-256).
 PAIR_TRAFFIC = {
-    "workload": "C2 n=200000 q=48 pI=0.7",
+    "workload": "C4 n=2000000 q=128 pI=0.8",
     "path": "valu",
     "source": "paper_2401_06713_amd/csrc/relate.hip",
     "sha256": "a4eb31278c6673bdf4a234cbcec3ec625b313a2efa81133f8732b8622a2ac835",
-    "fetch_kib": 56653.5625,
-    "fetch_scale": 1048576.0 / 524308.5625,
-    "write_kib": 201274.6875,
+    "fetch_kib": 1337844.0,
+    "fetch_scale": 1048576.0 / 524315.3,
+    "write_kib": 2875592.7,
     "write_scale": 1048576.0 / 1048576.0,
 }
 
 FILL_TRAFFIC = {
-    "workload": "C2 n=200000 q=48 pI=0.7",
+    "workload": "C4 n=2000000 q=128 pI=0.8",
     "path": "valu",
     "source": "paper_2401_06713_amd/csrc/pairs.hip",
-    "sha256": "b5a775ea1d384add96289e3e171f7c1fe3b71a0945432081158fd93f797870ca",
-    "fetch_kib": 485762.0625,
-    "fetch_scale": 1048576.0 / 524308.5625,
-    "write_kib": 2065046.21875,
+    "sha256": "2860b52b0c6d72a1f8b698321645c40510b0fb0b76e5f775a4208de17037a710",
+    "fetch_kib": 6121524.7,
+    "fetch_scale": 1048576.0 / 524315.3,
+    "write_kib": 29713660.4,
     "write_scale": 1048576.0 / 1048576.0,
 }
 

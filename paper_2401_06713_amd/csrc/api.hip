@@ -90,8 +90,8 @@ struct picasso_ctx {
     DevBuf x, z, xz;  // bit-planes, and the interleaved copy the member gather reads
     // iteration buffers
     DevBuf ids, next_ids, lists, prio, bcnt, bstart, bmem, bslot, pos_of, bent, tmp_mem, tmp_slot, tiles, words, tile_off,
-        rb_off, R, D, bx, bz, tile_bucket, nslow, slow, slot_cnt, slot_off, rowptr, adj, col, blk, fre, nblk, st, rdy, jp_prog,
-        dirty, wake_at, wl, flags, pos, used, scan_tmp, scalars, out_colors, judge_out, inst, vinst, loff, binst,
+        rb_off, R, D, bx, bz, tile_bucket, nslow, slow, slot_cnt, slot_off, rowptr, adj, col, blk, fre, nblk, st, rdy, jp_prog, dflag,
+        wake_at, wl, flags, pos, used, scan_tmp, scalars, out_colors, judge_out, inst, vinst, loff, binst,
         inst_out, tail_recs, tail_table, tail_outs, tail_iters, tail_ranges, hits, csr_flag, rkey, dyn_hist, dyn_sstar,
         dyn_cut, rx_k64a, rx_k64b, rx_va, rx_vb, rx_tmp, rx_tr, rx_at, rx_cka, rx_ckb, rx_cva, rx_cvb;
     std::vector<InstRec> h_inst;  // table of the active instances (kept until the copy has completed)
@@ -371,6 +371,7 @@ CsrArgs csr_args(picasso_ctx *h, const Batch &b, int64_t P)
     ca.rb_off = static_cast<const int64_t *>(h->rb_off.p);
     ca.R = static_cast<const uint64_t *>(h->R.p);
     ca.D = static_cast<const uint64_t *>(h->D.p);
+    ca.dflag = static_cast<const uint8_t *>(h->dflag.p);
     ca.loff = b.loff;
     ca.bent = static_cast<const int64_t *>(h->bent.p);
     ca.slot_off = static_cast<const int64_t *>(h->slot_off.p);
@@ -440,6 +441,8 @@ int64_t build_conflict_graph(picasso_ctx *h, const Batch &b, int64_t m, int64_t 
     }
     // pairs sharing a smaller colour
     launch_fill_u64(D, bi.words, 0ull, st);
+    uint8_t *dflag = buf<uint8_t>(h, h->dflag, (size_t)std::max<int64_t>(E, 1));
+    launch_fill_u8(dflag, E, 0, st);
     int32_t *nslow = buf<int32_t>(h, h->nslow, 16);
     launch_fill_i32(nslow, 1, 0, st);
     DupArgs da{};
@@ -455,6 +458,7 @@ int64_t build_conflict_graph(picasso_ctx *h, const Batch &b, int64_t m, int64_t 
     da.inst = b.inst;
     da.R = R;
     da.D = D;
+    da.dflag = dflag;
     da.slow = buf<uint32_t>(h, h->slow, (size_t)P);
     da.n_slow = nslow;
     if (T_max > 1) {
@@ -611,7 +615,6 @@ int32_t color_buckets(picasso_ctx *h, const Batch &b, int64_t m, int64_t E, int6
     }
     j.st = buf<uint8_t>(h, h->st, (size_t)std::max<int64_t>(E, 1));
     j.rdy = buf<uint8_t>(h, h->rdy, (size_t)std::max<int64_t>(E, 1));
-    j.dirty = buf<uint32_t>(h, h->dirty, (size_t)P);
     j.wake_at = buf<unsigned long long>(h, h->wake_at, (size_t)P);
     j.wl_cap = (P + kJpSeg - 1) / kJpSeg;
     const int64_t wl_len = kJpSeg * j.wl_cap;
@@ -1305,7 +1308,7 @@ void picasso_destroy(picasso_handle h)
                      &h->bstart,  &h->bmem,     &h->bslot,   &h->pos_of,   &h->bent, &h->tmp_mem, &h->tmp_slot, &h->tiles,
                      &h->words,   &h->tile_off, &h->rb_off,  &h->R,        &h->D,       &h->nslow,    &h->slow,
                      &h->slot_cnt, &h->slot_off, &h->rowptr, &h->adj,      &h->col,     &h->blk,      &h->fre,
-                     &h->nblk,    &h->st,       &h->rdy,     &h->jp_prog, &h->dirty,   &h->wl,       &h->flags,   &h->pos,      &h->used,
+                     &h->nblk,    &h->st,       &h->rdy,     &h->jp_prog, &h->dflag, &h->wl,       &h->flags,   &h->pos,      &h->used,
                      &h->scan_tmp, &h->bx,      &h->bz,      &h->tile_bucket,
                      &h->scalars, &h->out_colors, &h->judge_out, &h->inst,    &h->vinst,    &h->loff,    &h->binst,    &h->inst_out, &h->tail_recs,
                      &h->tail_table, &h->tail_outs, &h->tail_iters, &h->tail_ranges, &h->wake_at,

@@ -54,12 +54,19 @@ __device__ __forceinline__ void append(const JpArgs &a, int64_t c2, int32_t *out
     out[sg * a.wl_cap + at] = (int32_t)c2;
 }
 
+// A bucket's wake_at word is its state on the worklists: kIdle (not listed),
+// a bucket position (listed, to be swept from that position), or kBusy (being
+// swept, nothing new yet).  One atomicMin both records a position and tells
+// the waker whether the bucket was idle, and so is not on any list: then the
+// waker lists it.  A bucket is listed once: by the waker that finds it idle,
+// or by its own visitor when a position arrived while it was busy.
+constexpr unsigned long long kIdle = ~0ull;
+constexpr unsigned long long kBusy = ~0ull - 1ull;
+
 __device__ __forceinline__ void wake(const JpArgs &a, int64_t c2, int64_t pos, int32_t *out, int32_t *out_count)
 {
     __builtin_amdgcn_s_waitcnt(0);  // the state change is complete before its position is published
-    atomicMin(&a.wake_at[c2], (unsigned long long)pos);
-    if (__hip_atomic_exchange(&a.dirty[c2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
-        append(a, c2, out, out_count);
+    if (atomicMin(&a.wake_at[c2], (unsigned long long)pos) == kIdle) append(a, c2, out, out_count);
 }
 
 // The blocked slots of a vertex now run up to its slot at list entry e: that
@@ -79,7 +86,7 @@ __device__ __forceinline__ void ready_and_wake(const JpArgs &a, int64_t e, int32
 // still unknown in its bucket is marked not-taken there and its bucket is
 // woken (members after v in it may have waited on v).  Groups of 4 slots:
 // independent loads, one wait so the marks are complete before any wake,
-// independent exchanges.
+// independent wakes.
 __device__ __forceinline__ void release_later_slots(const JpArgs &a, int64_t l0, int k, int T, int32_t *out,
                                                     int32_t *out_count)
 {
@@ -104,17 +111,12 @@ __device__ __forceinline__ void release_later_slots(const JpArgs &a, int64_t l0,
         for (int j = 0; j < G; ++j)
             if (need[j]) __hip_atomic_store(&a.st[pos[j]], ST_NOT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __builtin_amdgcn_s_waitcnt(0);  // the marks are complete before their positions are published
+        unsigned long long old[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) old[j] = need[j] ? atomicMin(&a.wake_at[cc[j]], (unsigned long long)pos[j]) : 0ull;
 #pragma unroll
         for (int j = 0; j < G; ++j)
-            if (need[j]) atomicMin(&a.wake_at[cc[j]], (unsigned long long)pos[j]);
-        uint32_t old[G];
-#pragma unroll
-        for (int j = 0; j < G; ++j)
-            old[j] = need[j] ? __hip_atomic_exchange(&a.dirty[cc[j]], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                             : 1u;
-#pragma unroll
-        for (int j = 0; j < G; ++j)
-            if (old[j] == 0u) append(a, cc[j], out, out_count);
+            if (old[j] == kIdle) append(a, cc[j], out, out_count);
     }
 }
 
@@ -523,14 +525,11 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(6)))
             else hi = mid;
         }
         const int64_t c = a.wl[cur][lo * a.wl_cap + (i - pre[lo])];
-        if (threadIdx.x == 0) {
-            __hip_atomic_exchange(&a.dirty[c], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            from = __hip_atomic_exchange(&a.wake_at[c], ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        if (threadIdx.x == 0)
+            from = __hip_atomic_exchange(&a.wake_at[c], kBusy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
-        // a bucket woken again while it was swept is swept again at once (its
-        // pending position consumed: the next round's visit finds nothing)
-        for (int sweep = 0; sweep <= kJpResweeps && from != ~0ull; ++sweep) {
+        // a bucket woken again while it was swept is swept again at once
+        for (int sweep = 0; sweep <= kJpResweeps && from < kBusy; ++sweep) {
             const int64_t base = a.bstart[c];
             const int64_t S = a.bstart[c + 1] - base;
             const int nwc = (int)((S + 63) >> 6);
@@ -540,11 +539,21 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(6)))
                 resolve_bucket(a, c, from, tak, unk, mv, mk, out, out_count);
             __syncthreads();
             if (threadIdx.x == 0)
-                from = __hip_atomic_exchange(&a.wake_at[c], ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                from = __hip_atomic_exchange(&a.wake_at[c], kBusy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __syncthreads();
         }
-        if (from != ~0ull && threadIdx.x == 0)  // not swept: keep the position for the next round
-            atomicMin(&a.wake_at[c], from);
+        if (threadIdx.x == 0) {
+            if (from < kBusy) {
+                // taken but not swept (resweep limit): the position goes back
+                // and the bucket onto the next list
+                atomicMin(&a.wake_at[c], from);
+                append(a, c, out, out_count);
+            } else if (atomicCAS(&a.wake_at[c], kBusy, kIdle) != kBusy) {
+                // a position arrived after the last check (its waker found the
+                // bucket busy and left the listing to this visit)
+                append(a, c, out, out_count);
+            }
+        }
         __syncthreads();
     }
 }
@@ -585,13 +594,11 @@ __global__ void jp_batch_end_kernel(int32_t *cnt, int32_t rounds, const unsigned
 }
 
 // Worklist of every bucket (the first round, and the host's recovery round).
-__global__ void wl_all_kernel(int64_t P, int64_t cap, int32_t *wl, uint32_t *dirty, unsigned long long *wake_at,
-                              int32_t *cnt)
+__global__ void wl_all_kernel(int64_t P, int64_t cap, int32_t *wl, unsigned long long *wake_at, int32_t *cnt)
 {
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < P; c += (int64_t)gridDim.x * blockDim.x) {
         wl[(c % kJpSeg) * cap + c / kJpSeg] = (int32_t)c;
-        dirty[c] = 1u;
-        wake_at[c] = 0ull;  // whole bucket
+        wake_at[c] = 0ull;  // listed, whole bucket
     }
     if (blockIdx.x == 0 && threadIdx.x < kJpSeg) {
         const int64_t g = threadIdx.x;
@@ -699,7 +706,7 @@ unsigned grid_for(int64_t work, int threads, int64_t cap = 65535 * 16)
 void launch_jp_all(const JpArgs &a, hipStream_t st)
 {
     if (a.P <= 0) return;
-    wl_all_kernel<<<grid_for(a.P, 256), 256, 0, st>>>(a.P, a.wl_cap, a.wl[0], a.dirty, a.wake_at, a.wl_cnt);
+    wl_all_kernel<<<grid_for(a.P, 256), 256, 0, st>>>(a.P, a.wl_cap, a.wl[0], a.wake_at, a.wl_cnt);
     PCHECK_LAUNCH();
 }
 

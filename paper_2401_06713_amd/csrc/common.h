@@ -191,6 +191,7 @@ struct DupArgs {
     const InstRec *inst;
     const uint64_t *R;      // relation matrices (the exact check visits relation pairs only)
     uint64_t *D;            // pairs sharing a smaller colour (zeroed by the caller)
+    uint8_t *dflag;         // per bucket entry: 1 if its D row has a bit (zeroed by the caller)
     uint32_t *slow;         // buckets left to the exact per-pair check
     int32_t *n_slow;
 };
@@ -204,6 +205,7 @@ struct CsrArgs {
     int64_t P;
     const int64_t *rb_off;
     const uint64_t *R, *D;
+    const uint8_t *dflag;    // per bucket entry: its D row has a bit (rows without one read R alone)
     const int64_t *loff;     // list entry of (v, 0)
     const int64_t *bent;     // list entry of each bucket member
     int32_t *slot_cnt;       // count pass: edge count per list entry (vertex, slot)
@@ -241,8 +243,7 @@ struct JpArgs {
                             // bits 0-31, free in bits 32-63), fre and nblk are unused
     uint8_t *st;            // per bucket entry: unknown / taken / not taken
     uint8_t *rdy;           // per bucket entry: 1 once the vertex's lower slots are all known blocked
-    uint32_t *dirty;        // per bucket: waiting on a worklist
-    unsigned long long *wake_at;  // per bucket: first bucket position changed since it was last taken
+    unsigned long long *wake_at;  // per bucket: idle, busy, or the first position changed since it was last taken
     int32_t *wl[2];         // worklists of buckets: kJpSeg segments of wl_cap entries each
                             // (bucket c in segment c % kJpSeg)
     int64_t wl_cap;         // entries per segment, ceil(P / kJpSeg)

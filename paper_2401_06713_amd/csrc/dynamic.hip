@@ -36,35 +36,50 @@ constexpr uint8_t DST_NONE = 0, DST_REQ = 1, DST_DEAD = 2;
 constexpr int kHistThreads = 256;
 
 // Step 1: failures, and per-instance counts of active vertices by remaining
-// list size.  A block whose vertices all belong to one instance counts in
-// LDS first (a large instance would otherwise put every vertex on a handful
-// of global counters).
+// list size.  A block walks chunks of kHistThreads vertices; while its chunks
+// lie in one instance it counts in LDS and adds the bins to the instance's
+// global counters once (a large instance would otherwise put every block's
+// bins, or every vertex, on a handful of global counters).
+constexpr int kHistBlocks = 1024;
 __global__ void __launch_bounds__(kHistThreads) dyn_hist_kernel(DynArgs a)
 {
     extern __shared__ unsigned long long lh[];  // hist_w bins
-    const int64_t v0 = (int64_t)blockIdx.x * kHistThreads;
-    const int64_t v = v0 + threadIdx.x;
-    const int64_t last = std::min<int64_t>(v0 + kHistThreads, a.m) - 1;
-    const bool uniform = a.b.vinst[v0] == a.b.vinst[last];
-    if (uniform)
-        for (int i = threadIdx.x; i < a.hist_w; i += kHistThreads) lh[i] = 0ull;
+    for (int i = threadIdx.x; i < a.hist_w; i += kHistThreads) lh[i] = 0ull;
+    int32_t cur = -1;  // the instance the LDS bins count for (the same in every thread)
+    auto flush = [&]() {
+        __syncthreads();
+        if (cur >= 0) {
+            unsigned long long *g = a.hist + (int64_t)cur * a.hist_w;
+            for (int i = threadIdx.x; i < a.hist_w; i += kHistThreads)
+                if (lh[i]) {
+                    atomicAdd(&g[i], lh[i]);
+                    lh[i] = 0ull;
+                }
+        }
+        __syncthreads();
+    };
     __syncthreads();
-    if (v < a.m && a.col[v] == COL_UNDECIDED) {
-        const int32_t s = a.size[v];
-        if (s == 0) {
-            a.col[v] = COL_FAILED;
-        } else if (uniform) {
-            atomicAdd(&lh[s], 1ull);
-        } else {
-            atomicAdd(&a.hist[(int64_t)a.b.vinst[v] * a.hist_w + s], 1ull);
+    for (int64_t v0 = (int64_t)blockIdx.x * kHistThreads; v0 < a.m; v0 += (int64_t)gridDim.x * kHistThreads) {
+        const int64_t v = v0 + threadIdx.x;
+        const int64_t last = std::min<int64_t>(v0 + kHistThreads, a.m) - 1;
+        const int32_t i0 = a.b.vinst[v0];
+        const bool uniform = i0 == a.b.vinst[last];
+        if (uniform && i0 != cur) {
+            flush();
+            cur = i0;
+        }
+        if (v < a.m && a.col[v] == COL_UNDECIDED) {
+            const int32_t s = a.size[v];
+            if (s == 0) {
+                a.col[v] = COL_FAILED;
+            } else if (uniform) {
+                atomicAdd(&lh[s], 1ull);
+            } else {
+                atomicAdd(&a.hist[(int64_t)a.b.vinst[v] * a.hist_w + s], 1ull);
+            }
         }
     }
-    __syncthreads();
-    if (uniform) {
-        unsigned long long *g = a.hist + (int64_t)a.b.vinst[v0] * a.hist_w;
-        for (int i = threadIdx.x; i < a.hist_w; i += kHistThreads)
-            if (lh[i]) atomicAdd(&g[i], lh[i]);
-    }
+    flush();
 }
 
 // Step 2: each instance's request threshold; the bins are cleared for the
@@ -284,7 +299,8 @@ void launch_dyn_round(const DynArgs &a, int32_t round, hipStream_t st)
     if (a.m <= 0) return;
     const int64_t hb = (a.m + kHistThreads - 1) / kHistThreads;
     if (hb > 0x7FFFFFFF) throw Error(PICASSO_EINTERNAL, "dynamic colouring: too many vertices");
-    dyn_hist_kernel<<<(unsigned)hb, kHistThreads, (size_t)a.hist_w * sizeof(unsigned long long), st>>>(a);
+    dyn_hist_kernel<<<(unsigned)std::min<int64_t>(hb, kHistBlocks), kHistThreads,
+                      (size_t)a.hist_w * sizeof(unsigned long long), st>>>(a);
     PCHECK_LAUNCH();
     dyn_threshold_kernel<<<1, kThrThreads, 0, st>>>(a);
     PCHECK_LAUNCH();

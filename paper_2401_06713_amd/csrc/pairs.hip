@@ -10,7 +10,8 @@
 // words:
 //   R: relation bits between members (symmetric; relate.hip);
 //   D: pairs that share a colour smaller than the bucket's (dup_kernel).
-// The bucket's conflict edges are R & ~D.  count_kernel pop-counts each
+// The bucket's conflict edges are R & ~D (D is read only for the members
+// whose dflag byte says their row has a bit).  count_kernel pop-counts each
 // row into the member's (vertex, slot) segment length; after a scan,
 // fill_kernel expands each row into its CSR segment.  The colouring reads
 // the lower triangle of R (earlier members) directly.
@@ -109,6 +110,8 @@ __global__ void __launch_bounds__(kDupThreads) dup_kernel(DupArgs a)
         auto set_pair = [&](uint32_t pe, uint32_t pf) {
             atomicOr((unsigned long long *)&Dm[(int64_t)pe * nw + (pf >> 6)], 1ull << (pf & 63));
             atomicOr((unsigned long long *)&Dm[(int64_t)pf * nw + (pe >> 6)], 1ull << (pe & 63));
+            a.dflag[base + pe] = 1;
+            a.dflag[base + pf] = 1;
         };
         auto fetch = [&](int e, uint32_t &col, int &mem) {
             int l = 0, h = S;  // koff[l] <= e < koff[h]
@@ -244,6 +247,7 @@ __global__ void __launch_bounds__(kDupThreads) dup_kernel(DupArgs a)
                     if (any) row |= 1ull << b;
                 }
                 Dm[x] = row;
+                if (row) a.dflag[base + p] = 1;
             }
             continue;
         }
@@ -382,7 +386,10 @@ __global__ void __launch_bounds__(256) dup_slow_kernel(DupArgs a)
                         if (Lp[x] < Lq[y]) ++x;
                         else ++y;
                     }
-                    if (shared) atomicOr((unsigned long long *)&Dm[p * nw + (q >> 6)], 1ull << (q & 63));
+                    if (shared) {
+                        atomicOr((unsigned long long *)&Dm[p * nw + (q >> 6)], 1ull << (q & 63));
+                        a.dflag[base + p] = 1;
+                    }
                 }
             }
         }
@@ -401,7 +408,11 @@ __global__ void __launch_bounds__(kWave) count_kernel(CsrArgs a)
         const uint64_t *Dm = a.D + a.rb_off[c];
         for (int64_t p = threadIdx.x; p < S; p += kWave) {
             int cnt = 0;
-            for (int64_t w = 0; w < nw; ++w) cnt += __popcll(Rm[p * nw + w] & ~Dm[p * nw + w]);
+            if (a.dflag[base + p]) {
+                for (int64_t w = 0; w < nw; ++w) cnt += __popcll(Rm[p * nw + w] & ~Dm[p * nw + w]);
+            } else {
+                for (int64_t w = 0; w < nw; ++w) cnt += __popcll(Rm[p * nw + w]);
+            }
             a.slot_cnt[a.bent[base + p]] = cnt;
         }
     }
@@ -442,7 +453,11 @@ __global__ void __launch_bounds__(kWave * kFillWaves) fill_kernel(CsrArgs a, int
                 mv[p] = v;
                 seg[p] = a.slot_off[a.bent[base + p]];
             }
-            for (int64_t w = threadIdx.x; w < S * nw; w += blockDim.x) rows[w] = Rm[w] & ~Dm[w];
+            // D is read only for the rows that have a bit in it
+            for (int64_t w = threadIdx.x; w < S * nw; w += blockDim.x) {
+                const uint64_t r = Rm[w];
+                rows[w] = a.dflag[base + w / nw] ? r & ~Dm[w] : r;
+            }
             __syncthreads();
             for (int64_t p = wave; p < S; p += kFillWaves) {
                 if ((int64_t)mv[p] < a.v_lo || (int64_t)mv[p] >= a.v_hi) continue;  // another chunk's row
@@ -460,8 +475,9 @@ __global__ void __launch_bounds__(kWave * kFillWaves) fill_kernel(CsrArgs a, int
                 const int64_t v = a.bmem[base + p];
                 if (v < a.v_lo || v >= a.v_hi) continue;  // another chunk's row
                 int64_t at = a.slot_off[a.bent[base + p]] - a.adj_base;
+                const bool dd = a.dflag[base + p];
                 for (int64_t w = 0; w < nw; ++w) {
-                    const uint64_t bits = Rm[p * nw + w] & ~Dm[p * nw + w];
+                    const uint64_t bits = dd ? Rm[p * nw + w] & ~Dm[p * nw + w] : Rm[p * nw + w];
                     const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bits >> 32),
                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)bits, 0u));
                     if ((bits >> lane) & 1ull) a.adj[at + rank] = (int32_t)a.bmem[base + w * 64 + lane];

@@ -7,7 +7,8 @@
 // stable scatter.  Within a tile, elements are ranked in input order: per
 // round of 256 elements, each wave finds the lanes with its digit by one
 // ballot per digit bit, and per-wave digit counts in LDS order the four
-// waves.
+// waves.  The ranked tile is staged in LDS in digit order and written out
+// from there, in runs of one digit.
 //
 // Bucket build (Alg. 1 buckets of list entries, members in the colouring
 // order): the vertices are sorted by (priority, index) (eight passes over the
@@ -52,25 +53,56 @@ __global__ void __launch_bounds__(kRThreads) radix_hist_kernel(const K *__restri
     for (int d = threadIdx.x; d < kBins; d += kRThreads) counts[(int64_t)d * ntiles + blockIdx.x] = h[d];
 }
 
+// Scatter of one tile: each element's rank among the tile's elements of its
+// digit (stable, in input order) places it in LDS in digit order; the tile is
+// then written out from LDS, so consecutive threads write consecutive
+// positions of one digit's run instead of one scattered element each.
 template <typename K, int DB>
 __global__ void __launch_bounds__(kRThreads) radix_scatter_kernel(const K *__restrict__ keys,
                                                                   const uint32_t *__restrict__ vals, int64_t n,
                                                                   int shift, int64_t ntiles,
+                                                                  const uint32_t *__restrict__ counts,
                                                                   const int64_t *__restrict__ offsets,
                                                                   K *__restrict__ out_keys,
                                                                   uint32_t *__restrict__ out_vals)
 {
     constexpr int kBins = 1 << DB;
-    __shared__ int64_t off[kBins];
+    constexpr int kPer = kBins / kRThreads;  // bins per thread in the scan (1 or 2)
+    __shared__ int64_t off[kBins];          // global start of each digit's run of this tile
+    __shared__ uint32_t lstart[kBins];      // start of each digit in the tile (exclusive scan of its counts)
     __shared__ uint32_t running[kBins];
     __shared__ uint32_t wcnt[kRThreads / 64][kBins];
+    __shared__ uint32_t wtot[kRThreads / 64];
+    __shared__ K skey[kRTile];
+    __shared__ uint32_t sval[kRTile];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    for (int d = t; d < kBins; d += kRThreads) {
-        off[d] = offsets[(int64_t)d * ntiles + blockIdx.x];
+    const int64_t tile = blockIdx.x;
+    // the tile's digit counts, scanned: kPer bins per thread, then the waves
+    uint32_t cnt[kPer], sum = 0u;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int d = t * kPer + j;
+        off[d] = offsets[(int64_t)d * ntiles + tile];
         running[d] = 0u;
+        cnt[j] = counts[(int64_t)d * ntiles + tile];
+        sum += cnt[j];
+    }
+    uint32_t inc = sum;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += o;
+    }
+    if (lane == 63) wtot[wave] = inc;
+    __syncthreads();
+    uint32_t before = inc - sum;
+    for (int w = 0; w < wave; ++w) before += wtot[w];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        lstart[t * kPer + j] = before;
+        before += cnt[j];
     }
     const uint64_t lanes_below = (1ull << lane) - 1ull;
-    const int64_t base = (int64_t)blockIdx.x * kRTile;
+    const int64_t base = tile * kRTile;
     for (int i = 0; i < kRItems; ++i) {
         for (int w = 0; w < kRThreads / 64; ++w)
             for (int d = t; d < kBins; d += kRThreads) wcnt[w][d] = 0u;
@@ -95,12 +127,12 @@ __global__ void __launch_bounds__(kRThreads) radix_scatter_kernel(const K *__res
         if (leader) wcnt[wave][d] = (uint32_t)__popcll(peers);
         __syncthreads();
         if (valid) {
-            uint32_t before = running[d];
-            for (int w = 0; w < wave; ++w) before += wcnt[w][d];
-            const int64_t pos = off[d] + before + rank;
-            if (pos >= 0 && pos < n) {
-                out_keys[pos] = key;
-                out_vals[pos] = val;
+            uint32_t r = running[d];
+            for (int w = 0; w < wave; ++w) r += wcnt[w][d];
+            const uint32_t li = lstart[d] + r + rank;
+            if (li < (uint32_t)kRTile) {
+                skey[li] = key;
+                sval[li] = val;
             }
         }
         __syncthreads();
@@ -110,6 +142,17 @@ __global__ void __launch_bounds__(kRThreads) radix_scatter_kernel(const K *__res
             running[dd] += add;
         }
         __syncthreads();
+    }
+    // out of LDS in digit order
+    const int64_t m = n - base < kRTile ? n - base : kRTile;
+    for (int j = t; j < m; j += kRThreads) {
+        const K key = skey[j];
+        const uint32_t d = digit_of<K, DB>(key, shift);
+        const int64_t pos = off[d] + (j - (int64_t)lstart[d]);
+        if (pos >= 0 && pos < n) {
+            out_keys[pos] = key;
+            out_vals[pos] = sval[j];
+        }
     }
 }
 
@@ -237,8 +280,8 @@ void radix_pass(const K *src_k, const uint32_t *src_v, K *dst_k, uint32_t *dst_v
     radix_hist_kernel<K, DB><<<(unsigned)ntiles, kRThreads, 0, st>>>(src_k, n, shift, ntiles, counts);
     PCHECK_LAUNCH();
     exclusive_scan_u32_to_i64(counts, offsets, nc, false, scan_tmp, st);
-    radix_scatter_kernel<K, DB><<<(unsigned)ntiles, kRThreads, 0, st>>>(src_k, src_v, n, shift, ntiles, offsets,
-                                                                        dst_k, dst_v);
+    radix_scatter_kernel<K, DB><<<(unsigned)ntiles, kRThreads, 0, st>>>(src_k, src_v, n, shift, ntiles, counts,
+                                                                        offsets, dst_k, dst_v);
     PCHECK_LAUNCH();
 }
 
