@@ -52,6 +52,11 @@ constexpr int kDupScan = 512;                    // lists up to this long are pa
 constexpr int kDupSpan = 512;                    // colour ranges up to this wide use member bitsets
 constexpr int kDupBatch = 8;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
+// pair_scan reuses the two bitmaps: `seen` holds up to kDupScan listed
+// entries, `again` 256 counts and 257 offsets
+static_assert(kDupScan * sizeof(uint64_t) <= kDupWords * sizeof(uint32_t), "pair_scan's entries must fit `seen`");
+static_assert(256 + 257 <= kDupWords, "pair_scan's counts and offsets must fit `again`");
+static_assert(kDupScan <= kDupList && (kDupList & (kDupList - 1)) == 0, "list sizes");
 
 __device__ __forceinline__ uint32_t dup_hash(uint32_t colour)
 {
