@@ -70,6 +70,8 @@ struct picasso_ctx {
     std::vector<int32_t> inst_q;
     int device = 0;
     hipStream_t own_stream = nullptr;
+    hipStream_t tail_stream = nullptr;  // tail kernels, beside the main path (created on first use)
+    hipEvent_t tail_ready = nullptr, tail_done = nullptr;
     hipStream_t stream = nullptr;
     int64_t mem_budget = 0;
     int32_t pair_path = PICASSO_PATH_AUTO;
@@ -92,7 +94,7 @@ struct picasso_ctx {
     DevBuf ids, next_ids, lists, prio, bcnt, bstart, bmem, bslot, pos_of, bent, tmp_mem, tmp_slot, tiles, words, tile_off,
         rb_off, R, D, bx, bz, tile_bucket, nslow, slow, slot_cnt, slot_off, rowptr, adj, col, blk, fre, nblk, st, rdy, jp_prog, dflag,
         wake_at, wl, flags, pos, used, scan_tmp, scalars, out_colors, judge_out, inst, vinst, loff, binst,
-        inst_out, tail_recs, tail_table, tail_outs, tail_iters, tail_ranges, hits, csr_flag, rkey, dyn_hist, dyn_sstar,
+        inst_out, tail_recs, tail_table, tail_outs, tail_iters, tail_ranges, tail_ids, hits, csr_flag, rkey, dyn_hist, dyn_sstar,
         dyn_cut, rx_k64a, rx_k64b, rx_va, rx_vb, rx_tmp, rx_tr, rx_at, rx_cka, rx_ckb, rx_cva, rx_cvb;
     std::vector<InstRec> h_inst;  // table of the active instances (kept until the copy has completed)
     picasso_stats stats;
@@ -831,26 +833,63 @@ bool tail_table(int64_t m, double frac, double alpha, int32_t fixed_T, std::vect
     return true;
 }
 
-// After an iteration: hands the instances with 0 < m <= kTailMax (and every
+// Tail launches of one colouring call.  Each launch finishes the instances
+// that entered the tail in one iteration; it runs on the handle's tail stream
+// beside the main path, from its own copy of the instances' vertex ids, and
+// writes into its own slices of buffers sized for every instance (nothing is
+// reused within the call).  Its records are read back once the call ends.
+struct TailPlan {
+    TailRec *recs = nullptr;
+    int32_t *table = nullptr;
+    TailOut *outs = nullptr;
+    TailIter *iters = nullptr;
+    int32_t *ids = nullptr;
+    int64_t n_recs = 0, n_table = 0, n_ids = 0;
+    struct Launch {
+        uint32_t ell;
+        int64_t rec0;
+        std::vector<int32_t> tinst;
+    };
+    std::vector<Launch> launches;
+    std::vector<std::vector<TailRec>> h_recs;     // host copies kept until the call ends
+    std::vector<std::vector<int32_t>> h_tables;
+    std::vector<std::vector<int64_t>> h_ranges;
+};
+
+void tail_plan_init(picasso_ctx *h, TailPlan &tp)
+{
+    const size_t nb = (size_t)std::max<int32_t>(h->nb, 1);
+    tp.recs = buf<TailRec>(h, h->tail_recs, nb);
+    tp.table = buf<int32_t>(h, h->tail_table, nb * 2 * ((size_t)kTailMax + 1));
+    tp.outs = buf<TailOut>(h, h->tail_outs, nb);
+    tp.iters = buf<TailIter>(h, h->tail_iters, nb * kTailMax);
+    tp.ids = buf<int32_t>(h, h->tail_ids, nb * kTailMax);
+    if (!h->tail_stream) {
+        PCHECK_HIP(hipStreamCreateWithFlags(&h->tail_stream, hipStreamNonBlocking));
+        PCHECK_HIP(hipEventCreateWithFlags(&h->tail_ready, hipEventDisableTiming));
+        PCHECK_HIP(hipEventCreateWithFlags(&h->tail_done, hipEventDisableTiming));
+    }
+}
+
+// Hands the active instances with at most kTailMax vertices left (and every
 // iteration within the tail kernel's limits) to the tail kernel, which
 // finishes them; the other instances' vertices (contiguous runs of
 // h->next_ids) are gathered to the front of h->ids when some left.  Returns
-// the vertices left for the next iteration.  mi/off/n_colors and the
-// statistics are updated for the finished instances.
+// the vertices left for the next iteration; the finished instances' mi
+// become 0 (their colours and statistics are collected by tail_plan_finish).
 int64_t run_tails(picasso_ctx *h, const RunArgs &ra, const std::vector<int32_t> &act, std::vector<int64_t> &mi,
-                  std::vector<int64_t> &off, uint32_t ell, int64_t *n_colors, int32_t *d_out, picasso_stats &S,
-                  std::vector<int64_t> &iter_edges, bool &gathered)
+                  const std::vector<int64_t> &off, uint32_t ell, int32_t *d_out, TailPlan &tp, bool &gathered)
 {
     hipStream_t st = h->stream;
     std::vector<TailRec> trs;
     std::vector<int32_t> tinst, table;
-    std::vector<int64_t> ranges;
-    int64_t src = 0, kept = 0;
+    std::vector<int64_t> ranges, tranges;
+    int64_t src = 0, kept = 0, tcopy = 0;
     for (const int32_t i : act) {
         const int64_t mn = mi[i];
         if (mn > 0 && mn <= kTailMax && tail_table(mn, ra.fracs[i], ra.alphas[i], h->fixed_T, table)) {
             TailRec tr{};
-            tr.src = src;
+            tr.src = tcopy;  // in this launch's copy of the ids
             tr.m = mn;
             tr.sbase = h->inst_base[i];
             tr.cbase = off[i];
@@ -861,6 +900,9 @@ int64_t run_tails(picasso_ctx *h, const RunArgs &ra, const std::vector<int32_t> 
             tr.iter0 = (int32_t)(trs.size() * kTailMax);
             trs.push_back(tr);
             tinst.push_back(i);
+            tranges.push_back(src);
+            tranges.push_back(tcopy);
+            tcopy += mn;
         } else if (mn > 0) {
             ranges.push_back(src);
             ranges.push_back(kept);
@@ -871,51 +913,84 @@ int64_t run_tails(picasso_ctx *h, const RunArgs &ra, const std::vector<int32_t> 
     gathered = false;
     if (trs.empty()) return kept;
     const int32_t nt = (int32_t)trs.size();
-    TailRec *d_recs = buf<TailRec>(h, h->tail_recs, trs.size());
-    int32_t *d_table = buf<int32_t>(h, h->tail_table, table.size());
-    TailOut *d_outs = buf<TailOut>(h, h->tail_outs, trs.size());
-    TailIter *d_iters = buf<TailIter>(h, h->tail_iters, trs.size() * kTailMax);
+    if (tp.n_recs + nt > std::max<int32_t>(h->nb, 1) || tp.n_ids + tcopy > (int64_t)std::max<int32_t>(h->nb, 1) * kTailMax ||
+        tp.n_table + (int64_t)table.size() > (int64_t)std::max<int32_t>(h->nb, 1) * 2 * (kTailMax + 1))
+        throw Error(PICASSO_EINTERNAL, "tail buffers exceeded");
+    TailRec *d_recs = tp.recs + tp.n_recs;
+    int32_t *d_table = tp.table + tp.n_table;
+    int32_t *d_ids = tp.ids + tp.n_ids;
+    const int32_t *next = static_cast<const int32_t *>(h->next_ids.p);
+    // the tail instances' vertex ids, copied (the main path rewrites next_ids)
+    int64_t *d_tr = buf<int64_t>(h, h->tail_ranges, ranges.size() + tranges.size());
+    upload(h, d_tr, tranges.data(), tranges.size() * sizeof(int64_t));
+    launch_gather_ranges(next, d_ids, d_tr, (int32_t)(tranges.size() / 2), tcopy, st);
     upload(h, d_recs, trs.data(), trs.size() * sizeof(TailRec));
     upload(h, d_table, table.data(), table.size() * sizeof(int32_t));
-    const int32_t *next = static_cast<const int32_t *>(h->next_ids.p);
-    launch_tail(d_recs, nt, next, static_cast<const uint64_t *>(h->xz.p), h->W, d_table, d_out, d_outs, d_iters, st);
     if (kept > 0) {
-        int64_t *d_ranges = buf<int64_t>(h, h->tail_ranges, ranges.size());
+        int64_t *d_ranges = d_tr + tranges.size();
         upload(h, d_ranges, ranges.data(), ranges.size() * sizeof(int64_t));
         int32_t *ids = buf<int32_t>(h, h->ids, (size_t)kept);
         launch_gather_ranges(next, ids, d_ranges, (int32_t)(ranges.size() / 2), kept, st);
         gathered = true;
     }
-    std::vector<TailOut> outs(trs.size());
-    std::vector<TailIter> its(trs.size() * kTailMax);
-    download(h, outs.data(), d_outs, outs.size() * sizeof(TailOut));
-    download(h, its.data(), d_iters, its.size() * sizeof(TailIter));
-    for (int32_t b = 0; b < nt; ++b) {
-        const int32_t i = tinst[b];
-        picasso_instance_stats &is = h->istats[i];
-        n_colors[i] += outs[b].n_colors;
-        for (int32_t j = 0; j < outs[b].n_iters; ++j) {
-            const TailIter &ti = its[(size_t)b * kTailMax + j];
-            picasso_iter_stats it{};
-            it.m = ti.m;
-            it.P = ti.P;
-            it.T = ti.T;
-            it.pair_tests = ti.pair_tests;
-            it.edges = ti.edges;
-            it.edges_bound = ti.edges;  // counted exactly, no CSR to size
-            it.colored = ti.colored;
-            it.offset = h->nb == 1 ? ti.offset : 0;
-            it.pair_path = 0;
-            add_iter(S, iter_edges, (int64_t)ell + j, it);
-            off[i] += ti.P;
-            is.n_iters++;
-            is.palette_total += ti.P;
-            is.edges += ti.edges;
-            is.max_edges = std::max<int64_t>(is.max_edges, ti.edges);
-        }
-        mi[i] = 0;
-    }
+    // the copies and uploads are complete before the tail stream starts
+    PCHECK_HIP(hipEventRecord(h->tail_ready, st));
+    PCHECK_HIP(hipStreamWaitEvent(h->tail_stream, h->tail_ready, 0));
+    launch_tail(d_recs, nt, d_ids, static_cast<const uint64_t *>(h->xz.p), h->W, d_table, d_out, tp.outs + tp.n_recs,
+                tp.iters + tp.n_recs * kTailMax, h->tail_stream);
+    // d_tr is reused by the next launch's uploads: the gathers that read it
+    // are on the main stream, ordered before those uploads
+    tp.launches.push_back({ell, tp.n_recs, tinst});
+    tp.n_recs += nt;
+    tp.n_table += (int64_t)table.size();
+    tp.n_ids += tcopy;
+    tp.h_recs.push_back(std::move(trs));
+    tp.h_tables.push_back(std::move(table));
+    tp.h_ranges.push_back(std::move(tranges));
+    tp.h_ranges.push_back(std::move(ranges));
+    for (const int32_t i : tinst) mi[i] = 0;
     return kept;
+}
+
+// Waits for the tail launches (the main stream waits on the tail stream) and
+// adds their colour counts and iteration records.
+void tail_plan_finish(picasso_ctx *h, TailPlan &tp, std::vector<int64_t> &off, int64_t *n_colors, picasso_stats &S,
+                      std::vector<int64_t> &iter_edges)
+{
+    if (tp.launches.empty()) return;
+    PCHECK_HIP(hipEventRecord(h->tail_done, h->tail_stream));
+    PCHECK_HIP(hipStreamWaitEvent(h->stream, h->tail_done, 0));
+    std::vector<TailOut> outs((size_t)tp.n_recs);
+    std::vector<TailIter> its((size_t)tp.n_recs * kTailMax);
+    download(h, outs.data(), tp.outs, outs.size() * sizeof(TailOut));
+    download(h, its.data(), tp.iters, its.size() * sizeof(TailIter));
+    for (const TailPlan::Launch &L : tp.launches) {
+        for (size_t b = 0; b < L.tinst.size(); ++b) {
+            const int32_t i = L.tinst[b];
+            const int64_t r = L.rec0 + (int64_t)b;
+            picasso_instance_stats &is = h->istats[i];
+            n_colors[i] += outs[r].n_colors;
+            for (int32_t j = 0; j < outs[r].n_iters; ++j) {
+                const TailIter &ti = its[(size_t)r * kTailMax + j];
+                picasso_iter_stats it{};
+                it.m = ti.m;
+                it.P = ti.P;
+                it.T = ti.T;
+                it.pair_tests = ti.pair_tests;
+                it.edges = ti.edges;
+                it.edges_bound = ti.edges;  // counted exactly, no CSR to size
+                it.colored = ti.colored;
+                it.offset = h->nb == 1 ? ti.offset : 0;
+                it.pair_path = 0;
+                add_iter(S, iter_edges, (int64_t)L.ell + j, it);
+                off[i] += ti.P;
+                is.n_iters++;
+                is.palette_total += ti.P;
+                is.edges += ti.edges;
+                is.max_edges = std::max<int64_t>(is.max_edges, ti.edges);
+            }
+        }
+    }
 }
 
 // Colours every instance of the handle (Alg. 1 loop, all instances side by
@@ -941,6 +1016,9 @@ int64_t color_all(picasso_ctx *h, const RunArgs &ra, int32_t *d_out, int64_t *n_
     std::vector<int32_t> act;
     std::vector<int64_t> hv, iter_edges;
     std::vector<uint32_t> h_hits;
+    TailPlan tp;
+    const bool tails = !ra.mlp && h->use_tail && h->colourer == PICASSO_COLOURER_STATIC;
+    if (tails) tail_plan_init(h, tp);
     int64_t m = h->n;
     uint32_t ell = 1;
     while (m > 0) {
@@ -1092,15 +1170,15 @@ int64_t color_all(picasso_ctx *h, const RunArgs &ra, int32_t *d_out, int64_t *n_
         // others' vertices move to the front of the next vertex set
         bool gathered = false;
         // (with a schedule, once every further iteration uses its last entry)
-        if (!ra.mlp && h->use_tail && h->colourer == PICASSO_COLOURER_STATIC &&
-            (ra.n_steps == 0 || (int32_t)ell + 1 >= ra.n_steps)) {
-            const int64_t kept = run_tails(h, ra, act, mi, off, ell, n_colors, d_out, S, iter_edges, gathered);
+        if (tails && (ra.n_steps == 0 || (int32_t)ell + 1 >= ra.n_steps)) {
+            const int64_t kept = run_tails(h, ra, act, mi, off, ell, d_out, tp, gathered);
             m_next = kept;
         }
         if (!gathered) std::swap(h->ids, h->next_ids);
         m = m_next;
         ++ell;
     }
+    tail_plan_finish(h, tp, off, n_colors, S, iter_edges);
     PCHECK_HIP(hipStreamSynchronize(st));
     for (size_t k = 0; k < iter_edges.size(); ++k) S.max_edges = std::max(S.max_edges, iter_edges[k]);
     int64_t total = 0;
@@ -1311,11 +1389,15 @@ void picasso_destroy(picasso_handle h)
                      &h->nblk,    &h->st,       &h->rdy,     &h->jp_prog, &h->dflag, &h->wl,       &h->flags,   &h->pos,      &h->used,
                      &h->scan_tmp, &h->bx,      &h->bz,      &h->tile_bucket,
                      &h->scalars, &h->out_colors, &h->judge_out, &h->inst,    &h->vinst,    &h->loff,    &h->binst,    &h->inst_out, &h->tail_recs,
-                     &h->tail_table, &h->tail_outs, &h->tail_iters, &h->tail_ranges, &h->wake_at,
+                     &h->tail_table, &h->tail_outs, &h->tail_iters, &h->tail_ranges, &h->tail_ids, &h->wake_at,
                      &h->hits,    &h->csr_flag, &h->rkey,  &h->dyn_hist, &h->dyn_sstar, &h->dyn_cut,
                      &h->rx_k64a, &h->rx_k64b, &h->rx_va, &h->rx_vb,   &h->rx_tmp,  &h->rx_tr,   &h->rx_at,
                      &h->rx_cka,  &h->rx_ckb,  &h->rx_cva, &h->rx_cvb};
     for (DevBuf *b : all) h->arena.release(*b);
+    if (h->tail_stream) (void)hipStreamSynchronize(h->tail_stream);
+    if (h->tail_ready) (void)hipEventDestroy(h->tail_ready);
+    if (h->tail_done) (void)hipEventDestroy(h->tail_done);
+    if (h->tail_stream) (void)hipStreamDestroy(h->tail_stream);
     if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
     delete h;
 }
