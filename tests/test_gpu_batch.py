@@ -98,6 +98,28 @@ def test_batch_rounds_and_graph_options(mixed):
             assert nc[i] == rnc and np.array_equal(cols[i], rcol), (opts, i)
 
 
+def test_batch_on_caller_stream_and_repeated_calls(mixed):
+    """On a stream the caller owns (PICASSO_OPT_STREAM; the tail kernels run
+    on the handle's second stream and are joined back to it), and on three
+    calls in a row on one handle: the same colours and statistics."""
+    import torch
+
+    insts, refs = mixed
+    s = torch.cuda.Stream()
+    with pk.PicassoBatch([(d["x"], d["z"], d["q"]) for d in insts]) as h:
+        args = ([d["seed"] for d in insts], [d["frac"] for d in insts], [d["alpha"] for d in insts],
+                [d["rel"] for d in insts])
+        h.set_option(pk.OPT_STREAM, s.cuda_stream)
+        for rep in range(3):
+            nc, cols = h.color_batch(*args)
+            ist = h.instance_stats()
+            for i, (rnc, rcol, rst) in enumerate(refs):
+                assert nc[i] == rnc and np.array_equal(cols[i], rcol), (rep, i)
+                assert ist[i]["n_iters"] == len(rst), (rep, i)
+        h.set_option(pk.OPT_STREAM, 0)
+    torch.cuda.synchronize()
+
+
 def test_batch_equals_single_handles(mixed):
     insts, refs = mixed
     picked = [d for d in insts if d["x"].shape[0] > 0][:6]
