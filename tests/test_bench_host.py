@@ -30,7 +30,8 @@ def test_recorded_traffic_is_gated_on_workload_and_source():
         got = bench.recorded_traffic(rec["workload"], rec["path"], rec)
         want = (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]) * 1024.0
         assert got == want and got > 0
-        assert bench.recorded_traffic("C4 n=2000000 q=128 pI=0.8", rec["path"], rec) is None
+        other = "C2 n=200000 q=48 pI=0.7" if rec["workload"].startswith("C4") else "C4 n=2000000 q=128 pI=0.8"
+        assert bench.recorded_traffic(other, rec["path"], rec) is None
         assert bench.recorded_traffic(rec["workload"], "mfma", rec) is None
         stale = dict(rec, sha256="0" * 64)  # the kernel source changed since the counters were taken
         assert bench.recorded_traffic(rec["workload"], rec["path"], stale) is None
