@@ -95,7 +95,7 @@ struct picasso_ctx {
         rb_off, R, D, bx, bz, tile_bucket, nslow, slow, slot_cnt, slot_off, rowptr, adj, col, blk, fre, nblk, st, rdy, jp_prog, dflag,
         wake_at, wl, flags, pos, used, scan_tmp, scalars, out_colors, judge_out, inst, vinst, loff, binst,
         inst_out, tail_recs, tail_table, tail_outs, tail_iters, tail_ranges, tail_ids, hits, csr_flag, rkey, dyn_hist, dyn_sstar,
-        dyn_cut, rx_k64a, rx_k64b, rx_va, rx_vb, rx_tmp, rx_tr, rx_at, rx_cka, rx_ckb, rx_cva, rx_cvb;
+        dyn_cut, rx_k32a, rx_k32b, rx_va, rx_vb, rx_tmp, rx_tr, rx_at, rx_cka, rx_ckb, rx_cva, rx_cvb;
     std::vector<InstRec> h_inst;  // table of the active instances (kept until the copy has completed)
     picasso_stats stats;
     std::vector<picasso_instance_stats> istats;
@@ -253,13 +253,13 @@ BucketInfo buckets_from_lists(picasso_ctx *h, Batch &b, int64_t m, int64_t E, in
     if (radix) {
         // vertices in (priority, index) order, their entries in that order,
         // then a stable sort by colour: sorted buckets in one pass per digit
-        uint64_t *k64a = buf<uint64_t>(h, h->rx_k64a, (size_t)m), *k64b = buf<uint64_t>(h, h->rx_k64b, (size_t)m);
+        uint32_t *k32a = buf<uint32_t>(h, h->rx_k32a, (size_t)m), *k32b = buf<uint32_t>(h, h->rx_k32b, (size_t)m);
         uint32_t *va = buf<uint32_t>(h, h->rx_va, (size_t)m), *vb = buf<uint32_t>(h, h->rx_vb, (size_t)m);
         void *rtmp = h->arena.ensure(h->rx_tmp, radix_tmp_bytes(std::max<int64_t>(m, E)));
-        PCHECK_HIP(hipMemcpyAsync(k64a, prio, (size_t)m * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
-        launch_iota_u32(va, m, st);
-        const int f1 = radix_sort_pairs<uint64_t>(k64a, va, k64b, vb, m, 0, 64, rtmp, st);
-        const uint32_t *perm = f1 ? vb : va;
+        launch_prio_keys(prio, m, k32a, va, st);
+        const int f1 = radix_sort_pairs<uint32_t>(k32a, va, k32b, vb, m, 0, 32, rtmp, st);
+        uint32_t *perm = f1 ? vb : va;
+        launch_prio_ties(f1 ? k32b : k32a, perm, prio, m, st);
         int32_t *tr = buf<int32_t>(h, h->rx_tr, (size_t)m);
         int64_t *at = buf<int64_t>(h, h->rx_at, (size_t)m + 1);
         launch_ranked_sizes(perm, m, b.loff, tr, st);
@@ -1391,7 +1391,7 @@ void picasso_destroy(picasso_handle h)
                      &h->scalars, &h->out_colors, &h->judge_out, &h->inst,    &h->vinst,    &h->loff,    &h->binst,    &h->inst_out, &h->tail_recs,
                      &h->tail_table, &h->tail_outs, &h->tail_iters, &h->tail_ranges, &h->tail_ids, &h->wake_at,
                      &h->hits,    &h->csr_flag, &h->rkey,  &h->dyn_hist, &h->dyn_sstar, &h->dyn_cut,
-                     &h->rx_k64a, &h->rx_k64b, &h->rx_va, &h->rx_vb,   &h->rx_tmp,  &h->rx_tr,   &h->rx_at,
+                     &h->rx_k32a, &h->rx_k32b, &h->rx_va, &h->rx_vb,   &h->rx_tmp,  &h->rx_tr,   &h->rx_at,
                      &h->rx_cka,  &h->rx_ckb,  &h->rx_cva, &h->rx_cvb};
     for (DevBuf *b : all) h->arena.release(*b);
     if (h->tail_stream) (void)hipStreamSynchronize(h->tail_stream);

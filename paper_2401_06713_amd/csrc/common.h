@@ -34,6 +34,20 @@ constexpr uint32_t TAG_PRIO = 0x5052494Fu;
 constexpr int32_t COL_UNDECIDED = -2;
 constexpr int32_t COL_FAILED = -1;
 
+// ---- XCD-aware workgroup order ---------------------------------------------
+// The dispatcher hands workgroups to the eight XCDs in turn (workgroup i to
+// XCD i mod 8), and each XCD has an L2 of its own.  For work whose
+// neighbouring items share output or input cache lines, this maps workgroup
+// ids to items so that each XCD takes one contiguous run of items in order;
+// the few items past the last multiple of eight keep their own ids.  A
+// bijection on [0, n).
+__device__ __forceinline__ int64_t xcd_item(int64_t bid, int64_t n)
+{
+    const int64_t q = n >> 3;
+    if (bid >= (q << 3)) return bid;
+    return (bid & 7) * q + (bid >> 3);
+}
+
 // ---- Philox4x32-10, device side --------------------------------------------
 // Counter (v, s, ell, tag), key (seed lo, seed hi); returns word1:word0.
 __device__ __forceinline__ uint64_t philox_draw(uint64_t seed, uint32_t v, uint32_t s, uint32_t ell, uint32_t tag)
@@ -274,14 +288,19 @@ void launch_jp_batch_begin(const JpArgs &a, int32_t rounds, hipStream_t st);
 void launch_jp_round(const JpArgs &a, int cur, int32_t k, hipStream_t st);
 void launch_jp_batch_end(const JpArgs &a, int32_t rounds, hipStream_t st);
 // radix.hip: stable LSD radix sort of (key, 32-bit value) pairs by bits
-// [bit_lo, bit_hi) in 8-bit digits; ping-pongs between the two buffer pairs
+// [bit_lo, bit_hi) in 8- or 9-bit digits; ping-pongs between the two buffer pairs
 // and returns 1 if the result is in the alternate pair.  tmp: at least
 // radix_tmp_bytes(n) bytes.
 size_t radix_tmp_bytes(int64_t n);
 template <typename K>
 int radix_sort_pairs(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals_alt, int64_t n, int bit_lo, int bit_hi,
                      void *tmp, hipStream_t st);
-void launch_iota_u32(uint32_t *p, int64_t n, hipStream_t st);
+// Vertex order by (priority, index): keys hi[v] = the high half of prio[v]
+// and values idx[v] = v for radix_sort_pairs over bits [0, 32); then, on the
+// sorted keys and values (perm), the runs of equal high halves ordered by
+// the whole priority.
+void launch_prio_keys(const uint64_t *prio, int64_t m, uint32_t *hi, uint32_t *idx, hipStream_t st);
+void launch_prio_ties(const uint32_t *hi, uint32_t *perm, const uint64_t *prio, int64_t m, hipStream_t st);
 // List sizes of the vertices in priority order (perm[r]: the vertex at rank r).
 void launch_ranked_sizes(const uint32_t *perm, int64_t m, const int64_t *loff, int32_t *tr, hipStream_t st);
 // (colour, entry index) of every list entry, vertices in priority order

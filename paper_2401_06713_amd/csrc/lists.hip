@@ -182,7 +182,18 @@ __global__ void bucket_pairs_kernel(const uint32_t *__restrict__ bcnt, int64_t P
         const unsigned long long o = __shfl_down(mx, d, 64);
         mx = o > mx ? o : mx;
     }
+    // one pair of atomics per workgroup: they all land on one line
+    __shared__ unsigned long long ws[4], wm[4];
     if ((threadIdx.x & 63) == 0) {
+        ws[threadIdx.x >> 6] = s;
+        wm[threadIdx.x >> 6] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+            s += ws[w];
+            mx = wm[w] > mx ? wm[w] : mx;
+        }
         if (s) atomicAdd(&pairs[0], s);
         atomicMax(&pairs[1], mx);
     }
@@ -425,7 +436,7 @@ void launch_check_padding(const uint64_t *x, const uint64_t *z, int64_t n, int32
 void launch_bucket_pairs(const uint32_t *bcnt, int64_t P, unsigned long long *pairs, hipStream_t st)
 {
     if (P <= 0) return;
-    bucket_pairs_kernel<<<grid_for(P, 256, 2048), 256, 0, st>>>(bcnt, P, pairs);
+    bucket_pairs_kernel<<<grid_for(P, 256, 128), 256, 0, st>>>(bcnt, P, pairs);
     PCHECK_LAUNCH();
 }
 

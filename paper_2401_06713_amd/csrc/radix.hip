@@ -8,11 +8,15 @@
 // round of 256 elements, each wave finds the lanes with its digit by one
 // ballot per digit bit, and per-wave digit counts in LDS order the four
 // waves.  The ranked tile is staged in LDS in digit order and written out
-// from there, in runs of one digit.
+// from there, in runs of one digit.  Tiles go to the XCDs in contiguous
+// runs: a digit's runs from neighbouring tiles are neighbours in the output,
+// as are the tiles' entries in the (digit, tile) count and offset tables, so
+// their partly written or read cache lines meet in one L2.
 //
 // Bucket build (Alg. 1 buckets of list entries, members in the colouring
-// order): the vertices are sorted by (priority, index) (eight passes over the
-// 64-bit priority, stable from ascending index), their list entries are
+// order): the vertices are sorted by (priority, index) (four passes over the
+// priority's high half, stable from ascending index, then the rare runs of
+// equal high halves ordered by the whole priority), their list entries are
 // emitted in that order, and a stable sort by colour then leaves every
 // bucket's members in priority order -- count, scatter and the per-bucket
 // sort in one pass over the entries per colour digit, with no atomics on
@@ -43,14 +47,15 @@ __global__ void __launch_bounds__(kRThreads) radix_hist_kernel(const K *__restri
     __shared__ uint32_t h[kBins];
     for (int d = threadIdx.x; d < kBins; d += kRThreads) h[d] = 0u;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kRTile;
+    const int64_t tile = xcd_item(blockIdx.x, ntiles);
+    const int64_t base = tile * kRTile;
 #pragma unroll
     for (int i = 0; i < kRItems; ++i) {
         const int64_t g = base + (int64_t)i * kRThreads + threadIdx.x;
         if (g < n) atomicAdd(&h[digit_of<K, DB>(keys[g], shift)], 1u);
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < kBins; d += kRThreads) counts[(int64_t)d * ntiles + blockIdx.x] = h[d];
+    for (int d = threadIdx.x; d < kBins; d += kRThreads) counts[(int64_t)d * ntiles + tile] = h[d];
 }
 
 // Scatter of one tile: each element's rank among the tile's elements of its
@@ -76,7 +81,7 @@ __global__ void __launch_bounds__(kRThreads) radix_scatter_kernel(const K *__res
     __shared__ K skey[kRTile];
     __shared__ uint32_t sval[kRTile];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int64_t tile = blockIdx.x;
+    const int64_t tile = xcd_item(blockIdx.x, ntiles);
     // the tile's digit counts, scanned: kPer bins per thread, then the waves
     uint32_t cnt[kPer], sum = 0u;
 #pragma unroll
@@ -158,10 +163,44 @@ __global__ void __launch_bounds__(kRThreads) radix_scatter_kernel(const K *__res
 
 // ---- bucket build ------------------------------------------------------------
 
-__global__ void iota_u32_kernel(uint32_t *p, int64_t n)
+// Sort keys of the vertex order: the high half of each 64-bit priority,
+// with the vertex index as the value.
+__global__ void prio_keys_kernel(const uint64_t *__restrict__ prio, int64_t m, uint32_t *__restrict__ hi,
+                                 uint32_t *__restrict__ idx)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = (uint32_t)i;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        hi[i] = (uint32_t)(prio[i] >> 32);
+        idx[i] = (uint32_t)i;
+    }
+}
+
+// After the stable sort by the high halves, every run of equal high halves
+// is in index order; the thread at the start of a run puts it in (priority,
+// index) order by insertion on the full priorities.  Runs are short: of m
+// random priorities, about m^2 / 2^33 pairs share a high half.
+__global__ void prio_ties_kernel(const uint32_t *__restrict__ hi, uint32_t *__restrict__ perm,
+                                 const uint64_t *__restrict__ prio, int64_t m)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t h = hi[i];
+        if (i + 1 >= m || hi[i + 1] != h) continue;
+        if (i > 0 && hi[i - 1] == h) continue;
+        int64_t end = i + 2;
+        while (end < m && hi[end] == h) ++end;
+        for (int64_t j = i + 1; j < end; ++j) {
+            const uint32_t v = perm[j];
+            const uint64_t pv = prio[v];
+            int64_t k = j;
+            while (k > i) {
+                const uint32_t u = perm[k - 1];
+                const uint64_t pu = prio[u];
+                if (pu < pv || (pu == pv && u < v)) break;
+                perm[k] = u;
+                --k;
+            }
+            perm[k] = v;
+        }
+    }
 }
 
 // List sizes in priority order (vertex perm[r] at rank r).
@@ -317,15 +356,20 @@ int radix_sort_pairs(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals_alt, i
     return flips;
 }
 
-template int radix_sort_pairs<uint64_t>(uint64_t *, uint32_t *, uint64_t *, uint32_t *, int64_t, int, int, void *,
-                                        hipStream_t);
 template int radix_sort_pairs<uint32_t>(uint32_t *, uint32_t *, uint32_t *, uint32_t *, int64_t, int, int, void *,
                                         hipStream_t);
 
-void launch_iota_u32(uint32_t *p, int64_t n, hipStream_t st)
+void launch_prio_keys(const uint64_t *prio, int64_t m, uint32_t *hi, uint32_t *idx, hipStream_t st)
 {
-    if (n <= 0) return;
-    iota_u32_kernel<<<grid_for(n, 256), 256, 0, st>>>(p, n);
+    if (m <= 0) return;
+    prio_keys_kernel<<<grid_for(m, 256), 256, 0, st>>>(prio, m, hi, idx);
+    PCHECK_LAUNCH();
+}
+
+void launch_prio_ties(const uint32_t *hi, uint32_t *perm, const uint64_t *prio, int64_t m, hipStream_t st)
+{
+    if (m <= 1) return;
+    prio_ties_kernel<<<grid_for(m, 256), 256, 0, st>>>(hi, perm, prio, m);
     PCHECK_LAUNCH();
 }
 
