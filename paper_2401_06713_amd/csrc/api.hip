@@ -86,13 +86,14 @@ struct picasso_ctx {
     int32_t bucket_build = 0;  // 0 auto, 1 atomics + per-bucket sort, 2 radix sort
     int32_t colourer = PICASSO_COLOURER_STATIC;
     int32_t dyn_divisor = 16;  // dynamic colourer: about one active vertex in this many requests per round
+    int64_t seg_m = 0;       // vertex stride of h->seg (the last conflict-graph build's m)
     int32_t csr_sizing = 1;  // colouring calls: 1 CSR sized by the predicted bound, 0 by the exact
                              // size, 2 bound forced to zero (every iteration refills; for tests)
     Arena arena;
     DevBuf x, z, xz;  // bit-planes, and the interleaved copy the member gather reads
     // iteration buffers
     DevBuf ids, next_ids, lists, prio, bcnt, bstart, bmem, bslot, pos_of, bent, tmp_mem, tmp_slot, tiles, words, tile_off,
-        rb_off, R, D, bx, bz, tile_bucket, nslow, slow, slot_cnt, slot_off, rowptr, adj, col, blk, fre, nblk, st, rdy, jp_prog, dflag,
+        rb_off, R, D, bx, bz, tile_bucket, nslow, slow, seg, deg, rowptr, adj, col, blk, fre, nblk, st, rdy, jp_prog, dflag,
         wake_at, wl, flags, pos, used, scan_tmp, scalars, out_colors, judge_out, inst, vinst, loff, binst,
         inst_out, tail_recs, tail_table, tail_outs, tail_iters, tail_ranges, tail_ids, hits, csr_flag, rkey, dyn_hist, dyn_sstar,
         dyn_cut, rx_k32a, rx_k32b, rx_va, rx_vb, rx_tmp, rx_tr, rx_at, rx_cka, rx_ckb, rx_cva, rx_cvb;
@@ -375,8 +376,9 @@ CsrArgs csr_args(picasso_ctx *h, const Batch &b, int64_t P)
     ca.D = static_cast<const uint64_t *>(h->D.p);
     ca.dflag = static_cast<const uint8_t *>(h->dflag.p);
     ca.loff = b.loff;
-    ca.bent = static_cast<const int64_t *>(h->bent.p);
-    ca.slot_off = static_cast<const int64_t *>(h->slot_off.p);
+    ca.seg = static_cast<int32_t *>(h->seg.p);
+    ca.seg_m = h->seg_m;
+    ca.rowptr = static_cast<const int64_t *>(h->rowptr.p);
     ca.v_lo = 0;
     ca.v_hi = INT64_MAX;
     ca.adj_base = 0;
@@ -385,8 +387,8 @@ CsrArgs csr_args(picasso_ctx *h, const Batch &b, int64_t P)
 
 // Relation matrices, duplicate-pair matrices, CSR counts, scan and fill.
 // rel_mask bit r: some instance of the batch uses relation r.  Returns
-// |E_c|; the CSR is in h->rowptr / h->adj, the per-entry offsets in
-// h->slot_off.
+// |E_c|; the CSR is in h->rowptr / h->adj, each member's offset within its
+// row in h->seg (slot-major, stride h->seg_m).
 int64_t build_conflict_graph(picasso_ctx *h, const Batch &b, int64_t m, int64_t E, int64_t P, int32_t T_max,
                              int32_t rel_mask, const BucketInfo &bi, double *ms_relate, double *ms_csr,
                              bool *used_mfma = nullptr, bool csr_required = true, int64_t edge_bound = -1,
@@ -467,16 +469,17 @@ int64_t build_conflict_graph(picasso_ctx *h, const Batch &b, int64_t m, int64_t 
         launch_dup(da, st);
         launch_dup_slow(da, st);  // its bucket count is read on the device
     }
-    // edge counts per (vertex, slot), scan, row pointers
-    CsrArgs ca = csr_args(h, b, P);
-    ca.slot_cnt = buf<int32_t>(h, h->slot_cnt, (size_t)std::max<int64_t>(E, 1));
-    launch_count(ca, st);
-    int64_t *slot_off = buf<int64_t>(h, h->slot_off, (size_t)E + 1);
-    void *tmp = h->arena.ensure(h->scan_tmp, scan_tmp_bytes(std::max<int64_t>(P, E) + 1));
-    exclusive_scan_i32_to_i64(ca.slot_cnt, slot_off, E, true, tmp, st);
+    // edge counts per (vertex, slot), their offsets within each row, row
+    // pointers from a scan of the row lengths
+    buf<int32_t>(h, h->seg, (size_t)std::max<int64_t>((int64_t)T_max * m, 1));
+    h->seg_m = m;
     int64_t *rowptr = buf<int64_t>(h, h->rowptr, (size_t)m + 1);
-    launch_rowptr(slot_off, m, b.loff, rowptr, st);
-    ca.slot_off = slot_off;
+    CsrArgs ca = csr_args(h, b, P);
+    launch_count(ca, st);
+    int32_t *deg = buf<int32_t>(h, h->deg, (size_t)std::max<int64_t>(m, 1));
+    launch_row_offsets(ca.seg, m, b.loff, deg, st);
+    void *tmp = h->arena.ensure(h->scan_tmp, scan_tmp_bytes(std::max<int64_t>(P, E) + 1));
+    exclusive_scan_i32_to_i64(deg, rowptr, m, true, tmp, st);
     if (edge_bound >= 0 && !csr_required &&
         (h->mem_budget <= 0 || 2 * edge_bound * (int64_t)sizeof(int32_t) <= h->mem_budget)) {
         // CSR sized by the predicted bound: the fill is queued without waiting
@@ -485,7 +488,7 @@ int64_t build_conflict_graph(picasso_ctx *h, const Batch &b, int64_t m, int64_t 
         const int64_t cap = 2 * edge_bound;
         ca.adj = buf<int32_t>(h, h->adj, (size_t)std::max<int64_t>(cap, 1));
         int32_t *flag = buf<int32_t>(h, h->csr_flag, 1);
-        launch_csr_guard(slot_off + E, cap, flag, st);
+        launch_csr_guard(rowptr + m, cap, flag, st);
         ca.skip = flag;
         tm.mark();
         launch_fill(ca, bi.max_size, st);
@@ -494,7 +497,7 @@ int64_t build_conflict_graph(picasso_ctx *h, const Batch &b, int64_t m, int64_t 
         if (ms_csr) *ms_csr = tm.ms(2, 3);
         return -1;
     }
-    const int64_t total = read_scalar(h, slot_off + E);
+    const int64_t total = read_scalar(h, rowptr + m);
     if (total % 2) throw Error(PICASSO_EINTERNAL, "odd CSR size");
     const int64_t bytes = total * (int64_t)sizeof(int32_t);
     if (h->mem_budget > 0 && bytes > h->mem_budget) {
@@ -1123,7 +1126,7 @@ int64_t color_all(picasso_ctx *h, const RunArgs &ra, int32_t *d_out, int64_t *n_
         exclusive_scan_i32_to_i64(flags, pos, m, true, tmp, st);
         int32_t *next = buf<int32_t>(h, h->next_ids, (size_t)m);
         launch_compact_ids(m, d_ids, flags, pos, next, st);
-        launch_instance_totals(b, pos, static_cast<const int64_t *>(h->slot_off.p), iout + na,
+        launch_instance_totals(b, pos, static_cast<const int64_t *>(h->rowptr.p), iout + na,
                                h->edges_on ? iout + 2 * na : nullptr, st);
         tm.mark();
         hv.resize((size_t)3 * na);
@@ -1385,7 +1388,7 @@ void picasso_destroy(picasso_handle h)
     DevBuf *all[] = {&h->x,       &h->z,       &h->xz,        &h->ids,     &h->next_ids, &h->lists,   &h->prio,     &h->bcnt,
                      &h->bstart,  &h->bmem,     &h->bslot,   &h->pos_of,   &h->bent, &h->tmp_mem, &h->tmp_slot, &h->tiles,
                      &h->words,   &h->tile_off, &h->rb_off,  &h->R,        &h->D,       &h->nslow,    &h->slow,
-                     &h->slot_cnt, &h->slot_off, &h->rowptr, &h->adj,      &h->col,     &h->blk,      &h->fre,
+                     &h->seg,      &h->deg,      &h->rowptr, &h->adj,      &h->col,     &h->blk,      &h->fre,
                      &h->nblk,    &h->st,       &h->rdy,     &h->jp_prog, &h->dflag, &h->wl,       &h->flags,   &h->pos,      &h->used,
                      &h->scan_tmp, &h->bx,      &h->bz,      &h->tile_bucket,
                      &h->scalars, &h->out_colors, &h->judge_out, &h->inst,    &h->vinst,    &h->loff,    &h->binst,    &h->inst_out, &h->tail_recs,

@@ -683,13 +683,13 @@ __global__ void compact_kernel(int64_t m, const int32_t *ids, const int32_t *fla
         if (flag[i]) next_ids[pos[i]] = ids[i];
 }
 
-__global__ void instance_totals_kernel(Batch b, const int64_t *pos, const int64_t *slot_off, int64_t *m_next,
+__global__ void instance_totals_kernel(Batch b, const int64_t *pos, const int64_t *rowptr, int64_t *m_next,
                                        int64_t *edges)
 {
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < b.nb; i += gridDim.x * blockDim.x) {
         const InstRec &r = b.inst[i];
         if (m_next) m_next[i] = pos[r.vstart + r.m] - pos[r.vstart];
-        if (edges) edges[i] = (slot_off[r.loff + r.m * r.T] - slot_off[r.loff]) / 2;
+        if (edges) edges[i] = (rowptr[r.vstart + r.m] - rowptr[r.vstart]) / 2;
     }
 }
 
@@ -750,11 +750,11 @@ void launch_finish_iteration(const Batch &b, int64_t m, const int32_t *col, cons
     PCHECK_LAUNCH();
 }
 
-void launch_instance_totals(const Batch &b, const int64_t *pos, const int64_t *slot_off, int64_t *m_next,
+void launch_instance_totals(const Batch &b, const int64_t *pos, const int64_t *rowptr, int64_t *m_next,
                             int64_t *edges, hipStream_t st)
 {
     if (b.nb <= 0) return;
-    instance_totals_kernel<<<grid_for(b.nb, 256), 256, 0, st>>>(b, pos, slot_off, m_next, edges);
+    instance_totals_kernel<<<grid_for(b.nb, 256), 256, 0, st>>>(b, pos, rowptr, m_next, edges);
     PCHECK_LAUNCH();
 }
 

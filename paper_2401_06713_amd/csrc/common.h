@@ -221,9 +221,13 @@ struct CsrArgs {
     const uint64_t *R, *D;
     const uint8_t *dflag;    // per bucket entry: its D row has a bit (rows without one read R alone)
     const int64_t *loff;     // list entry of (v, 0)
-    const int64_t *bent;     // list entry of each bucket member
-    int32_t *slot_cnt;       // count pass: edge count per list entry (vertex, slot)
-    const int64_t *slot_off; // fill pass: exclusive scan of slot_cnt
+    // Segment of member (v, s) in v's CSR row, slot-major: seg[s * seg_m + v]
+    // holds its edge count after the count pass, its offset within the row
+    // after launch_row_offsets (members of one colour have nearby slots, so
+    // a bucket's accesses fall in a few slot rows of seg_m entries each)
+    int32_t *seg;
+    int64_t seg_m;
+    const int64_t *rowptr;   // fill pass: row starts (m + 1)
     int32_t *adj;            // fill pass: CSR column indices
     const int32_t *skip;     // fill pass: if non-null and nonzero, write nothing
     int64_t v_lo, v_hi;      // fill pass: only the rows of vertices in [v_lo, v_hi) ...
@@ -231,7 +235,9 @@ struct CsrArgs {
 };
 void launch_count(const CsrArgs &a, hipStream_t st);
 void launch_fill(const CsrArgs &a, int64_t max_size, hipStream_t st);  // max_size: largest bucket
-void launch_rowptr(const int64_t *slot_off, int64_t m, const int64_t *loff, int64_t *rowptr, hipStream_t st);
+// Each vertex's segment counts (seg, slot-major with stride m) become their
+// exclusive prefix within the row, in place; deg[v] = the row's length.
+void launch_row_offsets(int32_t *seg, int64_t m, const int64_t *loff, int32_t *deg, hipStream_t st);
 // flag = (*total > cap): the CSR of *total entries does not fit cap entries.
 void launch_csr_guard(const int64_t *total, int64_t cap, int32_t *flag, hipStream_t st);
 
@@ -353,8 +359,8 @@ void launch_csr_to_relation(int64_t m, const int64_t *rowptr, const int32_t *adj
 void launch_finish_iteration(const Batch &b, int64_t m, const int32_t *col, const int32_t *ids, int32_t *out_colors,
                              uint32_t *used_bits, unsigned long long *n_used, int32_t *uncol_flag, hipStream_t st);
 // Per instance: vertices left (from the compaction positions) and conflict
-// edges (from the CSR slot offsets, halved).
-void launch_instance_totals(const Batch &b, const int64_t *pos, const int64_t *slot_off, int64_t *m_next,
+// edges (from the CSR row pointers, halved).
+void launch_instance_totals(const Batch &b, const int64_t *pos, const int64_t *rowptr, int64_t *m_next,
                             int64_t *edges, hipStream_t st);
 void launch_compact_ids(int64_t m, const int32_t *ids, const int32_t *flag, const int64_t *pos, int32_t *next_ids,
                         hipStream_t st);

@@ -12,8 +12,9 @@
 //   D: pairs that share a colour smaller than the bucket's (dup_kernel).
 // The bucket's conflict edges are R & ~D (D is read only for the members
 // whose dflag byte says their row has a bit).  count_kernel pop-counts each
-// row into the member's (vertex, slot) segment length; after a scan,
-// fill_kernel expands each row into its CSR segment.  The colouring reads
+// row into the member's (vertex, slot) segment length; per-vertex prefixes
+// and a scan of the row lengths place the segments, and fill_kernel expands
+// each row into its CSR segment.  The colouring reads
 // the lower triangle of R (earlier members) directly.
 #include "common.h"
 
@@ -418,7 +419,7 @@ __global__ void __launch_bounds__(kWave) count_kernel(CsrArgs a)
             } else {
                 for (int64_t w = 0; w < nw; ++w) cnt += __popcll(Rm[p * nw + w]);
             }
-            a.slot_cnt[a.bent[base + p]] = cnt;
+            a.seg[(int64_t)a.bslot[base + p] * a.seg_m + a.bmem[base + p]] = cnt;
         }
     }
 }
@@ -456,7 +457,7 @@ __global__ void __launch_bounds__(kWave * kFillWaves) fill_kernel(CsrArgs a, int
             for (int64_t p = threadIdx.x; p < S; p += blockDim.x) {
                 const uint32_t v = a.bmem[base + p];
                 mv[p] = v;
-                seg[p] = a.slot_off[a.bent[base + p]];
+                seg[p] = a.rowptr[v] + a.seg[(int64_t)a.bslot[base + p] * a.seg_m + v];
             }
             // D is read only for the rows that have a bit in it
             for (int64_t w = threadIdx.x; w < S * nw; w += blockDim.x) {
@@ -479,7 +480,7 @@ __global__ void __launch_bounds__(kWave * kFillWaves) fill_kernel(CsrArgs a, int
             for (int64_t p = wave; p < S; p += kFillWaves) {
                 const int64_t v = a.bmem[base + p];
                 if (v < a.v_lo || v >= a.v_hi) continue;  // another chunk's row
-                int64_t at = a.slot_off[a.bent[base + p]] - a.adj_base;
+                int64_t at = a.rowptr[v] + a.seg[(int64_t)a.bslot[base + p] * a.seg_m + v] - a.adj_base;
                 const bool dd = a.dflag[base + p];
                 for (int64_t w = 0; w < nw; ++w) {
                     const uint64_t bits = dd ? Rm[p * nw + w] & ~Dm[p * nw + w] : Rm[p * nw + w];
@@ -493,10 +494,20 @@ __global__ void __launch_bounds__(kWave * kFillWaves) fill_kernel(CsrArgs a, int
     }
 }
 
-__global__ void rowptr_kernel(const int64_t *slot_off, int64_t m, const int64_t *loff, int64_t *rowptr)
+// One thread per vertex; for each slot the threads of a wave touch
+// consecutive vertices of one slot row.
+__global__ void row_offsets_kernel(int32_t *seg, int64_t m, const int64_t *loff, int32_t *deg)
 {
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v <= m; v += (int64_t)gridDim.x * blockDim.x)
-        rowptr[v] = slot_off[loff[v]];
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < m; v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t T = loff[v + 1] - loff[v];
+        int32_t run = 0;
+        for (int64_t s = 0; s < T; ++s) {
+            const int32_t c = seg[s * m + v];
+            seg[s * m + v] = run;
+            run += c;
+        }
+        deg[v] = run;
+    }
 }
 
 unsigned grid_cap(int64_t items, int64_t cap = 1 << 22)
@@ -549,10 +560,11 @@ void launch_csr_guard(const int64_t *total, int64_t cap, int32_t *flag, hipStrea
     PCHECK_LAUNCH();
 }
 
-void launch_rowptr(const int64_t *slot_off, int64_t m, const int64_t *loff, int64_t *rowptr, hipStream_t st)
+void launch_row_offsets(int32_t *seg, int64_t m, const int64_t *loff, int32_t *deg, hipStream_t st)
 {
-    const int64_t b = (m + 1 + 255) / 256;
-    rowptr_kernel<<<grid_cap(b, 65535 * 16), 256, 0, st>>>(slot_off, m, loff, rowptr);
+    if (m <= 0) return;
+    const int64_t b = (m + 255) / 256;
+    row_offsets_kernel<<<grid_cap(b, 65535 * 16), 256, 0, st>>>(seg, m, loff, deg);
     PCHECK_LAUNCH();
 }
 
