@@ -93,7 +93,7 @@ struct picasso_ctx {
     DevBuf x, z, xz;  // bit-planes, and the interleaved copy the member gather reads
     // iteration buffers
     DevBuf ids, next_ids, lists, prio, bcnt, bstart, bmem, bslot, pos_of, bent, tmp_mem, tmp_slot, tiles, words, tile_off,
-        rb_off, R, D, bx, bz, tile_bucket, nslow, slow, seg, deg, rowptr, adj, col, blk, fre, nblk, st, rdy, jp_prog, dflag,
+        rb_off, R, D, bx, bz, tile_bucket, nslow, slow, seg, seg_off, deg, rowptr, adj, col, blk, fre, nblk, st, rdy, jp_prog, dflag,
         wake_at, wl, flags, pos, used, scan_tmp, scalars, out_colors, judge_out, inst, vinst, loff, binst,
         inst_out, tail_recs, tail_table, tail_outs, tail_iters, tail_ranges, tail_ids, hits, csr_flag, rkey, dyn_hist, dyn_sstar,
         dyn_cut, rx_k32a, rx_k32b, rx_va, rx_vb, rx_tmp, rx_tr, rx_at, rx_cka, rx_ckb, rx_cva, rx_cvb;
@@ -377,8 +377,8 @@ CsrArgs csr_args(picasso_ctx *h, const Batch &b, int64_t P)
     ca.dflag = static_cast<const uint8_t *>(h->dflag.p);
     ca.loff = b.loff;
     ca.seg = static_cast<int32_t *>(h->seg.p);
+    ca.seg_off = static_cast<const int64_t *>(h->seg_off.p);
     ca.seg_m = h->seg_m;
-    ca.rowptr = static_cast<const int64_t *>(h->rowptr.p);
     ca.v_lo = 0;
     ca.v_hi = INT64_MAX;
     ca.adj_base = 0;
@@ -387,8 +387,8 @@ CsrArgs csr_args(picasso_ctx *h, const Batch &b, int64_t P)
 
 // Relation matrices, duplicate-pair matrices, CSR counts, scan and fill.
 // rel_mask bit r: some instance of the batch uses relation r.  Returns
-// |E_c|; the CSR is in h->rowptr / h->adj, each member's offset within its
-// row in h->seg (slot-major, stride h->seg_m).
+// |E_c|; the CSR is in h->rowptr / h->adj, each member's CSR position in
+// h->seg_off (slot-major, stride h->seg_m).
 int64_t build_conflict_graph(picasso_ctx *h, const Batch &b, int64_t m, int64_t E, int64_t P, int32_t T_max,
                              int32_t rel_mask, const BucketInfo &bi, double *ms_relate, double *ms_csr,
                              bool *used_mfma = nullptr, bool csr_required = true, int64_t edge_bound = -1,
@@ -469,17 +469,20 @@ int64_t build_conflict_graph(picasso_ctx *h, const Batch &b, int64_t m, int64_t 
         launch_dup(da, st);
         launch_dup_slow(da, st);  // its bucket count is read on the device
     }
-    // edge counts per (vertex, slot), their offsets within each row, row
-    // pointers from a scan of the row lengths
-    buf<int32_t>(h, h->seg, (size_t)std::max<int64_t>((int64_t)T_max * m, 1));
+    // edge counts per (vertex, slot), row lengths, row pointers from their
+    // scan, and each segment's CSR position
+    const size_t nseg = (size_t)std::max<int64_t>((int64_t)T_max * m, 1);
+    buf<int32_t>(h, h->seg, nseg);
+    buf<int64_t>(h, h->seg_off, nseg);
     h->seg_m = m;
     int64_t *rowptr = buf<int64_t>(h, h->rowptr, (size_t)m + 1);
     CsrArgs ca = csr_args(h, b, P);
     launch_count(ca, st);
     int32_t *deg = buf<int32_t>(h, h->deg, (size_t)std::max<int64_t>(m, 1));
-    launch_row_offsets(ca.seg, m, b.loff, deg, st);
+    launch_row_lengths(ca.seg, m, b.loff, deg, st);
     void *tmp = h->arena.ensure(h->scan_tmp, scan_tmp_bytes(std::max<int64_t>(P, E) + 1));
     exclusive_scan_i32_to_i64(deg, rowptr, m, true, tmp, st);
+    launch_seg_offsets(ca.seg, m, b.loff, rowptr, static_cast<int64_t *>(h->seg_off.p), st);
     if (edge_bound >= 0 && !csr_required &&
         (h->mem_budget <= 0 || 2 * edge_bound * (int64_t)sizeof(int32_t) <= h->mem_budget)) {
         // CSR sized by the predicted bound: the fill is queued without waiting
@@ -1388,7 +1391,7 @@ void picasso_destroy(picasso_handle h)
     DevBuf *all[] = {&h->x,       &h->z,       &h->xz,        &h->ids,     &h->next_ids, &h->lists,   &h->prio,     &h->bcnt,
                      &h->bstart,  &h->bmem,     &h->bslot,   &h->pos_of,   &h->bent, &h->tmp_mem, &h->tmp_slot, &h->tiles,
                      &h->words,   &h->tile_off, &h->rb_off,  &h->R,        &h->D,       &h->nslow,    &h->slow,
-                     &h->seg,      &h->deg,      &h->rowptr, &h->adj,      &h->col,     &h->blk,      &h->fre,
+                     &h->seg,      &h->seg_off,  &h->deg,      &h->rowptr, &h->adj,      &h->col,     &h->blk,      &h->fre,
                      &h->nblk,    &h->st,       &h->rdy,     &h->jp_prog, &h->dflag, &h->wl,       &h->flags,   &h->pos,      &h->used,
                      &h->scan_tmp, &h->bx,      &h->bz,      &h->tile_bucket,
                      &h->scalars, &h->out_colors, &h->judge_out, &h->inst,    &h->vinst,    &h->loff,    &h->binst,    &h->inst_out, &h->tail_recs,

@@ -221,13 +221,13 @@ struct CsrArgs {
     const uint64_t *R, *D;
     const uint8_t *dflag;    // per bucket entry: its D row has a bit (rows without one read R alone)
     const int64_t *loff;     // list entry of (v, 0)
-    // Segment of member (v, s) in v's CSR row, slot-major: seg[s * seg_m + v]
-    // holds its edge count after the count pass, its offset within the row
-    // after launch_row_offsets (members of one colour have nearby slots, so
-    // a bucket's accesses fall in a few slot rows of seg_m entries each)
+    // Segment of member (v, s) in v's CSR row, slot-major with stride seg_m:
+    // seg[s * seg_m + v] its edge count (count pass), seg_off[s * seg_m + v]
+    // its CSR position (fill pass).  Members of one colour hold it at nearby
+    // slots, so a bucket's accesses fall in a few slot rows.
     int32_t *seg;
+    const int64_t *seg_off;
     int64_t seg_m;
-    const int64_t *rowptr;   // fill pass: row starts (m + 1)
     int32_t *adj;            // fill pass: CSR column indices
     const int32_t *skip;     // fill pass: if non-null and nonzero, write nothing
     int64_t v_lo, v_hi;      // fill pass: only the rows of vertices in [v_lo, v_hi) ...
@@ -235,9 +235,12 @@ struct CsrArgs {
 };
 void launch_count(const CsrArgs &a, hipStream_t st);
 void launch_fill(const CsrArgs &a, int64_t max_size, hipStream_t st);  // max_size: largest bucket
-// Each vertex's segment counts (seg, slot-major with stride m) become their
-// exclusive prefix within the row, in place; deg[v] = the row's length.
-void launch_row_offsets(int32_t *seg, int64_t m, const int64_t *loff, int32_t *deg, hipStream_t st);
+// From the segment counts (seg, slot-major with stride m): deg[v] = the
+// length of v's row; then, with the row pointers, seg_off = each segment's
+// CSR position (rowptr[v] plus the counts of v's earlier slots).
+void launch_row_lengths(const int32_t *seg, int64_t m, const int64_t *loff, int32_t *deg, hipStream_t st);
+void launch_seg_offsets(const int32_t *seg, int64_t m, const int64_t *loff, const int64_t *rowptr, int64_t *seg_off,
+                        hipStream_t st);
 // flag = (*total > cap): the CSR of *total entries does not fit cap entries.
 void launch_csr_guard(const int64_t *total, int64_t cap, int32_t *flag, hipStream_t st);
 

@@ -457,7 +457,7 @@ __global__ void __launch_bounds__(kWave * kFillWaves) fill_kernel(CsrArgs a, int
             for (int64_t p = threadIdx.x; p < S; p += blockDim.x) {
                 const uint32_t v = a.bmem[base + p];
                 mv[p] = v;
-                seg[p] = a.rowptr[v] + a.seg[(int64_t)a.bslot[base + p] * a.seg_m + v];
+                seg[p] = a.seg_off[(int64_t)a.bslot[base + p] * a.seg_m + v];
             }
             // D is read only for the rows that have a bit in it
             for (int64_t w = threadIdx.x; w < S * nw; w += blockDim.x) {
@@ -480,7 +480,7 @@ __global__ void __launch_bounds__(kWave * kFillWaves) fill_kernel(CsrArgs a, int
             for (int64_t p = wave; p < S; p += kFillWaves) {
                 const int64_t v = a.bmem[base + p];
                 if (v < a.v_lo || v >= a.v_hi) continue;  // another chunk's row
-                int64_t at = a.rowptr[v] + a.seg[(int64_t)a.bslot[base + p] * a.seg_m + v] - a.adj_base;
+                int64_t at = a.seg_off[(int64_t)a.bslot[base + p] * a.seg_m + v] - a.adj_base;
                 const bool dd = a.dflag[base + p];
                 for (int64_t w = 0; w < nw; ++w) {
                     const uint64_t bits = dd ? Rm[p * nw + w] & ~Dm[p * nw + w] : Rm[p * nw + w];
@@ -496,17 +496,26 @@ __global__ void __launch_bounds__(kWave * kFillWaves) fill_kernel(CsrArgs a, int
 
 // One thread per vertex; for each slot the threads of a wave touch
 // consecutive vertices of one slot row.
-__global__ void row_offsets_kernel(int32_t *seg, int64_t m, const int64_t *loff, int32_t *deg)
+__global__ void row_lengths_kernel(const int32_t *seg, int64_t m, const int64_t *loff, int32_t *deg)
 {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < m; v += (int64_t)gridDim.x * blockDim.x) {
         const int64_t T = loff[v + 1] - loff[v];
         int32_t run = 0;
-        for (int64_t s = 0; s < T; ++s) {
-            const int32_t c = seg[s * m + v];
-            seg[s * m + v] = run;
-            run += c;
-        }
+        for (int64_t s = 0; s < T; ++s) run += seg[s * m + v];
         deg[v] = run;
+    }
+}
+
+__global__ void seg_offsets_kernel(const int32_t *seg, int64_t m, const int64_t *loff, const int64_t *rowptr,
+                                   int64_t *seg_off)
+{
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < m; v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t T = loff[v + 1] - loff[v];
+        int64_t at = rowptr[v];
+        for (int64_t s = 0; s < T; ++s) {
+            seg_off[s * m + v] = at;
+            at += seg[s * m + v];
+        }
     }
 }
 
@@ -560,11 +569,18 @@ void launch_csr_guard(const int64_t *total, int64_t cap, int32_t *flag, hipStrea
     PCHECK_LAUNCH();
 }
 
-void launch_row_offsets(int32_t *seg, int64_t m, const int64_t *loff, int32_t *deg, hipStream_t st)
+void launch_row_lengths(const int32_t *seg, int64_t m, const int64_t *loff, int32_t *deg, hipStream_t st)
 {
     if (m <= 0) return;
-    const int64_t b = (m + 255) / 256;
-    row_offsets_kernel<<<grid_cap(b, 65535 * 16), 256, 0, st>>>(seg, m, loff, deg);
+    row_lengths_kernel<<<grid_cap((m + 255) / 256, 65535 * 16), 256, 0, st>>>(seg, m, loff, deg);
+    PCHECK_LAUNCH();
+}
+
+void launch_seg_offsets(const int32_t *seg, int64_t m, const int64_t *loff, const int64_t *rowptr, int64_t *seg_off,
+                        hipStream_t st)
+{
+    if (m <= 0) return;
+    seg_offsets_kernel<<<grid_cap((m + 255) / 256, 65535 * 16), 256, 0, st>>>(seg, m, loff, rowptr, seg_off);
     PCHECK_LAUNCH();
 }
 
