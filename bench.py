@@ -34,9 +34,9 @@ PAIR_TRAFFIC = {
     "path": "valu",
     "source": "paper_2401_06713_amd/csrc/relate.hip",
     "sha256": "a4eb31278c6673bdf4a234cbcec3ec625b313a2efa81133f8732b8622a2ac835",
-    "fetch_kib": 1337841.3,
-    "fetch_scale": 1048576.0 / 524315.5,
-    "write_kib": 2874358.8,
+    "fetch_kib": 1337859.8,
+    "fetch_scale": 1048576.0 / 524315.6,
+    "write_kib": 2874454.8,
     "write_scale": 1048576.0 / 1048576.0,
 }
 
@@ -44,10 +44,10 @@ FILL_TRAFFIC = {
     "workload": "C4 n=2000000 q=128 pI=0.8",
     "path": "valu",
     "source": "paper_2401_06713_amd/csrc/pairs.hip",
-    "sha256": "e368bd66a44453978708043f323b8bbc8670c14b22b4308deccda45f678bca4c",
-    "fetch_kib": 5705958.75,
-    "fetch_scale": 1048576.0 / 524315.5,
-    "write_kib": 29703857.2,
+    "sha256": "d0553654c5e9c530158633d308c49bdc762ae6b5a59446278cc46b674ce8251f",
+    "fetch_kib": 5705837.75,
+    "fetch_scale": 1048576.0 / 524315.6,
+    "write_kib": 29703929.0,
     "write_scale": 1048576.0 / 1048576.0,
 }
 

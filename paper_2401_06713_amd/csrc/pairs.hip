@@ -403,23 +403,48 @@ __global__ void __launch_bounds__(256) dup_slow_kernel(DupArgs a)
 }
 
 // Conflict-edge count of every member: popcount(R & ~D) of its row, stored
-// at the member's (vertex, slot) position.
-__global__ void __launch_bounds__(kWave) count_kernel(CsrArgs a)
+// at the member's (vertex, slot) segment.  Buckets of up to kCountMembers
+// members are read word by word across the lanes (consecutive lanes,
+// consecutive words of the bucket's block), each row's popcounts summed in
+// LDS; larger buckets take one thread per row.
+constexpr int kCountThreads = 256;
+constexpr int kCountMembers = 1024;
+
+__global__ void __launch_bounds__(kCountThreads) count_kernel(CsrArgs a)
 {
+    __shared__ int cnt[kCountMembers];
+    const int t = threadIdx.x;
     for (int64_t c = blockIdx.x; c < a.P; c += gridDim.x) {
         const int64_t base = a.bstart[c];
         const int64_t S = a.bstart[c + 1] - base;
         const int64_t nw = (S + 63) >> 6;
         const uint64_t *Rm = a.R + a.rb_off[c];
         const uint64_t *Dm = a.D + a.rb_off[c];
-        for (int64_t p = threadIdx.x; p < S; p += kWave) {
-            int cnt = 0;
-            if (a.dflag[base + p]) {
-                for (int64_t w = 0; w < nw; ++w) cnt += __popcll(Rm[p * nw + w] & ~Dm[p * nw + w]);
-            } else {
-                for (int64_t w = 0; w < nw; ++w) cnt += __popcll(Rm[p * nw + w]);
+        if (S <= kCountMembers) {
+            __syncthreads();
+            for (int p = t; p < (int)S; p += kCountThreads) cnt[p] = 0;
+            __syncthreads();
+            const int words = (int)(S * nw), nw32 = (int)nw;
+            for (int x = t; x < words; x += kCountThreads) {
+                const int p = x / nw32;
+                uint64_t r = Rm[x];
+                if (a.dflag[base + p]) r &= ~Dm[x];
+                const int k = __popcll(r);
+                if (k) atomicAdd(&cnt[p], k);
             }
-            a.seg[(int64_t)a.bslot[base + p] * a.seg_m + a.bmem[base + p]] = cnt;
+            __syncthreads();
+            for (int p = t; p < (int)S; p += kCountThreads)
+                a.seg[(int64_t)a.bslot[base + p] * a.seg_m + a.bmem[base + p]] = cnt[p];
+        } else {
+            for (int64_t p = t; p < S; p += kCountThreads) {
+                int k = 0;
+                if (a.dflag[base + p]) {
+                    for (int64_t w = 0; w < nw; ++w) k += __popcll(Rm[p * nw + w] & ~Dm[p * nw + w]);
+                } else {
+                    for (int64_t w = 0; w < nw; ++w) k += __popcll(Rm[p * nw + w]);
+                }
+                a.seg[(int64_t)a.bslot[base + p] * a.seg_m + a.bmem[base + p]] = k;
+            }
         }
     }
 }
@@ -545,7 +570,7 @@ void launch_dup_slow(const DupArgs &a, hipStream_t st)
 void launch_count(const CsrArgs &a, hipStream_t st)
 {
     if (a.P <= 0) return;
-    count_kernel<<<grid_cap(a.P, 1 << 20), kWave, 0, st>>>(a);
+    count_kernel<<<grid_cap(a.P, 1 << 20), kCountThreads, 0, st>>>(a);
     PCHECK_LAUNCH();
 }
 
