@@ -647,13 +647,16 @@ int32_t color_buckets(picasso_ctx *h, const Batch &b, int64_t m, int64_t E, int6
     RoundGraph graph;
     const int32_t max_batch = std::max<int32_t>(h->jp_batch, 1);
     int32_t rounds = 0;
-    // rounds with nothing to do exit at once, so a first batch of several
-    // rounds costs less than host checks between them
-    int cur = 0, batch = std::min<int32_t>(8, max_batch);
+    // Rounds with nothing to do exit at once (a few us), so a whole batch
+    // first costs less than host checks between smaller ones.  The first
+    // batch is launched round by round: most iterations end within it, and
+    // capturing the graph, done only for a second batch, costs more than
+    // the launches it saves.
+    int cur = 0, batch = max_batch;
     unsigned long long at_restart = 0;
     bool fresh = true;  // the lists hold every bucket
     while (true) {
-        if (h->use_graph && batch == max_batch && max_batch > 1) {
+        if (h->use_graph && batch == max_batch && max_batch > 1 && rounds > 0) {
             if (!graph.exec[cur]) capture_rounds(h, j, graph, batch, cur);
             PCHECK_HIP(hipGraphLaunch(graph.exec[cur], st));
             if (batch & 1) cur ^= 1;
