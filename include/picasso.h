@@ -72,7 +72,10 @@ enum {
                                    the colouring calls count the edges and
                                    skip writing the CSR (they colour from the
                                    per-bucket relation matrices)                */
-    PICASSO_OPT_PAIR_PATH = 2,  /* 0 auto, 1 popcount VALU, 2 int8 MFMA          */
+    PICASSO_OPT_PAIR_PATH = 2,  /* 0 auto (= 1: the popcount kernel measured
+                                   faster on every workload), 1 popcount VALU,
+                                   2 int8 MFMA (EINVAL where q and the relation
+                                   do not fit its LDS rows)                   */
     PICASSO_OPT_FIXED_T = 3,    /* >0: list size T fixed (clamped to P) instead of
                                    ceil(alpha ln m); 0 restores the formula      */
     PICASSO_OPT_STREAM = 4,     /* hipStream_t (cast to int64) to run on; 0 = the

@@ -418,8 +418,9 @@ int64_t build_conflict_graph(picasso_ctx *h, const Batch &b, int64_t m, int64_t 
     tm.mark();
     for (int32_t rel = 0; rel < 3; ++rel) {
         if (!(rel_mask >> rel & 1)) continue;
-        const bool mfma = h->pair_path == PICASSO_PATH_MFMA ||
-                          (h->pair_path == PICASSO_PATH_AUTO && mfma_supported(h->q, rel));
+        // auto takes the popcount kernel, the faster one on every measured
+        // workload; the MFMA kernel runs on request (or when the tuner picks it)
+        const bool mfma = h->pair_path == PICASSO_PATH_MFMA;
         if (mfma && !mfma_supported(h->q, rel))
             throw Error(PICASSO_EINVAL, "the MFMA pair path does not support this q and relation");
         ra.relation = rel;

@@ -5,7 +5,8 @@ The knobs, all plain options of a handle:
 * pair tile shape: buckets of at most `cap` members take the int8 MFMA
   kernel (32 x 32 output tiles over a bucket staged whole in LDS), larger
   ones the popcount kernel (64-row tiles, one wave per row tile);
-  `cap = 0` sends every bucket to the popcount kernel;
+  `cap = 0` sends every bucket to the popcount kernel (the default) and
+  `cap = -1` every bucket the MFMA kernel's LDS rows can hold;
 * colouring rounds launched between two host progress checks;
 * whether a full batch of rounds is replayed from a captured HIP graph.
 
@@ -29,7 +30,7 @@ import numpy as np
 import paper_2401_06713_amd as pk
 
 CACHE_ENV = "PICASSO_TUNE_CACHE"
-DEFAULT = {"cap": -1, "jp_batch": 32, "graph": 1}
+DEFAULT = {"cap": 0, "jp_batch": 32, "graph": 1}
 CAPS = (0, 32, 64, 128, 256, -1)
 JP_BATCHES = (4, 8, 16, 32, 64)
 GRAPHS = (0, 1)
@@ -48,7 +49,7 @@ def signature(h: pk.Picasso, relations) -> str:
 def apply(h: pk.Picasso, cfg: dict):
     """Set a tuned configuration on a handle."""
     cap = int(cfg["cap"])
-    h.set_option(pk.OPT_PAIR_PATH, pk.PATH_VALU if cap == 0 else pk.PATH_MFMA if cap > 0 else pk.PATH_AUTO)
+    h.set_option(pk.OPT_PAIR_PATH, pk.PATH_VALU if cap == 0 else pk.PATH_MFMA)
     h.set_option(pk.OPT_MFMA_CAP, cap if cap > 0 else -1)
     h.set_option(pk.OPT_JP_BATCH, int(cfg["jp_batch"]))
     h.set_option(pk.OPT_GRAPH, int(cfg["graph"]))

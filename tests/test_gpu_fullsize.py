@@ -195,9 +195,10 @@ def test_c4_full_size_properties_and_samples(orc):
         nc, col = h.color(0, cfg.frac, cfg.alpha, rel)
         st = h.stats()
         say("C4 valu", nc, "colours", st["n_iters"], "iterations", round(st["ms_total"], 1), "ms")
-        h.set_option(pk.OPT_PAIR_PATH, pk.PATH_AUTO)
+        h.set_option(pk.OPT_PAIR_PATH, pk.PATH_MFMA)
         nc2, col2 = h.color(0, cfg.frac, cfg.alpha, rel)
         assert nc2 == nc and np.array_equal(col2, col)
+        assert h.stats()["iters"][0]["pair_path"] == pk.PATH_MFMA
         P, T = orc.params(n, cfg.frac, cfg.alpha)
         ne, rowptr = h.conflict_rowptr(0, 1, ids, P, T, rel)
     # whole-run properties
